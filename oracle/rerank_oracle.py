@@ -1,0 +1,235 @@
+"""FP64 CPU oracle for GNN-based re-ranking (Zhang et al., "Understanding Image
+Retrieval Re-Ranking: A Graph Neural Network Perspective", Section 3.3,
+Equations 7-14 and Algorithm 1).
+
+TEST INFRASTRUCTURE. Only the test-suite, the package smoke check and the
+CPU-baseline leg of the benchmark may import or run this module. The product
+path never calls it and shares no code with it: the GPU library has its own
+kernels, the oracle is plain NumPy/SciPy in float64.
+
+The method reaches a defined result (no approximation), so each function is
+the definition written out in float64, taken from the exact input values:
+
+  Eq. 7      S_ij = cos(x_i, x_j) over the union of queries and gallery.
+  Eq. 8      A_ij = 1 iff j is one of the k1 most similar rows of row i.
+  Eq. 9-10   A* = (A + A^T) / 2, entries in {0, 0.5, 1}.
+  Eq. 11     h_i^(0) = row i of A*  (vertex feature).
+  Eq. 12     edges e_ij = S_ij for j among the k2 most similar rows of i.
+  Eq. 14     h_i^(l+1) = h_i^(l) + sum_{j in N(i,k2)} e_ij^alpha h_j^(l)
+             (aggregator "sum", alpha = 2 in the paper's experiments),
+             followed by an L2 normalisation of every row (Section 3.3,
+             paragraph after Eq. 14).
+  Final      ranking by cosine similarity of the refined features; the
+             oracle returns the query x gallery distance 1 - cos.
+
+Readings taken where the paper is silent (each is also the GPU library's):
+  R1  cos is a true cosine: rows are divided by their norm.
+  R2  row i itself is always member 0 of N(i, k) with similarity exactly 1,
+      so every row has exactly k1 neighbours including itself.
+  R3  the order inside N(i, k) is similarity descending, ties to the lower
+      column index, -0.0 equal to +0.0.
+  R4  candidates are all N rows (queries and gallery alike).
+  R5  N(i, k2) is the first k2 members of N(i, k1) (k2 <= k1), self
+      included, so the self coefficient in Eq. 14 is 1 (residual) + 1.
+  R6  h^(0) is the raw A* row; normalisation happens after each layer.
+  R7  the edge weights use the original S and stay fixed for all layers.
+  R8  alpha is a non-negative integer; e^alpha is the plain power.
+  R9  output D_qg = 1 - cos(h_q, h_g) for q < Q <= g < N.
+  R10 node mode "raw" uses h^(0)_i = x_i (the Table 1 ablation column with
+      original features); with zero layers it gives the initial ranking.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = [
+    "unit_rows", "similarity_rows", "knn_of_row", "knn_lists", "adjacency",
+    "symmetric_adjacency", "edge_weights", "initial_features", "propagate",
+    "row_norms", "distances", "rerank", "Graph", "OracleResult",
+]
+
+
+# ----------------------------------------------------------------------- Eq. 7
+def unit_rows(x: np.ndarray) -> np.ndarray:
+    """Rows of ``x`` in float64 divided by their Euclidean norm (reading R1)."""
+    x = np.asarray(x, dtype=np.float64)
+    return x / np.sqrt(np.einsum("ij,ij->i", x, x))[:, None]
+
+
+def similarity_rows(xhat: np.ndarray, rows: Sequence[int]) -> np.ndarray:
+    """Rows ``rows`` of the cosine-similarity matrix S (Eq. 7); ``xhat`` are
+    unit rows. A float64 matrix product serves as the dot products."""
+    return xhat[np.asarray(rows)] @ xhat.T
+
+
+# ----------------------------------------------------------------------- Eq. 8
+def knn_of_row(s_row: np.ndarray, i: int, k: int, k_gap: Sequence[int] = ()):
+    """N(i, k) of Eq. 8 under readings R2-R4.
+
+    Returns ``(idx, val, gaps)``: ``idx[0] = i`` with ``val[0] = 1``, then the
+    k-1 other columns ordered by (S desc, column asc). ``gaps[m]`` for each
+    ``m`` in ``k_gap`` is T_(m-1) - T_(m), where T_1 >= T_2 >= ... are the
+    similarities of the other columns in that order: the margin by which the
+    m-th member of N(i, m) beats the first row left out. It is +inf when
+    m == 1 (self alone) or when no row is left out."""
+    n = s_row.shape[0]
+    s = np.asarray(s_row, dtype=np.float64) + 0.0  # -0.0 -> +0.0
+    s = s.copy()
+    s[i] = -np.inf
+    m_take = min(max(k, max(k_gap, default=1)), n - 1)  # other rows to order
+    if m_take > 0:
+        t = -np.partition(-s, m_take - 1)[m_take - 1]  # m_take-th largest value
+        cand = np.flatnonzero(s >= t)  # every row tied with it is a candidate
+        order = cand[np.lexsort((cand, -s[cand]))][:m_take]
+    else:
+        order = np.zeros(0, dtype=np.int64)
+    idx = np.concatenate([[i], order[: k - 1]]).astype(np.int64)
+    val = np.concatenate([[1.0], s[order[: k - 1]]])
+    gaps = {}
+    tv = s[order]
+    for m in k_gap:
+        if m <= 1 or m > n - 1:
+            gaps[m] = math.inf
+        else:
+            gaps[m] = float(tv[m - 2] - tv[m - 1])
+    return idx, val, gaps
+
+
+@dataclass
+class Graph:
+    """Neighbour lists of every requested row, in rank order."""
+
+    idx: np.ndarray  # (R, k1) int64
+    val: np.ndarray  # (R, k1) float64 similarities, val[:, 0] == 1
+    gap1: np.ndarray  # (R,) margin at the k1 boundary
+    gap2: np.ndarray  # (R,) margin at the k2 boundary
+
+
+def knn_lists(x: np.ndarray, k1: int, k2: Optional[int] = None,
+              rows: Optional[Iterable[int]] = None, block: int = 1024) -> Graph:
+    """N(i, k1) for the given rows (all rows by default), from float64 S rows
+    computed ``block`` rows at a time."""
+    xhat = unit_rows(x)
+    n = xhat.shape[0]
+    rows = np.arange(n) if rows is None else np.asarray(list(rows), dtype=np.int64)
+    k2 = k1 if k2 is None else k2
+    idx = np.empty((len(rows), k1), dtype=np.int64)
+    val = np.empty((len(rows), k1), dtype=np.float64)
+    g1 = np.empty(len(rows))
+    g2 = np.empty(len(rows))
+    for b0 in range(0, len(rows), block):
+        rb = rows[b0:b0 + block]
+        s_blk = similarity_rows(xhat, rb)
+        for r, i in enumerate(rb):
+            ii, vv, gg = knn_of_row(s_blk[r], int(i), k1, (k1, k2))
+            idx[b0 + r], val[b0 + r] = ii, vv
+            g1[b0 + r], g2[b0 + r] = gg[k1], gg[k2]
+    return Graph(idx, val, g1, g2)
+
+
+# --------------------------------------------------------------- Eq. 8 - 11
+def adjacency(idx: np.ndarray, n: int) -> sp.csr_matrix:
+    """A of Eq. 8 from complete neighbour lists (one row per vertex)."""
+    rows = np.repeat(np.arange(n), idx.shape[1])
+    return sp.csr_matrix((np.ones(idx.size), (rows, idx.ravel())), shape=(n, n))
+
+
+def symmetric_adjacency(idx: np.ndarray, n: int) -> sp.csr_matrix:
+    """A* = (A + A^T) / 2 (Eq. 9); its entries are those of Eq. 10."""
+    a = adjacency(idx, n)
+    return ((a + a.T) * 0.5).tocsr()
+
+
+# ------------------------------------------------------------- Eq. 12 and 14
+def edge_weights(idx: np.ndarray, val: np.ndarray, k2: int, alpha: int) -> sp.csr_matrix:
+    """W_ij = e_ij^alpha for j in N(i, k2) (Eq. 12 and the weight function of
+    Eq. 14), with N(i, k2) the first k2 members of N(i, k1) (reading R5)."""
+    n = idx.shape[0]
+    nb = idx[:, :k2]
+    e = val[:, :k2].astype(np.float64)
+    w = e ** int(alpha)
+    rows = np.repeat(np.arange(n), k2)
+    return sp.csr_matrix((w.ravel(), (rows, nb.ravel())), shape=(n, n))
+
+
+def initial_features(x: np.ndarray, idx: np.ndarray, node: str = "adj"):
+    """h^(0): rows of A* (Eq. 11, node mode "adj") or the raw features x_i
+    (node mode "raw", reading R10). Not normalised (reading R6)."""
+    n = x.shape[0]
+    if node == "adj":
+        return symmetric_adjacency(idx, n)
+    if node == "raw":
+        return np.asarray(x, dtype=np.float64).copy()
+    raise ValueError(node)
+
+
+def row_norms(h) -> np.ndarray:
+    if sp.issparse(h):
+        return np.sqrt(np.asarray(h.multiply(h).sum(axis=1)).ravel())
+    return np.sqrt(np.einsum("ij,ij->i", h, h))
+
+
+def _scale_rows(h, f):
+    if sp.issparse(h):
+        return (sp.diags(f) @ h).tocsr()
+    return h * f[:, None]
+
+
+def propagate(h0, w: sp.csr_matrix, layers: int, keep_all: bool = False):
+    """Eq. 14 with the sum aggregator, ``layers`` times, each followed by the
+    row L2 normalisation. ``keep_all`` also returns every intermediate h."""
+    h = h0
+    hist = [h0]
+    for _ in range(layers):
+        u = h + w @ h
+        if sp.issparse(u):
+            u = u.tocsr()
+        h = _scale_rows(u, 1.0 / row_norms(u))
+        hist.append(h)
+    return (h, hist) if keep_all else h
+
+
+def distances(h, n_query: int, q_rows: Optional[Sequence[int]] = None,
+              g_rows: Optional[Sequence[int]] = None) -> np.ndarray:
+    """D_qg = 1 - cos(h_q, h_g), queries ``q_rows`` (default all q < Q) by
+    gallery rows ``g_rows`` (default all Q <= g < N), as a dense array."""
+    n = h.shape[0]
+    q = np.arange(n_query) if q_rows is None else np.asarray(q_rows)
+    g = np.arange(n_query, n) if g_rows is None else np.asarray(g_rows)
+    nrm = row_norms(h)
+    hq, hg = h[q], h[g]
+    dot = hq @ hg.T
+    if sp.issparse(dot):
+        dot = dot.toarray()
+    dot = np.asarray(dot, dtype=np.float64)
+    return 1.0 - dot / (nrm[q][:, None] * nrm[g][None, :])
+
+
+# ------------------------------------------------------------- Algorithm 1
+@dataclass
+class OracleResult:
+    graph: Graph
+    h: object  # final features (scipy CSR for "adj", ndarray for "raw")
+    dist: np.ndarray  # (len(q_rows), len(g_rows))
+
+
+def rerank(x: np.ndarray, n_query: int, k1: int, k2: int, layers: int,
+           alpha: int = 2, node: str = "adj", q_rows=None, g_rows=None) -> OracleResult:
+    """Algorithm 1 end to end: similarity, k1 lists, A*, h^(0) and k2 edges,
+    ``layers`` propagation steps, query x gallery distances."""
+    x = np.asarray(x)
+    n = x.shape[0]
+    if not (1 <= n_query <= n - 1):
+        raise ValueError("need 1 <= n_query <= N-1")
+    if not (1 <= k2 <= k1 <= n):
+        raise ValueError("need 1 <= k2 <= k1 <= N")
+    g = knn_lists(x, k1, k2)
+    h0 = initial_features(x, g.idx, node)
+    w = edge_weights(g.idx, g.val, k2, alpha)
+    h = propagate(h0, w, layers)
+    return OracleResult(g, h, distances(h, n_query, q_rows, g_rows))

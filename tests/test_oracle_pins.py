@@ -1,0 +1,284 @@
+"""Pins of the FP64 oracle to facts that do not come from the oracle itself:
+a hand-worked example, brute-force counting on tiny inputs, closed forms,
+invariants stated by the equations, and library routines for special cases.
+CPU only."""
+import json
+import math
+from fractions import Fraction
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.spatial.distance import cdist
+
+from oracle import rerank_oracle as orc
+from paper_2012_07620_amd.synth import random_features
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_5pt.json")
+
+
+def _hand():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+# ------------------------------------------------------------ hand example
+def test_hand_example_similarity_and_lists():
+    g = _hand()
+    x = np.array(g["x"], dtype=np.float32)
+    s = orc.similarity_rows(orc.unit_rows(x), range(5))
+    for a, row in g["S_offdiag_by_hand"].items():
+        for b, v in row.items():
+            assert s[int(a), int(b)] == pytest.approx(v, abs=1e-15)
+            assert s[int(b), int(a)] == pytest.approx(v, abs=1e-15)
+    gr = orc.knn_lists(x, g["k1"], g["k2"])
+    assert gr.idx.tolist() == g["lists"]
+
+
+def test_hand_example_astar_and_layer1():
+    g = _hand()
+    x = np.array(g["x"], dtype=np.float32)
+    gr = orc.knn_lists(x, g["k1"], g["k2"])
+    a = orc.symmetric_adjacency(gr.idx, 5).toarray()
+    np.testing.assert_array_equal(a, np.array(g["A_star"]))
+    assert a.sum() == g["A_star_sum"]
+    w = orc.edge_weights(gr.idx, gr.val, g["k2"], g["alpha"])
+    h1 = orc.propagate(sp.csr_matrix(a), w, 1).toarray()
+    u = np.array(g["u_layer1"])
+    np.testing.assert_allclose(h1, u / np.linalg.norm(u, axis=1, keepdims=True), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("layers,key", [(0, "D_layers0"), (1, "D_layers1")])
+def test_hand_example_distances(layers, key):
+    g = _hand()
+    x = np.array(g["x"], dtype=np.float32)
+    res = orc.rerank(x, g["n_query"], g["k1"], g["k2"], layers, alpha=g["alpha"])
+    np.testing.assert_allclose(res.dist, np.array(g[key]), rtol=0, atol=1e-13)
+
+
+# --------------------------------------------------- brute-force kNN (Eq. 8)
+def _exact_keys(x, i):
+    """Exact order keys of cos(x_i, x_j) for integer-valued rows: the sign of
+    the dot product times dot^2 / |x_j|^2 is monotone in the cosine (the factor
+    |x_i| is common to the row), and rational, so ties are decided exactly."""
+    xi = [int(v) for v in x[i]]
+    keys = []
+    for row in x:
+        xj = [int(v) for v in row]
+        dot = sum(a * b for a, b in zip(xi, xj))
+        nj = sum(b * b for b in xj)
+        keys.append(Fraction((1 if dot > 0 else -1 if dot < 0 else 0) * dot * dot, nj))
+    return keys
+
+
+def _brute_lists(x, k, exact):
+    """N(i,k) by counting: column j != i has rank = number of other columns
+    that beat it under (S desc, index asc); members are self plus ranks < k-1.
+    ``exact`` uses rational keys (integer inputs), else float64 cosines."""
+    xx = np.asarray(x, dtype=np.float64)
+    nrm = np.sqrt((xx * xx).sum(1))
+    n = len(xx)
+    out = []
+    for i in range(n):
+        if exact:
+            s = _exact_keys(x, i)
+        else:
+            s = [float(np.dot(xx[i], xx[j]) / (nrm[i] * nrm[j])) + 0.0 for j in range(n)]
+        members = [None] * (k - 1)
+        for j in range(n):
+            if j == i:
+                continue
+            rank = sum(1 for m in range(n) if m not in (i, j) and (s[m] > s[j] or (s[m] == s[j] and m < j)))
+            if rank < k - 1:
+                members[rank] = j
+        out.append([i] + members)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_knn_matches_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(3, 28))
+    d = int(rng.integers(1, 6))
+    x = random_features(n, d, seed=100 + seed, dup_frac=0.3)
+    exact = bool(seed % 2)
+    if exact:  # integer features make many exact ties and exact zeros
+        x = np.round(x * 2).astype(np.float32)
+        x[np.all(x == 0, axis=1)] = 1.0
+    k = int(rng.integers(1, n + 1))
+    got = orc.knn_lists(x, k).idx.tolist()
+    ref = _brute_lists(x, k, exact)
+    for i in range(n):
+        if got[i] == ref[i]:
+            continue
+        # float64 may only break a tie that is exact in real arithmetic
+        # between two different vectors; duplicates must keep index order
+        keys = _exact_keys(x, i)
+        for a, b in zip(got[i], ref[i]):
+            if a != b:
+                assert exact and keys[a] == keys[b] and not np.array_equal(x[a], x[b]), (i, got[i], ref[i])
+
+
+def test_gaps_match_sorted_values():
+    x = random_features(30, 4, seed=7)
+    xx = x.astype(np.float64)
+    xx /= np.linalg.norm(xx, axis=1, keepdims=True)
+    s = xx @ xx.T
+    gr = orc.knn_lists(x, 6, 3)
+    for i in range(30):
+        t = np.sort(np.delete(s[i], i))[::-1]
+        assert gr.gap1[i] == pytest.approx(t[4] - t[5], abs=1e-15)
+        assert gr.gap2[i] == pytest.approx(t[1] - t[2], abs=1e-15)
+
+
+def test_signed_zero_similarities_tie():
+    # rows 1 and 2 are orthogonal to row 0 with +0.0 and -0.0 dot products
+    x = np.array([[1.0, 0.0], [0.0, 1.0], [-0.0, -1.0], [1.0, 1.0]], dtype=np.float32)
+    gr = orc.knn_lists(x, 3)
+    assert gr.idx[0].tolist() == [0, 3, 1]  # 1 beats 2 by index: +0 == -0
+
+
+# ------------------------------------------------------- A* (Eq. 9 - 10)
+@pytest.mark.parametrize("seed,n,k1", [(0, 40, 5), (1, 60, 12), (2, 25, 25), (3, 33, 1)])
+def test_astar_invariants(seed, n, k1):
+    x = random_features(n, 8, seed=seed, n_ids=4)
+    gr = orc.knn_lists(x, k1)
+    a = orc.symmetric_adjacency(gr.idx, n).toarray()
+    assert np.array_equal(a, a.T)
+    assert set(np.unique(a)) <= {0.0, 0.5, 1.0}
+    assert np.all(np.diag(a) == 1.0)
+    assert a.sum() == n * k1
+    assert np.all((a > 0).sum(1) >= k1)
+    lists = [set(r) for r in gr.idx.tolist()]
+    for i in range(n):
+        for j in range(n):
+            mutual = j in lists[i] and i in lists[j]
+            either = j in lists[i] or i in lists[j]
+            assert a[i, j] == (1.0 if mutual else 0.5 if either else 0.0)
+
+
+# ------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("layers", [0, 1, 3])
+def test_k1_one_gives_identity_graph(layers):
+    # k1 = 1: A* = I and N(i,1) = {i}; every h_i stays e_i, so all distinct
+    # rows are orthogonal: D = 1 everywhere.
+    x = random_features(20, 5, seed=3)
+    res = orc.rerank(x, 6, 1, 1, layers)
+    np.testing.assert_allclose(res.dist, 1.0, atol=1e-15)
+
+
+@pytest.mark.parametrize("layers", [0, 1, 2])
+def test_k1_n_gives_identical_rows(layers):
+    # k1 = N: A* is all ones and every h_i is the same vector: D = 0.
+    x = random_features(15, 3, seed=4)
+    res = orc.rerank(x, 5, 15, 4, layers)
+    np.testing.assert_allclose(res.dist, 0.0, atol=1e-14)
+
+
+@pytest.mark.parametrize("layers,alpha,k2", [(0, 2, 1), (1, 2, 3), (2, 0, 2), (3, 2, 4)])
+def test_orthogonal_duplicate_clusters(layers, alpha, k2):
+    # c clusters of m exact duplicates on orthogonal axes, k1 = m: each row's
+    # list is its own cluster, A* is block diagonal all-ones, and propagation
+    # keeps h_i a multiple of the cluster indicator: D = 0 inside, 1 across.
+    c, m = 4, 5
+    x = np.zeros((c * m, c), dtype=np.float32)
+    lab = np.repeat(np.arange(c), m)
+    perm = np.random.default_rng(1).permutation(c * m)
+    x[np.arange(c * m), lab[perm]] = 3.0
+    lab = lab[perm]
+    q = 7
+    res = orc.rerank(x, q, m, k2, layers, alpha=alpha)
+    expect = (lab[:q, None] != lab[None, q:]).astype(np.float64)
+    np.testing.assert_allclose(res.dist, expect, atol=1e-14)
+
+
+def test_raw_mode_zero_layers_is_initial_cosine_ranking():
+    x = random_features(50, 7, seed=5, n_ids=5)
+    res = orc.rerank(x, 12, 6, 3, 0, node="raw")
+    ref = cdist(x[:12].astype(np.float64), x[12:].astype(np.float64), metric="cosine")
+    np.testing.assert_allclose(res.dist, ref, atol=1e-13)
+
+
+def test_similarity_is_library_cosine():
+    x = random_features(40, 9, seed=6)
+    s = orc.similarity_rows(orc.unit_rows(x), range(40))
+    ref = 1.0 - cdist(x.astype(np.float64), x.astype(np.float64), metric="cosine")
+    np.testing.assert_allclose(s, ref, atol=1e-14)
+
+
+# --------------------------------------------------------------- invariants
+def test_unit_rows_nonnegative_and_support_after_each_layer():
+    n, k1, k2 = 80, 8, 4
+    x = random_features(n, 6, seed=8, n_ids=6)
+    gr = orc.knn_lists(x, k1, k2)
+    h0 = orc.initial_features(x, gr.idx)
+    w = orc.edge_weights(gr.idx, gr.val, k2, 2)
+    _, hist = orc.propagate(h0, w, 4, keep_all=True)
+    supp = (h0.toarray() != 0)
+    reach = (w.toarray() != 0) | np.eye(n, dtype=bool)
+    for layer, h in enumerate(hist[1:], start=1):
+        hd = h.toarray()
+        np.testing.assert_allclose(np.linalg.norm(hd, axis=1), 1.0, atol=1e-14)
+        assert hd.min() >= 0.0
+        supp = (reach.astype(int) @ supp.astype(int)) > 0
+        assert np.all((hd != 0) <= supp), f"support grew beyond {layer} hops"
+
+
+def test_over_smoothing_many_layers():
+    # with every row in N(i,k2) the update adds the same neighbourhood sum to
+    # all rows, so many layers drive every pair of features together
+    # (Section 4.2: the feature moves towards the neighbourhood mean).
+    x = random_features(12, 5, seed=9)
+    d0 = orc.rerank(x, 4, 12, 12, 0, node="raw").dist
+    d64 = orc.rerank(x, 4, 12, 12, 64, node="raw").dist
+    assert d0.max() > 0.2
+    assert d64.max() < 1e-12
+
+
+def test_weights_are_similarity_powers():
+    x = random_features(30, 4, seed=10)
+    gr = orc.knn_lists(x, 6, 3)
+    xx = orc.unit_rows(x)
+    for alpha in (0, 1, 2, 3):
+        w = orc.edge_weights(gr.idx, gr.val, 3, alpha).toarray()
+        for i in range(30):
+            for j in gr.idx[i, :3]:
+                s = 1.0 if j == i else float(xx[i] @ xx[j])
+                assert w[i, j] == pytest.approx(s ** alpha, abs=1e-14)
+            assert (w[i] != 0).sum() <= 3
+
+
+# ------------------------------------------------ planted mistakes are caught
+def _hand_check(res_fn):
+    g = _hand()
+    x = np.array(g["x"], dtype=np.float32)
+    d = res_fn(x, g)
+    return np.allclose(d, np.array(g["D_layers1"]), atol=1e-9)
+
+
+def test_planted_mistakes_fail_the_hand_pin(monkeypatch):
+    def run(x, g):
+        return orc.rerank(x, g["n_query"], g["k1"], g["k2"], 1, alpha=g["alpha"]).dist
+
+    assert _hand_check(run)
+    orig_w, orig_prop, orig_adj = orc.edge_weights, orc.propagate, orc.symmetric_adjacency
+    mutants = {
+        "alpha_dropped": ("edge_weights", lambda idx, val, k2, a: orig_w(idx, val, k2, 1)),
+        "no_residual": ("propagate", lambda h0, w, L, keep_all=False: _prop_no_residual(h0, w, L)),
+        "A_not_symmetrised": ("symmetric_adjacency", lambda idx, n: orc.adjacency(idx, n)),
+        "transposed_weights": ("edge_weights", lambda idx, val, k2, a: orig_w(idx, val, k2, a).T.tocsr()),
+    }
+    for name, (attr, fn) in mutants.items():
+        monkeypatch.setattr(orc, attr, fn)
+        assert not _hand_check(run), f"planted mistake {name} not caught"
+        monkeypatch.setattr(orc, attr, {"edge_weights": orig_w, "propagate": orig_prop,
+                                        "symmetric_adjacency": orig_adj}[attr])
+
+
+def _prop_no_residual(h0, w, layers):
+    h = h0
+    for _ in range(layers):
+        u = (w @ h).tocsr()
+        h = (sp.diags(1.0 / orc.row_norms(u)) @ u).tocsr()
+    return h
