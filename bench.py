@@ -1,0 +1,194 @@
+"""Benchmark of the GNN re-ranking hot path on one MI355X.
+
+One step = one whole re-ranking request (similarity product, top-k lists,
+FP32 re-score, A*, propagation layers, final query x gallery product) on a
+resident synthetic problem. Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mid|tiny|large]
+
+``value`` is N^2-elements per second of the FP32 path (N^2 / request time);
+``ms_per_step`` the FP32 request time. The same line carries the BF16 / FP8
+similarity variants on the same arrays, per-stage device times measured with
+HIP events on the launch stream, the roofline fraction of the dominant
+kernel, and the FP64 oracle timed on the host cores on the same problem.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "re-rank ms/request + N²-elem/s (FP32 vs BF16), p50/p99 at fixed QPS"
+PEAK = {"fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2500.0, "fp8_mfma_tflops": 5000.0, "hbm_gbs": 8000.0}
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def stage_work(spec, prec: str):
+    """Algorithmic work of one request per stage: (unit, amount)."""
+    n, q, g, d = spec.n, spec.n_query, spec.n_gallery, spec.dim
+    k1, k2, L = spec.k1, spec.k2, spec.layers
+    kc = min(k1 + (8 if prec == "f32" else 16), n, 256)
+    return {
+        "similarity": ("flop", 2.0 * n * n * d),
+        "topk": ("byte", 4.0 * n * n),
+        "rescore": ("flop", 2.0 * n * kc * d),
+        "adjacency": ("byte", 4.0 * n * n),
+        "propagate": ("byte", L * (k2 + 2) * 4.0 * n * n),
+        "final": ("flop", 2.0 * q * g * n),
+    }
+
+
+def roofline_entry(stage, unit, amount, ms, prec):
+    if ms <= 0:
+        return None
+    if unit == "flop":
+        ach = amount / (ms * 1e-3) / 1e12
+        peak = PEAK["fp32_mfma_tflops"]
+        if stage == "similarity" and prec == "bf16":
+            peak = PEAK["bf16_mfma_tflops"]
+        if stage == "similarity" and prec == "fp8":
+            peak = PEAK["fp8_mfma_tflops"]
+        if stage == "rescore":
+            return {"bound": "alu", "achieved": ach, "unit": "TFLOP/s"}
+        return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak}
+    ach = amount / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": ach / PEAK["hbm_gbs"]}
+
+
+def time_path(binding, torch, ctx, x, spec, prec, steps, warmup, out):
+    kw = dict(sim_prec=prec, ctx=ctx, out=out)
+    for _ in range(warmup):
+        binding.run(x, spec.n_query, spec.k1, spec.k2, spec.layers, **kw)
+    torch.cuda.synchronize()
+    ctx.stage_times()  # restart the per-stage averages
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        binding.run(x, spec.n_query, spec.k1, spec.k2, spec.layers, **kw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return ms, ctx.stage_times()
+
+
+def cpu_baseline(x32, spec):
+    """The FP64 oracle (as it stands) on the same problem, on this host."""
+    from oracle import rerank_oracle as orc
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    ref = orc.rerank(x32, spec.n_query, spec.k1, spec.k2, spec.layers)
+    t = time.perf_counter() - t0
+    return ref, {"value": spec.n * spec.n / t, "unit": "N^2-elem/s", "ms_per_request": t * 1e3,
+                 "cores": int(threads), "kind": "oracle",
+                 "sample": f"the whole {spec.name} request (float64 NumPy/SciPy oracle, one pass)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lowp", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2012_07620_amd import binding, synth
+
+    spec = {"tiny": synth.TINY, "mid": synth.MID, "large": synth.LARGE}[args.workload]
+    log(f"workload {spec.name}: generating")
+    prob = synth.make_problem(spec)
+    dev = torch.device("cuda:0")
+    if spec.dtype == "bf16":
+        x = torch.from_numpy(prob.x_bf16.view(np.int16)).to(dev).view(torch.bfloat16)
+    else:
+        x = torch.from_numpy(prob.x32).to(dev)
+    ctx = binding.Context(0, stage_timing=True)
+    out = torch.empty((spec.n_query, spec.n_gallery), dtype=torch.float32, device=dev)
+
+    log("timing fp32 path")
+    ms, stages = time_path(binding, torch, ctx, x, spec, "f32", args.steps, args.warmup, out)
+    d_f32 = out.cpu().numpy()
+    work = stage_work(spec, "f32")
+    roof = {k: roofline_entry(k, *work[k], stages[k], "f32") for k in work}
+    dominant = max(work, key=lambda k: stages[k])
+    dom = dict(roof[dominant])
+    dom.update({"kernel": dominant, "traffic": None, "ms_per_launch": stages[dominant]})
+
+    lowp = {}
+    if not args.no_lowp:
+        for prec in ("bf16", "fp8"):
+            log(f"timing {prec} similarity path")
+            out_l = torch.empty_like(out)
+            ms_l, st_l = time_path(binding, torch, ctx, x, spec, prec, args.steps, args.warmup, out_l)
+            wl = stage_work(spec, prec)
+            lowp[prec] = {"ms_per_request": ms_l, "value": spec.n ** 2 / (ms_l * 1e-3),
+                          "speedup_vs_f32": ms / ms_l, "stages_ms": st_l,
+                          "similarity_roofline": roofline_entry("similarity", *wl["similarity"], st_l["similarity"],
+                                                                prec),
+                          "dist": out_l.cpu().numpy()}
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host")
+        ref, cpu = cpu_baseline(prob.x32, spec)
+        parity = {"f32_max_abs_err_vs_fp64": float(np.abs(d_f32 - ref.dist).max())}
+        for prec, r in lowp.items():
+            parity[f"{prec}_max_abs_err_vs_fp64"] = float(np.abs(r["dist"] - ref.dist).max())
+    for r in lowp.values():
+        r.pop("dist", None)
+
+    phase1 = sum(stages[k] for k in ("prep", "similarity", "topk", "rescore", "adjacency"))
+    phase2 = stages["propagate"] + stages["final"]
+    line = {
+        "metric": METRIC,
+        "value": spec.n ** 2 / (ms * 1e-3),
+        "unit": "N^2-elem/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "ms_per_request": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "n": spec.n, "n_query": spec.n_query, "n_gallery": spec.n_gallery,
+                   "dim": spec.dim, "k1": spec.k1, "k2": spec.k2, "layers": spec.layers, "alpha": 2,
+                   "input_dtype": spec.dtype, "parallelism": "single GPU"},
+        "roofline": dom,
+        "cpu_baseline": cpu,
+        "stages_ms": stages,
+        "phase_ms": {"phase1_graph": phase1, "phase2_propagate_rank": phase2},
+        "stage_roofline": roof,
+        "lowp": lowp,
+        "parity": parity,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,194 @@
+/*
+ * rerank.h -- C ABI of the MI355X (gfx950) GNN re-ranking library.
+ *
+ * One re-ranking problem (Zhang et al., "Understanding Image Retrieval
+ * Re-Ranking: A Graph Neural Network Perspective", Section 3.1 problem
+ * definition and Section 3.3) is a set of N = Q + G feature vectors, the
+ * queries first (rows 0..Q-1) and the gallery after (rows Q..N-1), the union
+ * X_u of Eq. 7. Algorithm 1 turns it into query x gallery distances:
+ *
+ *   Eq. 7     S = cosine similarity of all rows (N x N)
+ *   Eq. 8     N(i, k1): the k1 most similar rows of row i (row i itself is
+ *             member 0 with similarity exactly 1; ties go to the lower index)
+ *   Eq. 9-11  h_i^(0) = row i of A* = (A + A^T) / 2
+ *   Eq. 12    edges e_ij = S_ij, j in N(i, k2) = the first k2 members of N(i, k1)
+ *   Eq. 14    h_i <- h_i + sum_j e_ij^alpha h_j, then h_i <- h_i / |h_i|,
+ *             repeated `layers` times (aggregator: sum)
+ *   final     D[q][g] = 1 - cos(h_q, h_{Q+g})
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers on the context's HIP device,
+ *     owned by the caller, row-major and contiguous. They must stay valid
+ *     until the work that uses them has completed (stream order for the
+ *     stream-ordered calls, until rerank_wait/rerank_poll report completion
+ *     for submitted requests).
+ *   - Functions return a rerank_status and never abort. Parameters are
+ *     validated before any work is enqueued; on error nothing is enqueued
+ *     and rerank_last_error() gives a readable reason.
+ *   - Inputs must be finite and no feature row may be all zero; the result is
+ *     unspecified otherwise.
+ *   - All library-owned device memory (similarity matrix, neighbour lists,
+ *     feature buffers) comes from a pool bounded by the context's budget.
+ */
+#ifndef RERANK_H
+#define RERANK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rerank_ctx rerank_ctx; /* opaque; created and owned by the library */
+
+typedef enum {
+  RERANK_OK = 0,
+  RERANK_E_INVALID = 1,   /* bad parameter or pointer */
+  RERANK_E_NOMEM = 2,     /* working set exceeds the context budget, or device allocation failed */
+  RERANK_E_HIP = 3,       /* a HIP runtime call or kernel launch failed */
+  RERANK_E_BUSY = 4,      /* request still running (rerank_poll/cancel) */
+  RERANK_E_TIMEOUT = 5,   /* rerank_wait timed out; the request keeps running */
+  RERANK_E_CANCELLED = 6, /* request was cancelled before it started */
+  RERANK_E_UNSUPPORTED = 7/* valid in the paper's terms but outside this build's limits */
+} rerank_status;
+
+/* Storage type of the caller's feature matrix. */
+typedef enum { RERANK_IN_F32 = 0, RERANK_IN_BF16 = 1 } rerank_in_dtype;
+
+/* Arithmetic of the Eq. 7 similarity product. F32 is the plain method.
+ * BF16 and FP8_E4M3 (per-row scales) compute S on low-precision matrix cores
+ * with FP32 accumulation, keep k1 + extra_cand candidates per row and
+ * re-score those in FP32 before the final k1 cut. Everything after the
+ * neighbour lists is FP32 in every mode. */
+typedef enum { RERANK_SIM_F32 = 0, RERANK_SIM_BF16 = 1, RERANK_SIM_FP8_E4M3 = 2 } rerank_sim_prec;
+
+/* Vertex feature h^(0) (Table 1 ablation columns): A* rows as in Eq. 11, or
+ * the raw features x_i (with zero layers this reproduces the initial
+ * cosine ranking). */
+typedef enum { RERANK_NODE_ADJ_SYM = 0, RERANK_NODE_RAW = 1 } rerank_node;
+
+/* Arithmetic of the final query x gallery product. F32 is plain FP32 matrix
+ * cores; BF16X3 splits each FP32 operand into a high and a low bfloat16 part
+ * and sums the three leading partial products on bfloat16 matrix cores with
+ * FP32 accumulation (relative error of each product about 2^-16). */
+typedef enum { RERANK_FINAL_F32 = 0, RERANK_FINAL_BF16X3 = 1 } rerank_final_prec;
+
+typedef struct {
+  int32_t n;          /* N = Q + G rows of X_u, N >= 2 */
+  int32_t n_query;    /* Q, 1 <= Q <= N - 1 */
+  int32_t dim;        /* feature dimension d >= 1 */
+  int32_t k1;         /* Eq. 8 list length, 1 <= k1 <= N */
+  int32_t k2;         /* Eq. 12 edges per vertex, 1 <= k2 <= k1 */
+  int32_t layers;     /* propagation steps of Eq. 14, 0 <= layers <= 256 */
+  int32_t alpha;      /* Eq. 14 weight exponent, integer 0..8 (the paper uses 2) */
+  int32_t sim_prec;   /* rerank_sim_prec */
+  int32_t extra_cand; /* candidates beyond k1 re-scored in FP32; -1 = default
+                         (8 for F32, 16 for BF16/FP8); 0 disables re-scoring
+                         (F32 only). k1 + extra_cand is capped at N and at 256. */
+  int32_t node;       /* rerank_node */
+  int32_t final_prec; /* rerank_final_prec */
+} rerank_params;
+
+/* Fill *p with the paper's settings (alpha 2, sum aggregator, A* features,
+ * two layers, FP32) for a problem of n rows, q queries, d dimensions and the
+ * given k1/k2. Pure host function. */
+void rerank_default_params(rerank_params* p, int32_t n, int32_t q, int32_t d, int32_t k1, int32_t k2);
+
+/* Check *p against the limits above. Pure host function (no device access). */
+rerank_status rerank_validate(const rerank_params* p);
+
+/* Bytes of library-owned device memory one problem with parameters *p needs.
+ * Pure host function; used for admission. */
+rerank_status rerank_workspace_bytes(const rerank_params* p, size_t* bytes);
+
+/* Context flags. STAGE_TIMING records a HIP event pair around every stage of
+ * the direct calls (on the call's stream) so rerank_stage_times can report
+ * per-stage device time; it adds no synchronisation. */
+#define RERANK_CTX_STAGE_TIMING 1u
+
+/* Create a context on HIP device `hip_device`. The context never holds more
+ * than `hbm_budget_bytes` of device memory (0 = 90% of the device's free
+ * memory at creation). flags: 0 or RERANK_CTX_STAGE_TIMING. */
+rerank_status rerank_create(rerank_ctx** out, int hip_device, size_t hbm_budget_bytes, uint32_t flags);
+
+/* Wait for all work of the context, stop its scheduler, free its memory. */
+rerank_status rerank_destroy(rerank_ctx* ctx);
+
+/* Full method (Algorithm 1), stream-ordered on `hip_stream` (a hipStream_t;
+ * NULL = the null stream); the host does not wait.
+ *   d_x     N x dim features, float32 or bfloat16 bit patterns (in_dtype)
+ *   d_dist  out: Q x G float32, D[q][g] = 1 - cos(h_q, h_{Q+g})
+ *   d_knn_idx, d_knn_val  optional out (NULL to skip): N x k1 int32 list of
+ *           N(i, k1) in rank order and the matching float32 similarities
+ * Calls on one context are serialised on the device in call order (they
+ * share the context's working memory), whatever streams they use. */
+rerank_status rerank_run(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype,
+                         float* d_dist, int32_t* d_knn_idx, float* d_knn_val, void* hip_stream);
+
+/* Phase 1 only (Eq. 7-8, the k-NN graph): the N x k1 neighbour lists and
+ * their similarities, same argument meaning as rerank_run. */
+rerank_status rerank_knn(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype,
+                         int32_t* d_knn_idx, float* d_knn_val, void* hip_stream);
+
+/* Eq. 7 only: d_s (N rows, row stride ld_s >= N floats) receives S computed
+ * with p->sim_prec arithmetic (low-precision modes return their
+ * low-precision S). Stream-ordered like rerank_run. */
+rerank_status rerank_similarity(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype,
+                                float* d_s, int64_t ld_s, void* hip_stream);
+
+/* ---- serving: asynchronous requests with admission and continuous batching
+ * A submitted request is admitted once its working set (rerank_workspace_bytes)
+ * fits in the free part of the context budget; admitted requests run
+ * concurrently on the context's streams. Each request's result is the same as
+ * rerank_run on the same input. The caller keeps d_x and d_dist valid until
+ * the request is reported done. Tickets are unique per context. */
+rerank_status rerank_submit(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype,
+                            float* d_dist, uint64_t* ticket);
+
+/* *done = 1 once the request finished (successfully or not), else 0. */
+rerank_status rerank_poll(rerank_ctx* ctx, uint64_t ticket, int* done);
+
+/* Block until the request is done or `timeout_us` passes (negative = no
+ * limit). Returns the request's own status (RERANK_OK, an error it met, or
+ * RERANK_E_CANCELLED), or RERANK_E_TIMEOUT. *latency_ms (optional) receives
+ * submit-to-completion time. A finished ticket is forgotten after a
+ * successful wait. */
+rerank_status rerank_wait(rerank_ctx* ctx, uint64_t ticket, int64_t timeout_us, double* latency_ms);
+
+/* Cancel a request that has not started; RERANK_E_BUSY if it already runs. */
+rerank_status rerank_cancel(rerank_ctx* ctx, uint64_t ticket);
+
+/* Stages of one problem, in pipeline order (Phase 1 of the paper's Table 3 is
+ * PREP..ADJACENCY, Phase 2 is PROPAGATE..FINAL). */
+typedef enum {
+  RERANK_STAGE_PREP = 0,       /* norms, padded / low-precision feature copies */
+  RERANK_STAGE_SIMILARITY = 1, /* Eq. 7 product */
+  RERANK_STAGE_TOPK = 2,       /* top-(k1 + extra) per row */
+  RERANK_STAGE_RESCORE = 3,    /* FP32 re-score and k1 cut (Eq. 8) */
+  RERANK_STAGE_ADJACENCY = 4,  /* A* rows, Eq. 9-11 */
+  RERANK_STAGE_PROPAGATE = 5,  /* all layers of Eq. 14 */
+  RERANK_STAGE_FINAL = 6,      /* query x gallery product and distances */
+  RERANK_STAGE_COUNT = 7
+} rerank_stage;
+
+/* Mean device milliseconds per direct call of each stage, over the direct
+ * calls since the previous rerank_stage_times on this context (waits for
+ * them to finish, then restarts the averages). Needs a context created with
+ * RERANK_CTX_STAGE_TIMING. ms_out receives RERANK_STAGE_COUNT values; stages
+ * that did not run read 0. RERANK_E_INVALID if timing is off. */
+rerank_status rerank_stage_times(rerank_ctx* ctx, double* ms_out);
+
+/* Static name of a stage ("prep", "similarity", ...), NULL if out of range. */
+const char* rerank_stage_name(int32_t stage);
+
+/* Static string for a status code. */
+const char* rerank_status_str(rerank_status s);
+
+/* Detail of the last error raised on this thread (any context), "" if none. */
+const char* rerank_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RERANK_H */

@@ -1,0 +1,29 @@
+// The context object behind the opaque rerank_ctx handle.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <mutex>
+#include <string>
+
+#include "pipeline.h"
+
+namespace rr {
+class Server;
+void set_error(const std::string& msg);
+rerank_status hip_fail(hipError_t e, const char* what);
+}  // namespace rr
+
+struct rerank_ctx {
+  int device = 0;
+  size_t budget = 0;
+  std::mutex mu;             // guards the direct-call working set below
+  void* ws = nullptr;        // working set of rerank_run / rerank_knn / rerank_similarity
+  size_t ws_bytes = 0;
+  hipEvent_t ws_free = nullptr;  // recorded after the last direct call's kernels
+  std::atomic<size_t> reserved{0};  // bytes held by the direct working set + admitted requests
+  uint32_t flags = 0;
+  rr::StageClock* clock = nullptr;  // set with RERANK_CTX_STAGE_TIMING
+  rr::Server* server = nullptr;     // serving scheduler, started on first submit
+  std::mutex server_mu;
+};

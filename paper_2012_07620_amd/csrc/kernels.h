@@ -1,0 +1,79 @@
+// Launchers of the gfx950 kernels (host side). Every launcher enqueues on
+// `s` and returns the launch status; shapes are validated by the caller.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rr {
+
+enum class SimPrec : int { F32 = 0, BF16 = 1, FP8 = 2 };
+enum class FinalPrec : int { F32 = 0, BF16X3 = 1 };
+
+// Row stride (elements) of the padded K-major copies the GEMMs read: every
+// row is a whole number of 128-byte stages.
+inline int64_t pad_k_elems(int64_t d, int bytes_per_elem) {
+  const int64_t per = 128 / bytes_per_elem;
+  return (d + per - 1) / per * per;
+}
+// Row stride of the N x N similarity / feature buffers (256-byte rows).
+inline int64_t pad_n(int64_t n) { return (n + 63) / 64 * 64; }
+
+// a1: feature preparation. Reads X (f32 or bf16 bits), writes
+//   xp  N x ldp float32 copy, zero-padded (always)
+//   rn  1 / |x_i| (compensated sum of squares, correctly rounded sqrt/div)
+//   xl  low-precision copy (bf16 or fp8 e4m3, ldl elements) when prec != F32
+//   sl  per-row scale of the low-precision product (rn_i, or rn_i * s_i)
+hipError_t launch_prep(const void* x, int in_bf16, int n, int d, float* xp, int64_t ldp, float* rn,
+                       SimPrec prec, void* xl, int64_t ldl, float* sl, hipStream_t s);
+
+// a2 / a7: C = A * B^T on matrix cores. A: M rows, B: Nn rows, K-major,
+// row strides in bytes (multiples of 128), kbytes = K extent in bytes.
+// Similarity epilogue: out[i][j] = acc * sa[i] * sb[j] (-0 -> +0), ldo floats.
+hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes,
+                           const float* sa, float* out, int64_t ldo, hipStream_t s);
+// Final epilogue: out[q][g] = 1 - sa[q] * sb[g] * acc, ldo floats.
+hipError_t launch_gemm_dist(const float* a, int M, const float* b, int Nn, int64_t ld_elems, int64_t kelems,
+                            const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s);
+hipError_t launch_gemm_dist_bf16x3(const uint16_t* a_hi, const uint16_t* a_lo, int M, const uint16_t* b_hi,
+                                   const uint16_t* b_lo, int Nn, int64_t ld_elems, int64_t kelems,
+                                   const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s);
+
+// a3: per-row top-K (K <= 256) of rows [0, rows) of S (row stride ldS,
+// N valid columns) under (value desc, column asc), the row's own column first.
+hipError_t launch_topk(const float* S, int64_t ldS, int N, int rows, int K, int32_t* idx, float* val,
+                       int ldo, hipStream_t s);
+
+// a3b: FP32 compensated re-score of Kc candidates per row, then the k1 cut.
+hipError_t launch_rescore(const float* xp, int64_t ldp, int d, const float* rn, int n, const int32_t* cand,
+                          int Kc, int k1, int32_t* knn_idx, float* knn_val, hipStream_t s);
+// Copy the first k1 of Kc candidates (no re-score).
+hipError_t launch_take_prefix(const int32_t* cand_idx, const float* cand_val, int n, int Kc, int k1,
+                              int32_t* knn_idx, float* knn_val, hipStream_t s);
+
+// a4: zero an n x ld float buffer (fill kernel, usable under graph capture).
+hipError_t launch_fill_zero(float* buf, int64_t count, hipStream_t s);
+// a4: scatter A* = (A + A^T)/2 into a zeroed N x ldH buffer; count in-degrees
+// and mutual pairs (for the zero-layer norms).
+hipError_t launch_astar_scatter(const int32_t* knn_idx, int n, int k1, float* H, int64_t ldH, int32_t* indeg,
+                                int32_t* mutual, hipStream_t s);
+// sigma_i = 1 / |A*_i| from the counts.
+hipError_t launch_astar_sigma(const int32_t* indeg, const int32_t* mutual, int n, int k1, float* sigma,
+                              hipStream_t s);
+
+// a5 + a6: one propagation layer (Eq. 14, sum aggregator) with lazy
+// normalisation: hout_i = sin_i*hin_i + sum_{r<k2} w_ir * sin_{j_r} * hin_{j_r},
+// w_i0 = 1 for the row itself, w_ir = val_ir^alpha; sout_i = 1/|hout_i|.
+// sin == nullptr means all ones. When hi/lo are non-null the row is also
+// written as bf16 high/low parts (final bf16x3 product).
+hipError_t launch_propagate(const float* hin, const float* sin, int n, int64_t ld, int64_t cols,
+                            const int32_t* knn_idx, const float* knn_val, int k1, int k2, int alpha,
+                            float* hout, float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s);
+// Split rows of an FP32 matrix into bf16 high/low parts (for L = 0 or raw).
+hipError_t launch_split_bf16(const float* h, int n, int64_t ld, uint16_t* hi, uint16_t* lo, hipStream_t s);
+
+// Copy helpers.
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t count, hipStream_t s);
+hipError_t launch_copy_f32(const float* src, float* dst, int64_t count, hipStream_t s);
+hipError_t launch_fill_f32(float* dst, float v, int64_t count, hipStream_t s);
+
+}  // namespace rr

@@ -1,0 +1,176 @@
+// Stream-ordered pipeline of one re-ranking problem (Algorithm 1):
+// prep -> similarity (Eq. 7) -> top-(k1+m) -> FP32 re-score -> k1 lists
+// (Eq. 8) -> A* (Eq. 9-11) -> L propagation layers (Eq. 12-14) -> final
+// query x gallery product. Every step is a kernel of this library.
+#include "pipeline.h"
+
+namespace rr {
+
+#define RR_TRY(call)                      \
+  do {                                    \
+    hipError_t e_ = (call);               \
+    if (e_ != hipSuccess) {               \
+      if (where) *where = #call;          \
+      return e_;                          \
+    }                                     \
+  } while (0)
+
+#define RR_STAGE(st, edge)                              \
+  do {                                                  \
+    if (clk) RR_TRY(clk->mark((st), (edge), s));        \
+  } while (0)
+
+hipError_t StageClock::init() {
+  for (auto& st : sets)
+    for (auto& pr : st.ev)
+      for (auto& e : pr) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+      }
+  return hipSuccess;
+}
+
+void StageClock::destroy() {
+  for (auto& st : sets)
+    for (auto& pr : st.ev)
+      for (auto& e : pr)
+        if (e) hipEventDestroy(e), e = nullptr;
+}
+
+hipError_t StageClock::harvest(Set& st) {
+  if (!st.pending) return hipSuccess;
+  for (int k = 0; k < RERANK_STAGE_COUNT; k++) {
+    if (!st.ran[k]) continue;
+    hipError_t r = hipEventSynchronize(st.ev[k][1]);
+    if (r != hipSuccess) return r;
+    float ms = 0.f;
+    r = hipEventElapsedTime(&ms, st.ev[k][0], st.ev[k][1]);
+    if (r != hipSuccess) return r;
+    sum_ms[k] += ms;
+    runs[k] += 1;
+    st.ran[k] = false;
+  }
+  st.pending = false;
+  return hipSuccess;
+}
+
+hipError_t StageClock::begin_call() {
+  cur = &sets[next];
+  next = (next + 1) % kSets;
+  return harvest(*cur);
+}
+
+hipError_t StageClock::totals(double* mean_ms) {
+  for (auto& st : sets) {
+    hipError_t r = harvest(st);
+    if (r != hipSuccess) return r;
+  }
+  for (int k = 0; k < RERANK_STAGE_COUNT; k++) {
+    mean_ms[k] = runs[k] ? sum_ms[k] / runs[k] : 0.0;
+    sum_ms[k] = 0.0;
+    runs[k] = 0;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+static T* at(void* ws, size_t off) {
+  return (T*)((char*)ws + off);
+}
+
+hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipStream_t s, const char** where,
+                       StageClock* clk) {
+  float* xp = at<float>(ws, P.o_xp);
+  float* rn = at<float>(ws, P.o_rn);
+  float* sl = at<float>(ws, P.o_sl);
+  void* xl = P.lbytes ? at<void>(ws, P.o_xl) : nullptr;
+  float* S = at<float>(ws, P.o_a);
+  int32_t* ci = at<int32_t>(ws, P.o_ci);
+  float* cv = at<float>(ws, P.o_cv);
+  int32_t* ki = at<int32_t>(ws, P.o_ki);
+  float* kv = at<float>(ws, P.o_kv);
+  RR_STAGE(RERANK_STAGE_PREP, 0);
+  RR_TRY(launch_prep(x, in_bf16, P.n, P.d, xp, P.ldp, rn, P.prec, xl, P.ldl, sl, s));
+  RR_STAGE(RERANK_STAGE_PREP, 1);
+  RR_STAGE(RERANK_STAGE_SIMILARITY, 0);
+  if (P.prec == SimPrec::F32)
+    RR_TRY(launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, S, P.ldN, s));
+  else
+    RR_TRY(launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, S, P.ldN, s));
+  RR_STAGE(RERANK_STAGE_SIMILARITY, 1);
+  RR_STAGE(RERANK_STAGE_TOPK, 0);
+  RR_TRY(launch_topk(S, P.ldN, P.n, P.n, P.kc, ci, cv, P.kc, s));
+  RR_STAGE(RERANK_STAGE_TOPK, 1);
+  RR_STAGE(RERANK_STAGE_RESCORE, 0);
+  if (P.rescore)
+    RR_TRY(launch_rescore(xp, P.ldp, P.d, rn, P.n, ci, P.kc, P.k1, ki, kv, s));
+  else
+    RR_TRY(launch_take_prefix(ci, cv, P.n, P.kc, P.k1, ki, kv, s));
+  RR_STAGE(RERANK_STAGE_RESCORE, 1);
+  return hipSuccess;
+}
+
+hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, float* dist, hipStream_t s,
+                          const char** where, StageClock* clk) {
+  hipError_t e = enqueue_knn(P, ws, x, in_bf16, s, where, clk);
+  if (e != hipSuccess) return e;
+  float* xp = at<float>(ws, P.o_xp);
+  float* rn = at<float>(ws, P.o_rn);
+  float* A = at<float>(ws, P.o_a);
+  float* B = P.layers > 0 ? at<float>(ws, P.o_b) : nullptr;
+  int32_t* ki = at<int32_t>(ws, P.o_ki);
+  float* kv = at<float>(ws, P.o_kv);
+  float* sa = at<float>(ws, P.o_sa);
+  float* sb = at<float>(ws, P.o_sb);
+  uint16_t* hi = P.fprec == FinalPrec::BF16X3 ? at<uint16_t>(ws, P.o_hi) : nullptr;
+  uint16_t* lo = P.fprec == FinalPrec::BF16X3 ? at<uint16_t>(ws, P.o_lo) : nullptr;
+
+  const float* cur;
+  const float* csig;
+  RR_STAGE(RERANK_STAGE_ADJACENCY, 0);
+  if (P.node == RERANK_NODE_ADJ_SYM) {
+    int32_t* indeg = at<int32_t>(ws, P.o_indeg);
+    int32_t* mut = at<int32_t>(ws, P.o_mut);
+    RR_TRY(launch_fill_zero(A, (int64_t)P.n * P.ldN, s));
+    RR_TRY(launch_fill_zero((float*)indeg, P.n & ~3, s));
+    RR_TRY(launch_fill_f32((float*)indeg + (P.n & ~3), 0.f, P.n & 3, s));
+    RR_TRY(launch_fill_zero((float*)mut, P.n & ~3, s));
+    RR_TRY(launch_fill_f32((float*)mut + (P.n & ~3), 0.f, P.n & 3, s));
+    RR_TRY(launch_astar_scatter(ki, P.n, P.k1, A, P.ldN, indeg, mut, s));
+    cur = A;
+    csig = nullptr;  // h^(0) is the raw A* row (not normalised)
+    if (P.layers == 0) {
+      RR_TRY(launch_astar_sigma(indeg, mut, P.n, P.k1, sa, s));
+      csig = sa;
+    }
+  } else {
+    cur = xp;  // raw features, zero-padded to ldp
+    csig = (P.layers == 0) ? rn : nullptr;
+  }
+  RR_STAGE(RERANK_STAGE_ADJACENCY, 1);
+  RR_STAGE(RERANK_STAGE_PROPAGATE, 0);
+  for (int l = 0; l < P.layers; l++) {
+    float* out = (cur == A) ? B : A;
+    float* osig = (csig == sa) ? sb : sa;
+    const bool last = (l == P.layers - 1);
+    RR_TRY(launch_propagate(cur, csig, P.n, P.ldH, P.ldH, ki, kv, P.k1, P.k2, P.alpha, out, osig,
+                            last ? hi : nullptr, last ? lo : nullptr, s));
+    cur = out;
+    csig = osig;
+  }
+  RR_STAGE(RERANK_STAGE_PROPAGATE, 1);
+  RR_STAGE(RERANK_STAGE_FINAL, 0);
+  const float* hq = cur;
+  const float* hg = cur + (size_t)P.q * P.ldH;
+  if (P.fprec == FinalPrec::F32) {
+    RR_TRY(launch_gemm_dist(hq, P.q, hg, P.g, P.ldH, P.ldH, csig, csig + P.q, dist, P.g, s));
+  } else {
+    if (P.layers == 0) RR_TRY(launch_split_bf16(cur, P.n, P.ldH, hi, lo, s));
+    RR_TRY(launch_gemm_dist_bf16x3(hi, lo, P.q, hi + (size_t)P.q * P.ldH, lo + (size_t)P.q * P.ldH, P.g, P.ldH,
+                                   P.ldH, csig, csig + P.q, dist, P.g, s));
+  }
+  RR_STAGE(RERANK_STAGE_FINAL, 1);
+  return hipSuccess;
+}
+
+}  // namespace rr

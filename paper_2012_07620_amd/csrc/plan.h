@@ -1,0 +1,39 @@
+// Parameter validation and device working-set layout of one problem.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/rerank.h"
+#include "kernels.h"
+
+namespace rr {
+
+constexpr int kMaxCand = 256;   // k1 + extra candidates held by one wavefront
+constexpr int kMaxLayers = 256; // Table 2 goes up to 256 layers
+constexpr int kMaxAlpha = 8;
+
+struct Plan {
+  int n = 0, q = 0, g = 0, d = 0, k1 = 0, k2 = 0, layers = 0, alpha = 0, kc = 0;
+  SimPrec prec = SimPrec::F32;
+  FinalPrec fprec = FinalPrec::F32;
+  bool rescore = false;
+  int node = RERANK_NODE_ADJ_SYM;
+  int64_t ldp = 0;  // fp32 feature copy row stride (elements)
+  int64_t ldl = 0;  // low-precision copy row stride (elements)
+  int lbytes = 0;   // bytes per low-precision element
+  int64_t ldN = 0;  // similarity / A* row stride
+  int64_t ldH = 0;  // propagated feature row stride (ldN, or ldp in raw mode)
+  // byte offsets into the working set
+  size_t o_xp = 0, o_xl = 0, o_rn = 0, o_sl = 0, o_a = 0, o_b = 0, o_ci = 0, o_cv = 0, o_ki = 0, o_kv = 0,
+         o_sa = 0, o_sb = 0, o_indeg = 0, o_mut = 0, o_hi = 0, o_lo = 0;
+  size_t total = 0;
+};
+
+// Returns RERANK_OK or an error with a reason in *why.
+rerank_status validate_params(const rerank_params* p, std::string* why);
+// Fills the layout for valid parameters. knn_only skips propagation buffers.
+void make_plan(const rerank_params* p, bool knn_only, Plan* out);
+
+}  // namespace rr

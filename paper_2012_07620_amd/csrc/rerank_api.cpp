@@ -1,0 +1,332 @@
+// C entry points declared in include/rerank.h.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ctx.h"
+#include "pipeline.h"
+#include "serve.h"
+
+namespace rr {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+rerank_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what ? what : "HIP call") + ": " + hipGetErrorString(e));
+  return (e == hipErrorOutOfMemory) ? RERANK_E_NOMEM : RERANK_E_HIP;
+}
+
+// Grow the direct-call working set to `bytes` (device memory, within budget).
+static rerank_status ensure_ws(rerank_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return RERANK_OK;
+  if (bytes > c->budget) {
+    set_error("working set of " + std::to_string(bytes) + " bytes exceeds the context budget of " +
+              std::to_string(c->budget));
+    return RERANK_E_NOMEM;
+  }
+  const size_t others = c->reserved.load() - c->ws_bytes;
+  if (others + bytes > c->budget) {
+    set_error("working set does not fit next to the admitted serving requests");
+    return RERANK_E_NOMEM;
+  }
+  if (c->ws) {
+    hipError_t e = hipEventSynchronize(c->ws_free);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    e = hipFree(c->ws);
+    if (e != hipSuccess) return hip_fail(e, "hipFree");
+    c->reserved -= c->ws_bytes;
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&c->ws, bytes);
+  if (e != hipSuccess) {
+    c->ws = nullptr;
+    return hip_fail(e, "hipMalloc(working set)");
+  }
+  c->ws_bytes = bytes;
+  c->reserved += bytes;
+  return RERANK_OK;
+}
+
+static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+static rerank_status check_common(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype) {
+  std::string why;
+  if (!ctx) {
+    set_error("ctx is NULL");
+    return RERANK_E_INVALID;
+  }
+  rerank_status st = validate_params(p, &why);
+  if (st != RERANK_OK) {
+    set_error(why);
+    return st;
+  }
+  if (in_dtype != RERANK_IN_F32 && in_dtype != RERANK_IN_BF16) {
+    set_error("unknown in_dtype");
+    return RERANK_E_INVALID;
+  }
+  if (!d_x || !aligned(d_x, in_dtype == RERANK_IN_F32 ? 4 : 2)) {
+    set_error("d_x is NULL or misaligned");
+    return RERANK_E_INVALID;
+  }
+  return RERANK_OK;
+}
+
+// Run `body` on the context's working set, serialised after earlier direct calls.
+template <typename F>
+static rerank_status with_ws(rerank_ctx* ctx, const Plan& P, void* hip_stream, F body) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  rerank_status st = ensure_ws(ctx, P.total);
+  if (st != RERANK_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  e = hipStreamWaitEvent(s, ctx->ws_free, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  const char* where = nullptr;
+  if (ctx->clock) {
+    e = ctx->clock->begin_call();
+    if (e != hipSuccess) return hip_fail(e, "stage clock");
+  }
+  e = body(s, &where);
+  if (e != hipSuccess) return hip_fail(e, where);
+  e = hipEventRecord(ctx->ws_free, s);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return RERANK_OK;
+}
+
+}  // namespace rr
+
+using namespace rr;
+
+extern "C" {
+
+void rerank_default_params(rerank_params* p, int32_t n, int32_t q, int32_t d, int32_t k1, int32_t k2) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->n = n;
+  p->n_query = q;
+  p->dim = d;
+  p->k1 = k1;
+  p->k2 = k2;
+  p->layers = 2;
+  p->alpha = 2;
+  p->sim_prec = RERANK_SIM_F32;
+  p->extra_cand = -1;
+  p->node = RERANK_NODE_ADJ_SYM;
+  p->final_prec = RERANK_FINAL_F32;
+}
+
+rerank_status rerank_validate(const rerank_params* p) {
+  std::string why;
+  rerank_status st = validate_params(p, &why);
+  if (st != RERANK_OK) set_error(why);
+  return st;
+}
+
+rerank_status rerank_workspace_bytes(const rerank_params* p, size_t* bytes) {
+  std::string why;
+  rerank_status st = validate_params(p, &why);
+  if (st != RERANK_OK) {
+    set_error(why);
+    return st;
+  }
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return RERANK_E_INVALID;
+  }
+  Plan P;
+  make_plan(p, false, &P);
+  *bytes = P.total;
+  return RERANK_OK;
+}
+
+rerank_status rerank_create(rerank_ctx** out, int hip_device, size_t hbm_budget_bytes, uint32_t flags) {
+  if (!out) {
+    set_error("out is NULL");
+    return RERANK_E_INVALID;
+  }
+  *out = nullptr;
+  if (flags & ~RERANK_CTX_STAGE_TIMING) {
+    set_error("unknown flags");
+    return RERANK_E_INVALID;
+  }
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (hip_device < 0 || hip_device >= count) {
+    set_error("no such HIP device");
+    return RERANK_E_INVALID;
+  }
+  e = hipSetDevice(hip_device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  size_t free_b = 0, total_b = 0;
+  e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) return hip_fail(e, "hipMemGetInfo");
+  rerank_ctx* c = new (std::nothrow) rerank_ctx();
+  if (!c) {
+    set_error("host allocation failed");
+    return RERANK_E_NOMEM;
+  }
+  c->device = hip_device;
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+  c->flags = flags;
+  e = hipEventCreateWithFlags(&c->ws_free, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipEventCreate");
+  }
+  if (flags & RERANK_CTX_STAGE_TIMING) {
+    c->clock = new StageClock();
+    e = c->clock->init();
+    if (e != hipSuccess) {
+      c->clock->destroy();
+      delete c->clock;
+      hipEventDestroy(c->ws_free);
+      delete c;
+      return hip_fail(e, "hipEventCreate(stage clock)");
+    }
+  }
+  *out = c;
+  return RERANK_OK;
+}
+
+rerank_status rerank_destroy(rerank_ctx* ctx) {
+  if (!ctx) {
+    set_error("ctx is NULL");
+    return RERANK_E_INVALID;
+  }
+  rerank_status st = RERANK_OK;
+  hipSetDevice(ctx->device);
+  if (ctx->server) {
+    server_stop(ctx->server);
+    ctx->server = nullptr;
+  }
+  if (ctx->ws) {
+    hipError_t e = hipEventSynchronize(ctx->ws_free);
+    if (e != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
+    hipFree(ctx->ws);
+  }
+  if (ctx->ws_free) hipEventDestroy(ctx->ws_free);
+  if (ctx->clock) {
+    ctx->clock->destroy();
+    delete ctx->clock;
+  }
+  delete ctx;
+  return st;
+}
+
+rerank_status rerank_run(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype, float* d_dist,
+                         int32_t* d_knn_idx, float* d_knn_val, void* hip_stream) {
+  rerank_status st = check_common(ctx, p, d_x, in_dtype);
+  if (st != RERANK_OK) return st;
+  if (!d_dist || !aligned(d_dist, 4)) {
+    set_error("d_dist is NULL or misaligned");
+    return RERANK_E_INVALID;
+  }
+  if ((d_knn_idx && !aligned(d_knn_idx, 4)) || (d_knn_val && !aligned(d_knn_val, 4))) {
+    set_error("knn output misaligned");
+    return RERANK_E_INVALID;
+  }
+  Plan P;
+  make_plan(p, false, &P);
+  return with_ws(ctx, P, hip_stream, [&](hipStream_t s, const char** where) -> hipError_t {
+    hipError_t e = enqueue_rerank(P, ctx->ws, d_x, in_dtype == RERANK_IN_BF16, d_dist, s, where, ctx->clock);
+    if (e != hipSuccess) return e;
+    const int64_t cnt = (int64_t)P.n * P.k1;
+    if (d_knn_idx) {
+      e = launch_copy_i32((const int32_t*)((char*)ctx->ws + P.o_ki), d_knn_idx, cnt, s);
+      if (e != hipSuccess) return e;
+    }
+    if (d_knn_val) e = launch_copy_f32((const float*)((char*)ctx->ws + P.o_kv), d_knn_val, cnt, s);
+    return e;
+  });
+}
+
+rerank_status rerank_knn(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype,
+                         int32_t* d_knn_idx, float* d_knn_val, void* hip_stream) {
+  rerank_status st = check_common(ctx, p, d_x, in_dtype);
+  if (st != RERANK_OK) return st;
+  if (!d_knn_idx || !d_knn_val || !aligned(d_knn_idx, 4) || !aligned(d_knn_val, 4)) {
+    set_error("knn outputs are NULL or misaligned");
+    return RERANK_E_INVALID;
+  }
+  Plan P;
+  make_plan(p, true, &P);
+  return with_ws(ctx, P, hip_stream, [&](hipStream_t s, const char** where) -> hipError_t {
+    hipError_t e = enqueue_knn(P, ctx->ws, d_x, in_dtype == RERANK_IN_BF16, s, where, ctx->clock);
+    if (e != hipSuccess) return e;
+    const int64_t cnt = (int64_t)P.n * P.k1;
+    e = launch_copy_i32((const int32_t*)((char*)ctx->ws + P.o_ki), d_knn_idx, cnt, s);
+    if (e != hipSuccess) return e;
+    return launch_copy_f32((const float*)((char*)ctx->ws + P.o_kv), d_knn_val, cnt, s);
+  });
+}
+
+rerank_status rerank_similarity(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype,
+                                float* d_s, int64_t ld_s, void* hip_stream) {
+  rerank_status st = check_common(ctx, p, d_x, in_dtype);
+  if (st != RERANK_OK) return st;
+  if (!d_s || !aligned(d_s, 4) || ld_s < p->n) {
+    set_error("d_s is NULL/misaligned or ld_s < n");
+    return RERANK_E_INVALID;
+  }
+  Plan P;
+  make_plan(p, true, &P);
+  return with_ws(ctx, P, hip_stream, [&](hipStream_t s, const char** where) -> hipError_t {
+    float* xp = (float*)((char*)ctx->ws + P.o_xp);
+    float* rn = (float*)((char*)ctx->ws + P.o_rn);
+    float* sl = (float*)((char*)ctx->ws + P.o_sl);
+    void* xl = P.lbytes ? (char*)ctx->ws + P.o_xl : nullptr;
+    hipError_t e = launch_prep(d_x, in_dtype == RERANK_IN_BF16, P.n, P.d, xp, P.ldp, rn, P.prec, xl, P.ldl, sl, s);
+    if (e != hipSuccess) {
+      *where = "launch_prep";
+      return e;
+    }
+    if (P.prec == SimPrec::F32)
+      e = launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, d_s, ld_s, s);
+    else
+      e = launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, d_s, ld_s, s);
+    if (e != hipSuccess) *where = "launch_gemm_sim";
+    return e;
+  });
+}
+
+rerank_status rerank_stage_times(rerank_ctx* ctx, double* ms_out) {
+  if (!ctx || !ms_out || !ctx->clock) {
+    set_error("stage timing is off for this context");
+    return RERANK_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipError_t e = ctx->clock->totals(ms_out);
+  if (e != hipSuccess) return hip_fail(e, "stage clock");
+  return RERANK_OK;
+}
+
+const char* rerank_stage_name(int32_t stage) {
+  static const char* names[RERANK_STAGE_COUNT] = {"prep",      "similarity", "topk", "rescore",
+                                                  "adjacency", "propagate",  "final"};
+  return (stage >= 0 && stage < RERANK_STAGE_COUNT) ? names[stage] : nullptr;
+}
+
+const char* rerank_status_str(rerank_status s) {
+  switch (s) {
+    case RERANK_OK: return "ok";
+    case RERANK_E_INVALID: return "invalid argument";
+    case RERANK_E_NOMEM: return "out of memory budget";
+    case RERANK_E_HIP: return "HIP error";
+    case RERANK_E_BUSY: return "busy";
+    case RERANK_E_TIMEOUT: return "timeout";
+    case RERANK_E_CANCELLED: return "cancelled";
+    case RERANK_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* rerank_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

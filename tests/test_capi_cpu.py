@@ -1,0 +1,88 @@
+"""The C-ABI library loads and exports every entry point the header declares;
+host-only entry points (validation, working-set size, status strings) behave.
+No GPU needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2012_07620_amd import binding
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "rerank.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rerank_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.library()
+    names = declared_symbols()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(binding.EXPORTS)
+
+
+def test_params_struct_matches_header():
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{(.*?)\} rerank_params;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b([a-z_0-9]+)\s*[;,]", body)
+    assert fields == [f for f, _ in binding.Params._fields_]
+
+
+def _p(**kw):
+    base = dict(n=1000, n_query=100, dim=128, k1=10, k2=3, layers=1)
+    base.update(kw)
+    return binding.make_params(**base)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(), binding.OK),
+    (dict(n=1), binding.E_INVALID),
+    (dict(n_query=0), binding.E_INVALID),
+    (dict(n_query=1000), binding.E_INVALID),
+    (dict(dim=0), binding.E_INVALID),
+    (dict(k1=0), binding.E_INVALID),
+    (dict(k1=1001), binding.E_INVALID),
+    (dict(k2=11), binding.E_INVALID),
+    (dict(k2=0), binding.E_INVALID),
+    (dict(layers=-1), binding.E_INVALID),
+    (dict(layers=257), binding.E_INVALID),
+    (dict(alpha=9), binding.E_INVALID),
+    (dict(alpha=-1), binding.E_INVALID),
+    (dict(k1=257, n=5000), binding.E_UNSUPPORTED),
+    (dict(sim_prec="bf16", extra_cand=0), binding.E_INVALID),
+    (dict(k1=1000, k2=1000, n=1000), binding.E_UNSUPPORTED),
+    (dict(k1=256, k2=7, n=300), binding.OK),
+])
+def test_validation(kw, status):
+    assert binding.validate(_p(**kw)) == status
+    if status != binding.OK:
+        assert binding.library().rerank_last_error().decode()
+
+
+def test_workspace_bytes_scales_with_n_squared():
+    a = binding.workspace_bytes(_p())
+    b = binding.workspace_bytes(_p(n=2000))
+    c = binding.workspace_bytes(_p(layers=0))
+    assert a > 2 * 4 * 1000 * 1000  # at least the two N x N float buffers
+    assert 3.5 < b / a < 4.5
+    assert c < a
+    mid = binding.workspace_bytes(binding.make_params(19281, 3368, 2048, 26, 7, 1))
+    assert 2 * 4 * 19281 * 19281 < mid < 3.5e9
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    lib = binding.library()
+    p = _p()
+    assert lib.rerank_workspace_bytes(ctypes.byref(p), None) == binding.E_INVALID
+    assert lib.rerank_validate(None) == binding.E_INVALID
+    assert lib.rerank_run(None, ctypes.byref(p), None, 0, None, None, None, None) == binding.E_INVALID
+    assert lib.rerank_create(None, 0, 0, 0) == binding.E_INVALID
+    for s in range(8):
+        assert lib.rerank_status_str(s)

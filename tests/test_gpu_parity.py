@@ -1,0 +1,158 @@
+"""GPU path vs the FP64 oracle on small problems (several tiles, ragged
+tails, degenerate cases). Every call goes through the C-ABI library."""
+import numpy as np
+import pytest
+
+from oracle import rerank_oracle as orc
+from paper_2012_07620_amd import synth
+from tests.parity import compare_distances, compare_lists, tainted_rows
+
+pytestmark = pytest.mark.gpu
+
+D_TOL_F32 = 1e-4  # FP32 path: |D - D_oracle|
+D_TOL_LOWP = 2e-2  # BF16 / FP8 similarity paths
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _run(gpu_lib, x, q, k1, k2, layers, **kw):
+    import torch
+    from paper_2012_07620_amd import binding
+    d, ki, kv = binding.run(_dev(x), q, k1, k2, layers, return_knn=True, **kw)
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), ki.cpu().numpy(), kv.cpu().numpy()
+
+
+def _check_full(gpu_lib, x, q, k1, k2, layers, alpha=2, node="adj", tol=D_TOL_F32, **kw):
+    print(f"case n={len(x)} q={q} d={x.shape[1]} k1={k1} k2={k2} L={layers} alpha={alpha} node={node} {kw}",
+          flush=True)
+    dg, ki, kv = _run(gpu_lib, x, q, k1, k2, layers, alpha=alpha, node=node, **kw)
+    ref = orc.rerank(x, q, k1, k2, layers, alpha=alpha, node=node)
+    f1, f2 = compare_lists(ki, ref.graph, k2)
+    ok = ~np.isin(np.arange(len(x)), f1)
+    np.testing.assert_allclose(kv[ok], ref.graph.val[ok], atol=2e-6)
+    taint = tainted_rows(ref.graph.idx, ki, f1, f2, k2, layers)
+    return compare_distances(dg, ref.dist, q, taint, tol)
+
+
+def test_similarity_f32_tiny(gpu_lib):
+    import torch
+    from paper_2012_07620_amd import binding
+    p = synth.make_problem(synth.TINY)
+    s = binding.similarity(_dev(p.x32))
+    torch.cuda.synchronize()
+    s = s.cpu().numpy()
+    ref = orc.similarity_rows(orc.unit_rows(p.x32), range(p.spec.n))
+    err = np.abs(s - ref).max()
+    print("max |S - S64| =", err)
+    assert err < 2e-6
+    assert np.array_equal(s, s.T)
+
+
+def test_knn_f32_tiny(gpu_lib):
+    import torch
+    from paper_2012_07620_amd import binding
+    p = synth.make_problem(synth.TINY)
+    ki, kv = binding.knn(_dev(p.x32), 10)
+    torch.cuda.synchronize()
+    g = orc.knn_lists(p.x32, 10, 3)
+    f1, f2 = compare_lists(ki.cpu().numpy(), g, 3)
+    assert f1.size == 0 and f2.size == 0
+    np.testing.assert_allclose(kv.cpu().numpy(), g.val, atol=2e-7)
+
+
+def test_run_f32_tiny(gpu_lib):
+    p = synth.make_problem(synth.TINY)
+    s = p.spec
+    mx, mean, excused = _check_full(gpu_lib, p.x32, s.n_query, s.k1, s.k2, s.layers)
+    print(f"tiny f32: max err {mx:.2e} mean {mean:.2e} excused {excused}")
+    assert excused == 0
+
+
+EDGE = [
+    # n, q, d, k1, k2, layers, alpha, node, dup, n_ids
+    (2, 1, 1, 1, 1, 0, 2, "adj", 0.0, 0),
+    (2, 1, 3, 2, 2, 1, 2, "adj", 0.0, 0),
+    (5, 2, 2, 3, 2, 1, 2, "adj", 0.0, 0),
+    (65, 7, 33, 5, 2, 2, 2, "adj", 0.0, 4),
+    (130, 30, 64, 9, 4, 3, 2, "adj", 0.2, 6),
+    (200, 50, 17, 200, 7, 1, 2, "adj", 0.0, 0),
+    (257, 64, 128, 1, 1, 2, 2, "adj", 0.0, 5),
+    (300, 100, 40, 12, 12, 0, 2, "adj", 0.0, 10),
+    (300, 100, 40, 12, 5, 2, 0, "adj", 0.0, 10),
+    (333, 33, 96, 20, 6, 0, 2, "raw", 0.0, 8),
+    (333, 33, 96, 20, 6, 2, 2, "raw", 0.0, 8),
+    (511, 200, 256, 64, 8, 1, 3, "adj", 0.1, 20),
+    (700, 300, 24, 100, 10, 2, 2, "adj", 0.0, 7),
+    (1029, 129, 130, 250, 30, 1, 2, "adj", 0.0, 9),
+]
+
+
+@pytest.mark.parametrize("n,q,d,k1,k2,layers,alpha,node,dup,n_ids", EDGE)
+def test_edge_cases_f32(gpu_lib, n, q, d, k1, k2, layers, alpha, node, dup, n_ids):
+    x = synth.random_features(n, d, seed=n * 7 + d, n_ids=n_ids, dup_frac=dup)
+    mx, mean, excused = _check_full(gpu_lib, x, q, k1, k2, layers, alpha=alpha, node=node)
+    print(f"max err {mx:.2e} mean {mean:.2e} excused pairs {excused}")
+
+
+def test_integer_ties_hand_example(gpu_lib):
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_5pt.json")))
+    x = np.array(g["x"], dtype=np.float32)
+    for layers, key in ((0, "D_layers0"), (1, "D_layers1")):
+        dg, ki, _ = _run(gpu_lib, x, g["n_query"], g["k1"], g["k2"], layers)
+        assert ki.tolist() == g["lists"]
+        np.testing.assert_allclose(dg, np.array(g[key]), atol=1e-6)
+
+
+def test_bf16_input_matches_f32_of_same_values(gpu_lib):
+    import torch
+    spec = synth.ProblemSpec("b", 40, 260, 64, 12, 0.5, 0.05, 8, 3, 2, "bf16", 9)
+    p = synth.make_problem(spec)
+    xb = torch.from_numpy(p.x_bf16.view(np.int16)).cuda().view(torch.bfloat16)
+    from paper_2012_07620_amd import binding
+    d1 = binding.run(xb, 40, 8, 3, 2)
+    d2 = binding.run(_dev(p.x32), 40, 8, 3, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(d1, d2)
+    _check_full(gpu_lib, p.x32, 40, 8, 3, 2)
+
+
+def test_repeat_runs_bit_identical(gpu_lib):
+    import torch
+    from paper_2012_07620_amd import binding
+    p = synth.make_problem(synth.TINY)
+    x = _dev(p.x32)
+    a = binding.run(x, 100, 10, 3, 2)
+    b = binding.run(x, 100, 10, 3, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_low_precision_tiny(gpu_lib, prec):
+    p = synth.make_problem(synth.TINY)
+    s = p.spec
+    dg, ki, kv = _run(gpu_lib, p.x32, s.n_query, s.k1, s.k2, s.layers, sim_prec=prec)
+    ref = orc.rerank(p.x32, s.n_query, s.k1, s.k2, s.layers)
+    overlap = np.mean([len(set(a) & set(b)) / s.k1 for a, b in zip(ki.tolist(), ref.graph.idx.tolist())])
+    err = np.abs(dg - ref.dist)
+    print(f"{prec}: top-k1 overlap {overlap:.5f}, D max err {err.max():.2e} mean {err.mean():.2e}")
+    assert overlap >= 0.995
+    assert err.max() <= D_TOL_LOWP
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_low_precision_similarity_error(gpu_lib, prec):
+    import torch
+    from paper_2012_07620_amd import binding
+    p = synth.make_problem(synth.TINY)
+    s = binding.similarity(_dev(p.x32), sim_prec=prec)
+    torch.cuda.synchronize()
+    ref = orc.similarity_rows(orc.unit_rows(p.x32), range(p.spec.n))
+    err = np.abs(s.cpu().numpy() - ref)
+    print(f"{prec}: max |S - S64| = {err.max():.3e}, mean {err.mean():.3e}")
+    assert err.max() < (0.02 if prec == "bf16" else 0.08)
