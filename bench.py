@@ -37,7 +37,7 @@ def stage_work(spec, prec: str):
     """Algorithmic work of one request per stage: (unit, amount)."""
     n, q, g, d = spec.n, spec.n_query, spec.n_gallery, spec.dim
     k1, k2, L = spec.k1, spec.k2, spec.layers
-    kc = min(k1 + (8 if prec == "f32" else 16), n, 256)
+    kc = min(k1 + {"f32": 8, "bf16": 16, "fp8": 32}[prec], n, 256)
     return {
         "similarity": ("flop", 2.0 * n * n * d),
         "topk": ("byte", 4.0 * n * n),
@@ -106,6 +106,8 @@ def main() -> int:
     ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lowp", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, copy a 1 GiB float32 tensor once (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -147,6 +149,14 @@ def main() -> int:
                           "similarity_roofline": roofline_entry("similarity", *wl["similarity"], st_l["similarity"],
                                                                 prec),
                           "dist": out_l.cpu().numpy()}
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     cpu = None
     parity = None

@@ -84,8 +84,9 @@ typedef struct {
   int32_t alpha;      /* Eq. 14 weight exponent, integer 0..8 (the paper uses 2) */
   int32_t sim_prec;   /* rerank_sim_prec */
   int32_t extra_cand; /* candidates beyond k1 re-scored in FP32; -1 = default
-                         (8 for F32, 16 for BF16/FP8); 0 disables re-scoring
-                         (F32 only). k1 + extra_cand is capped at N and at 256. */
+                         (8 for F32, 16 for BF16, 32 for FP8); 0 disables
+                         re-scoring (F32 only). k1 + extra_cand is capped at N
+                         and at 256. */
   int32_t node;       /* rerank_node */
   int32_t final_prec; /* rerank_final_prec */
 } rerank_params;

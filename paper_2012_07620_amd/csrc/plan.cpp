@@ -47,7 +47,7 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o) {
   P.fprec = (FinalPrec)p->final_prec;
   P.node = p->node;
   int extra = p->extra_cand;
-  if (extra < 0) extra = (P.prec == SimPrec::F32) ? 8 : 16;
+  if (extra < 0) extra = (P.prec == SimPrec::F32) ? 8 : (P.prec == SimPrec::BF16 ? 16 : 32);
   int64_t kc = (int64_t)p->k1 + extra;
   if (kc > p->n) kc = p->n;
   if (kc > kMaxCand) kc = kMaxCand;
