@@ -82,6 +82,59 @@ def time_path(binding, torch, ctx, x, spec, prec, steps, warmup, out):
     return ms, ctx.stage_times()
 
 
+def serve_stream(binding, torch, synth, count, warmup, qps=None, prec="f32", reqs=None):
+    """Submit the requests of a serving stream and wait for all of them.
+
+    qps None: closed loop (everything submitted at once; the throughput is the
+    saturation rate). Otherwise requests are submitted at their Poisson arrival
+    times. Latency = submit -> completion, as measured by the library."""
+    ctx = binding.Context(0)
+    xs, outs, specs = reqs
+    # warm-up requests: compile graphs, fill the working-set cache
+    for i in range(warmup):
+        s = specs[i]
+        t = binding.submit(ctx, xs[i], outs[i], s.n_query, s.k1, s.k2, s.layers, sim_prec=prec)
+        binding.wait(ctx, t)
+    meas = range(warmup, warmup + count)
+    rng = np.random.default_rng(17)
+    gaps = rng.exponential(1.0 / qps, len(meas)) if qps else np.zeros(len(meas))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = []
+    for k, i in enumerate(meas):
+        if qps:
+            delay = t0 + arrivals[k] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+        s = specs[i]
+        tickets.append(binding.submit(ctx, xs[i], outs[i], s.n_query, s.k1, s.k2, s.layers, sim_prec=prec))
+    lat = [binding.wait(ctx, t) for t in tickets]
+    t1 = time.perf_counter()
+    ctx.close()
+    n2 = sum(specs[i].n ** 2 for i in meas)
+    return {"requests": len(meas), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(np.mean(lat)), "req_per_s": len(meas) / (t1 - t0), "n2_per_s": n2 / (t1 - t0)}
+
+
+def serving_bench(binding, torch, synth, count, warmup):
+    stream = synth.StreamSpec()
+    specs = [s for _, s in synth.request_specs(stream, count + warmup, qps=1.0)]
+    dev = torch.device("cuda:0")
+    xs = [synth.make_features_device(s, dev) for s in specs]
+    outs = [torch.empty((s.n_query, s.n_gallery), dtype=torch.float32, device=dev) for s in specs]
+    torch.cuda.synchronize()
+    reqs = (xs, outs, specs)
+    sat = serve_stream(binding, torch, synth, count, warmup, None, "f32", reqs)
+    qps = 0.7 * sat["req_per_s"]
+    res = {"stream": "N ~ U[1000, 30000], 15% queries, d in {512, 2048}, bf16, k1=20 k2=6 L=1, Poisson arrivals",
+           "saturation_f32_req_per_s": sat["req_per_s"], "qps": qps}
+    for prec in ("f32", "bf16"):
+        res[prec] = serve_stream(binding, torch, synth, count, warmup, qps, prec, reqs)
+    del xs, outs
+    return res
+
+
 def cpu_baseline(x32, spec):
     """The FP64 oracle (as it stands) on the same problem, on this host."""
     from oracle import rerank_oracle as orc
@@ -106,6 +159,8 @@ def main() -> int:
     ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lowp", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy a 1 GiB float32 tensor once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -154,9 +209,15 @@ def main() -> int:
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)  # reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del a, b
+
+    serving = None
+    if not args.no_serve:
+        log("serving stream")
+        del out
+        serving = serving_bench(binding, torch, synth, args.serve_requests, 20)
 
     cpu = None
     parity = None
@@ -195,6 +256,7 @@ def main() -> int:
         "stage_roofline": roof,
         "lowp": lowp,
         "parity": parity,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -1,0 +1,207 @@
+// Tile engine of the "NT" products C = A * B^T on gfx950 matrix cores,
+// shared by the direct launches (one tile per workgroup) and the persistent
+// grouped launches of the serving path (workgroups loop over tiles).
+//
+// Both operands are K-major rows (feature rows for the Eq. 7 similarity,
+// refined feature rows for the final ranking product), so each 128 x 128
+// output tile streams 128-byte K slices of 128 A rows and 128 B rows through
+// LDS (double-buffered, 144-byte padded rows), and four wavefronts each own a
+// 64 x 64 sub-tile of 2 x 2 MFMA 32x32 blocks.
+//
+// K order inside a stage: lane half h = lane/32 feeds the MFMA with bytes
+// [64h, 64h+64) of its row's 128-byte slice. A and B use the same map, so
+// every product pairs equal K positions; the K summation order is simply
+// permuted, which a dot product allows.
+//
+// Element types per 128-byte stage: 32 fp32 (v_mfma 32x32x2 f32, 16 steps),
+// 64 bf16 (32x32x16 bf16, 4 steps) or 128 OCP e4m3 (32x32x64 f8f6f4, unit
+// block scales, 2 steps). Accumulation is FP32 in every mode.
+#pragma once
+#include "common.h"
+
+namespace rr {
+
+constexpr int BM = 128, BN = 128, BKB = 128, LDSR = BKB + 16, TILEB = BM * LDSR;
+constexpr int GEMM_LDS_BYTES = 4 * TILEB;  // 73728
+constexpr int TSTRIDE = BM + 1;            // transposed-tile LDS row stride (floats)
+static_assert(BN * TSTRIDE * 4 <= GEMM_LDS_BYTES, "transpose staging must fit the GEMM LDS");
+
+enum { MODE_F32 = 0, MODE_BF16 = 1, MODE_FP8 = 2 };
+enum { EPI_SIM = 0, EPI_DIST = 1, EPI_SIM_SYM = 2 };
+
+template <int MODE>
+__device__ __forceinline__ void mfma_stage(f32x16 (&acc)[2][2], const u32x4 (&a)[2][4], const u32x4 (&b)[2][4]) {
+  if constexpr (MODE == MODE_F32) {
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+#pragma unroll
+        for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+          for (int sn = 0; sn < 2; sn++)
+            acc[sm][sn] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[sm][c][e]),
+                                                               __uint_as_float(b[sn][c][e]), acc[sm][sn], 0, 0, 0);
+  } else if constexpr (MODE == MODE_BF16) {
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+#pragma unroll
+      for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+        for (int sn = 0; sn < 2; sn++)
+          acc[sm][sn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[sm][c]),
+                                                                __builtin_bit_cast(bf16x8, b[sn][c]), acc[sm][sn], 0,
+                                                                0, 0);
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < 2; kk++)
+#pragma unroll
+      for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+        for (int sn = 0; sn < 2; sn++) {
+          const u32x4 a0 = a[sm][2 * kk], a1 = a[sm][2 * kk + 1];
+          const u32x4 b0 = b[sn][2 * kk], b1 = b[sn][2 * kk + 1];
+          const i32x8 av = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3],
+                            (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+          const i32x8 bv = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3],
+                            (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+          // formats 0/0 = e4m3 for A and B; scale exponents 127 = 2^0
+          acc[sm][sn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[sm][sn], 0, 0, 0, 127, 0, 127);
+        }
+  }
+}
+
+struct GemmArgs {
+  const uint8_t* A;
+  const uint8_t* B;
+  int M, Nn;
+  int64_t lda, ldb;  // bytes
+  int nst;           // 128-byte K stages
+  const float* sa;
+  const float* sb;
+  float* out;
+  int64_t ldo;  // floats
+};
+
+// One 128 x 128 output tile (tm, tn). Uses `lds` (GEMM_LDS_BYTES) and block
+// barriers: every thread of the workgroup must call it with the same tile.
+// EPI_SIM_SYM (A == B, tm <= tn): also stores the mirrored tile C^T, so only
+// the upper triangle of tiles is computed.
+template <int MODE, int EPI>
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uint8_t* lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = tm * BM, n0 = tn * BN;
+
+  const uint8_t* pa[4];
+  const uint8_t* pb[4];
+  int ls[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int f = u * 256 + tid, row = f >> 3, c = f & 7;
+    pa[u] = g.A + (int64_t)min(m0 + row, g.M - 1) * g.lda + c * 16;
+    pb[u] = g.B + (int64_t)min(n0 + row, g.Nn - 1) * g.ldb + c * 16;
+    ls[u] = row * LDSR + c * 16;
+  }
+  u32x4 ra[4], rb[4];
+  auto gload = [&](int st) {
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      ra[u] = *(const u32x4*)(pa[u] + (int64_t)st * BKB);
+      rb[u] = *(const u32x4*)(pb[u] + (int64_t)st * BKB);
+    }
+  };
+  auto lstore = [&](int buf) {
+    uint8_t* base = lds + buf * 2 * TILEB;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      *(u32x4*)(base + ls[u]) = ra[u];
+      *(u32x4*)(base + TILEB + ls[u]) = rb[u];
+    }
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+    for (int sn = 0; sn < 2; sn++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[sm][sn][r] = 0.f;
+
+  const int fa = (wm * 64 + (lane & 31)) * LDSR + (lane >> 5) * 64;
+  const int fb = (wn * 64 + (lane & 31)) * LDSR + (lane >> 5) * 64;
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int st = 0; st < g.nst; st++) {
+    const int buf = st & 1;
+    if (st + 1 < g.nst) gload(st + 1);
+    const uint8_t* la = lds + buf * 2 * TILEB;
+    const uint8_t* lb = la + TILEB;
+    u32x4 a[2][4], b[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; s++)
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        a[s][c] = *(const u32x4*)(la + fa + s * 32 * LDSR + c * 16);
+        b[s][c] = *(const u32x4*)(lb + fb + s * 32 * LDSR + c * 16);
+      }
+    mfma_stage<MODE>(acc, a, b);
+    if (st + 1 < g.nst) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // 32x32 accumulator layout: register r of lane l holds
+  // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of its block.
+  const bool mirror = (EPI == EPI_SIM_SYM) && (tm != tn);
+  float* tr = (float*)lds;  // transposed staging, valid after the loop's last barrier
+#pragma unroll
+  for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+    for (int sn = 0; sn < 2; sn++) {
+      const int lc = wn * 64 + sn * 32 + (lane & 31);
+      const int col = n0 + lc;
+      const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int row = m0 + lr;
+        const float v = acc[sm][sn][r];
+        if (EPI == EPI_DIST) {
+          if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = 1.0f - g.sa[row] * scol * v;
+        } else {
+          const float s = (row < g.M && col < g.Nn) ? v * g.sa[row] * scol + 0.0f : 0.f;
+          if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = s;
+          if (mirror) tr[lc * TSTRIDE + lr] = s;
+        }
+      }
+    }
+  if (mirror) {
+    __syncthreads();
+    // rows n0.. of C^T: thread t writes columns t%128 of rows t/128, +2, ...
+    const int c = tid & 127;
+    for (int rr = tid >> 7; rr < BN; rr += 2) {
+      const int row = n0 + rr, col = m0 + c;
+      if (row < g.Nn && col < g.M) g.out[(int64_t)row * g.ldo + col] = tr[rr * TSTRIDE + c];
+    }
+  }
+  __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
+}
+
+// Upper-triangle tile t (0 <= t < T(T+1)/2) of a T x T tile grid, row-major
+// over tm: (0,0),(0,1)..(0,T-1),(1,1),...
+__device__ __forceinline__ void upper_tile(int t, int T, int& tm, int& tn) {
+  // rows before tm hold tm*T - tm*(tm-1)/2 tiles; invert with a float guess, then fix up
+  float b = 2.f * T + 1.f;
+  int m = (int)((b - __builtin_sqrtf(b * b - 8.f * (float)t)) * 0.5f);
+  if (m < 0) m = 0;
+  if (m > T - 1) m = T - 1;
+  auto first = [&](int mm) { return mm * T - mm * (mm - 1) / 2; };
+  while (m > 0 && first(m) > t) m--;
+  while (m + 1 < T && first(m + 1) <= t) m++;
+  tm = m;
+  tn = m + (t - first(m));
+}
+
+}  // namespace rr

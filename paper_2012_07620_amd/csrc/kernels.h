@@ -50,15 +50,14 @@ hipError_t launch_rescore(const float* xp, int64_t ldp, int d, const float* rn, 
 hipError_t launch_take_prefix(const int32_t* cand_idx, const float* cand_val, int n, int Kc, int k1,
                               int32_t* knn_idx, float* knn_val, hipStream_t s);
 
-// a4: zero an n x ld float buffer (fill kernel, usable under graph capture).
+// a4: zero a float range (fill kernel, usable under graph capture).
 hipError_t launch_fill_zero(float* buf, int64_t count, hipStream_t s);
-// a4: scatter A* = (A + A^T)/2 into a zeroed N x ldH buffer; count in-degrees
-// and mutual pairs (for the zero-layer norms).
-hipError_t launch_astar_scatter(const int32_t* knn_idx, int n, int k1, float* H, int64_t ldH, int32_t* indeg,
-                                int32_t* mutual, hipStream_t s);
-// sigma_i = 1 / |A*_i| from the counts.
-hipError_t launch_astar_sigma(const int32_t* indeg, const int32_t* mutual, int n, int k1, float* sigma,
-                              hipStream_t s);
+// a4: scatter A* = (A + A^T)/2 into a zeroed N x ldH buffer; cnt[0..n) counts
+// in-degrees and cnt[n..2n) mutual pairs (both zeroed beforehand).
+hipError_t launch_astar_scatter(const int32_t* knn_idx, int n, int k1, float* H, int64_t ldH, int32_t* cnt,
+                                hipStream_t s);
+// sigma_i = 1 / |A*_i| from the counts (zero-layer final product).
+hipError_t launch_astar_sigma(const int32_t* cnt, int n, int k1, float* sigma, hipStream_t s);
 
 // a5 + a6: one propagation layer (Eq. 14, sum aggregator) with lazy
 // normalisation: hout_i = sin_i*hin_i + sum_{r<k2} w_ir * sin_{j_r} * hin_{j_r},
@@ -74,6 +73,5 @@ hipError_t launch_split_bf16(const float* h, int n, int64_t ld, uint16_t* hi, ui
 // Copy helpers.
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t count, hipStream_t s);
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t count, hipStream_t s);
-hipError_t launch_fill_f32(float* dst, float v, int64_t count, hipStream_t s);
 
 }  // namespace rr

@@ -129,18 +129,14 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
   const float* csig;
   RR_STAGE(RERANK_STAGE_ADJACENCY, 0);
   if (P.node == RERANK_NODE_ADJ_SYM) {
-    int32_t* indeg = at<int32_t>(ws, P.o_indeg);
-    int32_t* mut = at<int32_t>(ws, P.o_mut);
+    int32_t* cnt = at<int32_t>(ws, P.o_cnt);
     RR_TRY(launch_fill_zero(A, (int64_t)P.n * P.ldN, s));
-    RR_TRY(launch_fill_zero((float*)indeg, P.n & ~3, s));
-    RR_TRY(launch_fill_f32((float*)indeg + (P.n & ~3), 0.f, P.n & 3, s));
-    RR_TRY(launch_fill_zero((float*)mut, P.n & ~3, s));
-    RR_TRY(launch_fill_f32((float*)mut + (P.n & ~3), 0.f, P.n & 3, s));
-    RR_TRY(launch_astar_scatter(ki, P.n, P.k1, A, P.ldN, indeg, mut, s));
+    RR_TRY(launch_fill_zero((float*)cnt, (int64_t)P.n * 2, s));
+    RR_TRY(launch_astar_scatter(ki, P.n, P.k1, A, P.ldN, cnt, s));
     cur = A;
     csig = nullptr;  // h^(0) is the raw A* row (not normalised)
     if (P.layers == 0) {
-      RR_TRY(launch_astar_sigma(indeg, mut, P.n, P.k1, sa, s));
+      RR_TRY(launch_astar_sigma(cnt, P.n, P.k1, sa, s));
       csig = sa;
     }
   } else {

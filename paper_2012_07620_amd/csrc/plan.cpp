@@ -79,8 +79,7 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o) {
     if (P.layers > 0) P.o_b = take(n * P.ldH * 4);
     P.o_sa = take(n * 4);
     P.o_sb = take(n * 4);
-    P.o_indeg = take(n * 4);
-    P.o_mut = take(n * 4);
+    P.o_cnt = take(n * 8);  // in-degree and mutual counts, 2n int32
     if (P.fprec == FinalPrec::BF16X3) {
       P.o_hi = take(n * P.ldH * 2);
       P.o_lo = take(n * P.ldH * 2);

@@ -1,0 +1,341 @@
+// Per-work-item bodies of the row-parallel kernels (a1, a3, a3b, a4, a6),
+// shared by the direct launches and the persistent grouped launches.
+#pragma once
+#include "common.h"
+#include "kernels.h"
+
+namespace rr {
+
+// ============================================================== a1: prep
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+
+// OCP FP8 E4M3 (bias 7, largest finite 448, no infinities): round to nearest
+// even, saturate at 448. Input finite.
+__device__ __forceinline__ uint32_t e4m3_rne_sat(float f) {
+  const uint32_t sign = (__float_as_uint(f) >> 24) & 0x80u;
+  const float a = fabsf(f);
+  uint32_t code;
+  if (a >= 448.0f) {
+    code = 0x7Eu;
+  } else if (a < 0.015625f) {  // below 2^-6: subnormal steps of 2^-9 (8 = smallest normal)
+    code = (uint32_t)__builtin_rintf(a * 512.0f);
+  } else {
+    uint32_t b = __float_as_uint(a);
+    b += 0x7FFFFu + ((b >> 20) & 1u);  // keep 3 mantissa bits
+    code = ((((b >> 23) - 127u + 7u)) << 3) | ((b >> 20) & 7u);
+    if (code > 0x7Eu) code = 0x7Eu;
+  }
+  return sign | code;
+}
+
+// One wavefront per row: exact FP32 copy (zero-padded to ldp), 1/|x_i| from a
+// compensated sum of squares with correctly rounded sqrt and division, and the
+// low-precision copy with its row scale.
+template <SimPrec P, bool IN_BF16>
+__device__ __forceinline__ void prep_row(const void* __restrict__ x, int i, int d, float* __restrict__ xp,
+                                         int64_t ldp, float* __restrict__ rn, void* __restrict__ xl, int64_t ldl,
+                                         float* __restrict__ sl) {
+  const int lane = threadIdx.x & 63;
+  const int64_t src = (int64_t)i * d;
+  float* xr = xp + (int64_t)i * ldp;
+  DF acc{0.f, 0.f};
+  float amax = 0.f;
+  for (int k = lane; k < ldp; k += 64) {
+    float v = 0.f;
+    if (k < d) {
+      if (IN_BF16)
+        v = __uint_as_float((uint32_t)((const uint16_t*)x)[src + k] << 16);
+      else
+        v = ((const float*)x)[src + k];
+    }
+    xr[k] = v;
+    dot2_acc(acc, v, v);
+    amax = fmaxf(amax, fabsf(v));
+  }
+  acc = wave_sum_df(acc);
+  const float n2 = acc.hi + acc.lo;
+  const float r = __fdiv_rn(1.0f, __fsqrt_rn(n2));
+  if (P == SimPrec::BF16) {
+    uint16_t* xb = (uint16_t*)xl + (int64_t)i * ldl;
+    for (int k = lane; k < ldl; k += 64) {
+      uint16_t b = 0;
+      if (k < d) b = IN_BF16 ? ((const uint16_t*)x)[src + k] : bf16_rne(xr[k]);
+      xb[k] = b;
+    }
+    if (lane == 0) sl[i] = r;
+  } else if (P == SimPrec::FP8) {
+    amax = wave_max_f32(amax);
+    const float scale = amax > 0.f ? amax / 448.0f : 1.0f;
+    const float inv = amax > 0.f ? 448.0f / amax : 1.0f;
+    uint8_t* xq = (uint8_t*)xl + (int64_t)i * ldl;
+    for (int k = lane; k < ldl; k += 64) xq[k] = (uint8_t)(k < d ? e4m3_rne_sat(xr[k] * inv) : 0u);
+    if (lane == 0) sl[i] = r * scale;
+  }
+  if (lane == 0) rn[i] = r;
+}
+
+// ============================================================== a3: top-k
+// One wavefront owns one row and streams it once from HBM in 1024-column
+// chunks (four coalesced 1 KB loads per lane-group). The wave keeps the K
+// best keys seen so far as a sorted list spread over its lanes (64*R keys,
+// R = 1, 2 or 4) and a running threshold tau = the K-th best key. Columns
+// whose key beats tau are appended to a 128-entry LDS ring; every 64 entries
+// the ring is bitonic-sorted and merged into the list, which raises tau.
+// The first chunk seeds the list with the per-lane maxima so the threshold
+// is tight from the start.
+//
+// Key = (order-preserving bits of S_ij) << 32 | ~j: one 64-bit compare gives
+// "similarity descending, column ascending" (the tie rule), -0.0 == +0.0.
+// The row's own column gets the largest key, so it is always member 0.
+template <int R>
+__device__ __forceinline__ void topk_row(const float* __restrict__ S, int64_t ldS, int N, int i, int K,
+                                         int32_t* __restrict__ oidx, float* __restrict__ oval, int ldo,
+                                         uint64_t* ring) {
+  const int lane = threadIdx.x & 63;
+  const float* srow = S + (int64_t)i * ldS;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+
+  uint64_t best[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) best[r] = 0;
+  uint64_t tau = 0;
+  int head = 0, cnt = 0;
+
+  constexpr int U = 4;
+  constexpr int CH = 64 * 4 * U;
+  for (int c0 = 0; c0 < N; c0 += CH) {
+    f32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int col = c0 + u * 256 + lane * 4;
+      v[u] = (col < N) ? *(const f32x4*)(srow + col) : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    uint64_t lm = 0;
+    if (c0 == 0) {
+#pragma unroll
+      for (int u = 0; u < U; u++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int col = u * 256 + lane * 4 + e;
+          if (col < N) lm = umax64(lm, col == i ? self_key(i) : sel_key(v[u][e], (uint32_t)col));
+        }
+      best[0] = lm;
+      wave_sort_desc<R>(best);
+      tau = wave_rank_key<R>(best, K - 1);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int col = c0 + u * 256 + lane * 4 + e;
+        uint64_t key = 0;
+        if (col < N) key = (col == i) ? self_key(i) : sel_key(v[u][e], (uint32_t)col);
+        const bool pass = key > tau && key != lm;
+        const uint64_t m = __ballot(pass);
+        if (m) {
+          if (pass) ring[(head + cnt + __popcll(m & below)) & 127] = key;
+          cnt += __popcll(m);
+          if (cnt >= 64) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            const uint64_t b = ring[(head + lane) & 127];
+            head = (head + 64) & 127;
+            cnt -= 64;
+            wave_merge_batch<R>(best, b);
+            tau = wave_rank_key<R>(best, K - 1);
+          }
+        }
+      }
+  }
+  if (cnt > 0) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint64_t b = lane < cnt ? ring[(head + lane) & 127] : 0ull;
+    wave_merge_batch<R>(best, b);
+  }
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int e = r * 64 + lane;
+    if (e < K) {
+      const uint32_t j = key_col(best[r]);
+      oidx[(int64_t)i * ldo + e] = (int32_t)j;
+      oval[(int64_t)i * ldo + e] = (j == (uint32_t)i) ? 1.0f : key_val(best[r]);
+    }
+  }
+}
+
+// ============================================================== a3b: re-score
+// Candidates of row i re-scored as cos(x_i, x_j) with a compensated FP32 dot
+// product (error about one rounding of the result, far below the spacing of
+// distinct similarities the tie rule has to resolve), then sorted under
+// (similarity desc, column asc) with the row itself first; the first k1 are
+// N(i, k1) of Eq. 8. One wavefront per row; 16 lanes per candidate, four
+// candidates at a time.
+template <int R>
+__device__ __forceinline__ void rescore_row(const float* __restrict__ xp, int64_t ldp, const float* __restrict__ rn,
+                                            int i, const int32_t* __restrict__ cand, int Kc, int k1,
+                                            int32_t* __restrict__ kidx, float* __restrict__ kval) {
+  const int lane = threadIdx.x & 63;
+  const int sub = lane >> 4, sl = lane & 15;
+  const float* xi = xp + (int64_t)i * ldp;
+  const float rni = rn[i];
+  uint64_t keys[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) keys[r] = 0;
+  for (int c0 = 0; c0 < Kc; c0 += 4) {
+    const int c = c0 + sub;
+    const int j = (c < Kc) ? cand[(int64_t)i * Kc + c] : i;
+    DF acc{0.f, 0.f};
+    if (j != i) {
+      const float* xj = xp + (int64_t)j * ldp;
+      for (int k = sl * 4; k < ldp; k += 64) {
+        const f32x4 a = *(const f32x4*)(xi + k);
+        const f32x4 b = *(const f32x4*)(xj + k);
+        dot2_acc(acc, a.x, b.x);
+        dot2_acc(acc, a.y, b.y);
+        dot2_acc(acc, a.z, b.z);
+        dot2_acc(acc, a.w, b.w);
+      }
+    }
+#pragma unroll
+    for (int m = 8; m > 0; m >>= 1) {
+      DF o{__shfl_xor(acc.hi, m, kWave), __shfl_xor(acc.lo, m, kWave)};
+      acc = df_add(acc, o);
+    }
+    const float dot = acc.hi + acc.lo;
+    const uint64_t key = (j == i) ? self_key((uint32_t)i) : sel_key((dot * rni) * rn[j], (uint32_t)j);
+    // candidate c0 + s is held by lane (c0 + s) % 64 of slot (c0 + s) / 64
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      const uint64_t ks = shfl_u64(key, s * 16);
+      const int cs = c0 + s;
+      if (cs < Kc) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          if ((cs >> 6) == r && lane == (cs & 63)) keys[r] = ks;
+      }
+    }
+  }
+  wave_sort_desc<R>(keys);
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int e = r * 64 + lane;
+    if (e < k1) {
+      const uint32_t j = key_col(keys[r]);
+      kidx[(int64_t)i * k1 + e] = (int32_t)j;
+      kval[(int64_t)i * k1 + e] = (j == (uint32_t)i) ? 1.0f : key_val(keys[r]);
+    }
+  }
+}
+
+// ============================================================== a4: A*
+// Zero a float range: 8 float4 per thread per item (one item = 8192 floats).
+constexpr int FILL_ITEM = 256 * 4 * 8;
+__device__ __forceinline__ void fill_item(float* __restrict__ p, int64_t count, int64_t item) {
+  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+  const int64_t base = item * FILL_ITEM;
+#pragma unroll
+  for (int u = 0; u < 8; u++) {
+    const int64_t at = base + (int64_t)(u * 256 + threadIdx.x) * 4;
+    if (at + 3 < count) {
+      *(f32x4*)(p + at) = z;
+    } else {
+      for (int e = 0; e < 4; e++)
+        if (at + e < count) p[at + e] = 0.f;
+    }
+  }
+}
+
+// H[i][j] = H[j][i] = A*_ij for every j in N(i, k1): 1 when i is also in
+// N(j, k1), else 1/2 (Eq. 10). When both directions exist both writers store
+// the same value, so plain stores suffice. cnt[0..n) counts in-degrees,
+// cnt[n..2n) mutual pairs per row.
+__device__ __forceinline__ void scatter_pair(const int32_t* __restrict__ knn, int n, int k1, float* __restrict__ H,
+                                             int64_t ldH, int32_t* __restrict__ cnt, int64_t t) {
+  if (t >= (int64_t)n * k1) return;
+  const int i = (int)(t / k1);
+  const int j = knn[t];
+  const int32_t* lj = knn + (int64_t)j * k1;
+  bool mut = false;
+  for (int s = 0; s < k1; s++) mut |= (lj[s] == i);
+  const float v = mut ? 1.0f : 0.5f;
+  H[(int64_t)i * ldH + j] = v;
+  H[(int64_t)j * ldH + i] = v;
+  atomicAdd(cnt + j, 1);
+  if (mut) atomicAdd(cnt + n + i, 1);
+}
+
+// |A*_i|^2 = (#mutual) * 1 + (#one-way) * 1/4, one-way = out-only + in-only.
+__device__ __forceinline__ void astar_sigma_row(const int32_t* __restrict__ cnt, int n, int k1, float* __restrict__ sigma,
+                                                int i) {
+  if (i >= n) return;
+  const int m = cnt[n + i];
+  const float sq = (float)m + 0.25f * (float)(k1 - m + cnt[i] - m);
+  sigma[i] = __fdiv_rn(1.0f, __fsqrt_rn(sq));
+}
+
+// ============================================================== a5 + a6
+// One workgroup per output row: gather the row itself and its k2 - 1 other
+// edge rows (Eq. 12: the first k2 members of N(i, k1), member 0 = i), sum
+// with weights (Eq. 14, sum aggregator), reduce the squared norm. Rows are
+// kept unnormalised and the norm is carried as sigma = 1/|u| (the next layer
+// and the final product fold it in), so each layer is one streaming pass.
+struct PropShared {
+  int nb[256];
+  float cf[256];
+  float red[4];
+};
+
+__device__ __forceinline__ void propagate_row(const float* __restrict__ hin, const float* __restrict__ sin,
+                                              int64_t ld, int64_t cols, const int32_t* __restrict__ knn,
+                                              const float* __restrict__ kv, int k1, int k2, int alpha,
+                                              float* __restrict__ hout, float* __restrict__ sout,
+                                              uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int i,
+                                              PropShared& sh) {
+  const int tid = threadIdx.x;
+  if (tid < k2) {
+    const int j = knn[(int64_t)i * k1 + tid];
+    float w = 1.0f;
+    if (tid > 0) {  // member 0 is the row itself with e_ii = 1
+      const float e = kv[(int64_t)i * k1 + tid];
+      for (int a = 0; a < alpha; a++) w *= e;
+    }
+    const float sj = sin ? sin[j] : 1.0f;
+    // member 0: residual h_i plus the self edge (weight 1)
+    sh.cf[tid] = (tid == 0) ? 2.0f * sj : w * sj;
+    sh.nb[tid] = j;
+  }
+  __syncthreads();
+  float ss = 0.f;
+  const int64_t c4 = cols >> 2;
+  for (int64_t c = tid; c < c4; c += 256) {
+    f32x4 acc = sh.cf[0] * ((const f32x4*)(hin + (int64_t)sh.nb[0] * ld))[c];
+    for (int r = 1; r < k2; r++) acc += sh.cf[r] * ((const f32x4*)(hin + (int64_t)sh.nb[r] * ld))[c];
+    ((f32x4*)(hout + (int64_t)i * ld))[c] = acc;
+    ss += acc.x * acc.x + acc.y * acc.y + acc.z * acc.z + acc.w * acc.w;
+    if (hi) {
+      uint16_t h4[4], l4[4];
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        h4[e] = bf16_rne(acc[e]);
+        l4[e] = bf16_rne(acc[e] - __uint_as_float((uint32_t)h4[e] << 16));
+      }
+      uint16_t* ph = hi + (int64_t)i * ld + c * 4;
+      uint16_t* pl = lo + (int64_t)i * ld + c * 4;
+      *(uint2*)ph = make_uint2(h4[0] | ((uint32_t)h4[1] << 16), h4[2] | ((uint32_t)h4[3] << 16));
+      *(uint2*)pl = make_uint2(l4[0] | ((uint32_t)l4[1] << 16), l4[2] | ((uint32_t)l4[3] << 16));
+    }
+  }
+  ss = wave_sum_f32(ss);
+  if ((tid & 63) == 0) sh.red[tid >> 6] = ss;
+  __syncthreads();
+  if (tid == 0) {
+    const float t = (sh.red[0] + sh.red[1]) + (sh.red[2] + sh.red[3]);
+    sout[i] = __fdiv_rn(1.0f, __fsqrt_rn(t));
+  }
+  __syncthreads();  // sh is reused by the next row of a persistent workgroup
+}
+
+}  // namespace rr

@@ -172,3 +172,29 @@ def request_specs(stream: StreamSpec, count: int, qps: float):
                            "bf16", int(stream.seed * 100003 + r))
         out.append((float(t[r]), spec))
     return out
+
+
+def make_features_device(spec: ProblemSpec, device, seed: Optional[int] = None):
+    """Same recipe as :func:`make_problem`, drawn with torch's generator on
+    ``device`` (fast; used for the many requests of a serving stream). Returns
+    the features as a contiguous (N, d) tensor in the spec's storage dtype."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(spec.seed if seed is None else seed))
+    d = spec.dim
+    n_dis = int(round(spec.distractor_frac * spec.n_gallery))
+    n_gal_ids = spec.n_gallery - n_dis
+
+    def unit(v):
+        return v / v.norm(dim=1, keepdim=True)
+
+    centres = unit(torch.randn(spec.n_ids, d, generator=g, device=device))
+    q_lab = torch.arange(spec.n_query, device=device) % spec.n_ids
+    g_lab = torch.arange(n_gal_ids, device=device) % spec.n_ids
+    q_lab = q_lab[torch.randperm(spec.n_query, generator=g, device=device)]
+    g_lab = g_lab[torch.randperm(n_gal_ids, generator=g, device=device)]
+    dis = unit(torch.randn(n_dis, d, generator=g, device=device)) if n_dis else torch.zeros(0, d, device=device)
+    gal = torch.cat([centres[g_lab], dis])[torch.randperm(spec.n_gallery, generator=g, device=device)]
+    base = torch.cat([centres[q_lab], gal])
+    x = unit(base + torch.randn(base.shape, generator=g, device=device) * (spec.sigma / d ** 0.5))
+    return (x.to(torch.bfloat16) if spec.dtype == "bf16" else x.float()).contiguous()

@@ -1,0 +1,153 @@
+"""Serving path: continuous batching with admission by working-set bytes.
+
+Each request's result must be the same alone (rerank_run) and in the mix
+(rerank_submit while other requests run or queue); failure handling is
+forced from the host (tiny budgets, cancellation, zero timeouts, an injected
+allocation failure). Every call goes through the C-ABI library."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import rerank_oracle as orc
+from paper_2012_07620_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(seed, count, n_lo, n_hi, dims=(64, 130, 512), dtype="f32"):
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        q = max(1, int(round(0.15 * n)))
+        d = int(dims[r % len(dims)])
+        spec = synth.ProblemSpec(f"r{r}", q, n - q, d, max(2, n // 20), 0.5, 0.05, 20, 6, 1, dtype, seed * 1000 + r)
+        out.append(synth.make_problem(spec))
+    return out
+
+
+def _dev(p):
+    import torch
+    if p.spec.dtype == "bf16":
+        return torch.from_numpy(p.x_bf16.view(np.int16)).cuda().view(torch.bfloat16)
+    return torch.from_numpy(p.x32).cuda()
+
+
+def _solo(probs, prec="f32"):
+    import torch
+    from paper_2012_07620_amd import binding
+    ctx = binding.Context(0)
+    outs = []
+    for p in probs:
+        s = p.spec
+        outs.append(binding.run(_dev(p), s.n_query, s.k1, s.k2, s.layers, sim_prec=prec, ctx=ctx).cpu().numpy())
+    torch.cuda.synchronize()
+    ctx.close()
+    return outs
+
+
+def _serve(ctx, probs, prec="f32"):
+    import torch
+    from paper_2012_07620_amd import binding
+    xs = [_dev(p) for p in probs]
+    outs = [torch.full((p.spec.n_query, p.spec.n_gallery), float("nan"), device="cuda") for p in probs]
+    torch.cuda.synchronize()
+    tickets = []
+    for p, x, o in zip(probs, xs, outs):
+        s = p.spec
+        tickets.append(binding.submit(ctx, x, o, s.n_query, s.k1, s.k2, s.layers, sim_prec=prec))
+    return xs, outs, tickets
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_results_same_alone_and_in_the_mix(gpu_lib, prec):
+    from paper_2012_07620_amd import binding
+    probs = _requests(11, 14, 300, 3000) + _requests(12, 3, 9000, 12000, dims=(512,))
+    rng = np.random.default_rng(3)
+    probs = [probs[i] for i in rng.permutation(len(probs))]
+    print(f"case mix prec={prec} n={[p.spec.n for p in probs]}", flush=True)
+    solo = _solo(probs, prec)
+    ctx = binding.Context(0)
+    xs, outs, tickets = _serve(ctx, probs, prec)
+    lat = [binding.wait(ctx, t) for t in tickets]
+    for p, o, ref in zip(probs, outs, solo):
+        got = o.cpu().numpy()
+        assert np.array_equal(got, ref), f"{p.spec.name} differs alone vs in the mix (max {np.abs(got - ref).max()})"
+    print(f"latency ms: p50 {np.percentile(lat, 50):.2f} max {max(lat):.2f}")
+    # the mix is also right: two requests against the FP64 oracle
+    for p, o in list(zip(probs, outs))[:2]:
+        s = p.spec
+        ref = orc.rerank(p.x32, s.n_query, s.k1, s.k2, s.layers)
+        assert np.abs(o.cpu().numpy() - ref.dist).max() <= (1e-4 if prec == "f32" else 2e-2)
+    ctx.close()
+
+
+def test_admission_waits_for_memory(gpu_lib):
+    from paper_2012_07620_amd import binding
+    probs = _requests(21, 6, 5000, 7000, dims=(128,))
+    need = max(binding.workspace_bytes(binding.make_params(p.spec.n, p.spec.n_query, p.spec.dim, 20, 6, 1))
+               for p in probs)
+    solo = _solo(probs)
+    ctx = binding.Context(0, budget_bytes=int(need * 1.3))  # one request at a time fits
+    xs, outs, tickets = _serve(ctx, probs)
+    for t in tickets:
+        binding.wait(ctx, t)
+    for o, ref in zip(outs, solo):
+        assert np.array_equal(o.cpu().numpy(), ref)
+    ctx.close()
+
+
+def test_request_larger_than_budget_is_rejected(gpu_lib):
+    import torch
+    from paper_2012_07620_amd import binding
+    ctx = binding.Context(0, budget_bytes=64 << 20)
+    x = torch.randn(6000, 64, device="cuda")
+    out = torch.empty(900, 5100, device="cuda")
+    with pytest.raises(binding.RerankError) as ei:
+        binding.submit(ctx, x, out, 900, 20, 6, 1)
+    assert ei.value.status == binding.E_NOMEM
+    ctx.close()
+
+
+def test_cancel_pending_and_wait_timeout(gpu_lib):
+    from paper_2012_07620_amd import binding
+    probs = _requests(31, 4, 6000, 6000, dims=(256,))
+    need = binding.workspace_bytes(binding.make_params(6000, 900, 256, 20, 6, 1))
+    ctx = binding.Context(0, budget_bytes=int(need * 1.2))
+    xs, outs, tickets = _serve(ctx, probs)
+    binding.cancel(ctx, tickets[-1])  # still queued behind the others
+    with pytest.raises(binding.RerankError) as ei:
+        binding.wait(ctx, tickets[-1])
+    assert ei.value.status == binding.E_CANCELLED
+    with pytest.raises(binding.RerankError) as ei:
+        binding.wait(ctx, tickets[-2], timeout_us=0)
+    assert ei.value.status == binding.E_TIMEOUT
+    for t in tickets[:-1]:
+        binding.wait(ctx, t)
+    assert np.isnan(outs[-1].cpu().numpy()).all()  # cancelled work never ran
+    ctx.close()
+
+
+def test_injected_allocation_failure_fails_one_request(gpu_lib):
+    from paper_2012_07620_amd import binding
+    probs = _requests(41, 5, 9000, 10000, dims=(64,))  # large: one allocation each, in order
+    solo = _solo(probs)
+    os.environ["RERANK_FAULT"] = "alloc:3"
+    try:
+        ctx = binding.Context(0)
+        xs, outs, tickets = _serve(ctx, probs)
+    finally:
+        del os.environ["RERANK_FAULT"]
+    statuses = []
+    for t in tickets:
+        try:
+            binding.wait(ctx, t)
+            statuses.append(binding.OK)
+        except binding.RerankError as e:
+            statuses.append(e.status)
+    assert statuses.count(binding.E_NOMEM) == 1 and statuses[2] == binding.E_NOMEM
+    for st, o, ref in zip(statuses, outs, solo):
+        if st == binding.OK:
+            assert np.array_equal(o.cpu().numpy(), ref)
+    ctx.close()
