@@ -39,7 +39,7 @@ def stage_work(spec, prec: str):
     k1, k2, L = spec.k1, spec.k2, spec.layers
     kc = min(k1 + {"f32": 8, "bf16": 16, "fp8": 32}[prec], n, 256)
     return {
-        "similarity": ("flop", 2.0 * n * n * d),
+        "similarity": ("flop", 1.0 * n * (n + 1) * d),  # unique entries of the symmetric S
         "topk": ("byte", 4.0 * n * n),
         "rescore": ("flop", 2.0 * n * kc * d),
         "adjacency": ("byte", 4.0 * n * n),
