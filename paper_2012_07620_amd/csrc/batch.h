@@ -22,6 +22,9 @@ enum GStage : int {
   GS_SIGMA,      // 256 rows per item (zero-layer norms)
   GS_PROP,       // one row per item (per layer)
   GS_FINAL,      // one 128x128 distance tile per item
+  GS_MUTUAL,     // 256 (i, r) pairs per item (sparse first layer)
+  GS_SCAN,       // one item per problem
+  GS_CSR,        // 256 (i, r) pairs per item
   GS_COUNT
 };
 
@@ -44,6 +47,9 @@ struct ProbDesc {
   float* sa;
   float* sb;
   int32_t* cnt;
+  uint8_t* mflag;  // sparse first layer (A* mode, layers >= 1), else null
+  int32_t* off;
+  int32_t* inl;
 };
 
 struct BatchTable {

@@ -102,6 +102,62 @@ hipError_t launch_propagate(const float* hin, const float* sin, int n, int64_t l
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- sparse first layer
+__global__ void mutual_kernel(const int32_t* __restrict__ knn, int n, int k1, uint8_t* __restrict__ mflag,
+                              int32_t* __restrict__ innm) {
+  mutual_pair(knn, n, k1, mflag, innm, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+hipError_t launch_mutual(const int32_t* knn_idx, int n, int k1, uint8_t* mflag, int32_t* innm, hipStream_t s) {
+  const int64_t total = (int64_t)n * k1;
+  hipLaunchKernelGGL(mutual_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, knn_idx, n, k1, mflag,
+                     innm);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void scan_kernel(const int32_t* __restrict__ innm, int n, int32_t* __restrict__ off) {
+  __shared__ int32_t sh[256];
+  scan_offsets(innm, n, off, sh);
+}
+
+hipError_t launch_scan(const int32_t* innm, int n, int32_t* off, hipStream_t s) {
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(256), 0, s, innm, n, off);
+  return hipGetLastError();
+}
+
+__global__ void csr_kernel(const int32_t* __restrict__ knn, int n, int k1, const uint8_t* __restrict__ mflag,
+                           const int32_t* __restrict__ off, int32_t* __restrict__ cursor, int32_t* __restrict__ inl) {
+  csr_pair(knn, n, k1, mflag, off, cursor, inl, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+hipError_t launch_csr(const int32_t* knn_idx, int n, int k1, const uint8_t* mflag, const int32_t* off,
+                      int32_t* cursor, int32_t* inl, hipStream_t s) {
+  const int64_t total = (int64_t)n * k1;
+  hipLaunchKernelGGL(csr_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, knn_idx, n, k1, mflag, off,
+                     cursor, inl);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void first_layer_kernel(const int32_t* __restrict__ knn, const float* __restrict__ kv,
+                                                          const uint8_t* __restrict__ mflag,
+                                                          const int32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ inl, int k1, int k2, int alpha,
+                                                          int64_t ld, float* __restrict__ hout,
+                                                          float* __restrict__ sout, uint16_t* __restrict__ hi,
+                                                          uint16_t* __restrict__ lo) {
+  __shared__ FirstShared sh;
+  first_layer_row(knn, kv, mflag, off, inl, k1, k2, alpha, ld, hout, sout, hi, lo, blockIdx.x, sh);
+}
+
+hipError_t launch_first_layer(const int32_t* knn_idx, const float* knn_val, const uint8_t* mflag,
+                              const int32_t* off, const int32_t* inl, int n, int k1, int k2, int alpha, int64_t ld,
+                              float* hout, float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s) {
+  if (k2 < 1 || k2 > 256 || (ld & 3)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(first_layer_kernel, dim3(n), dim3(256), 0, s, knn_idx, knn_val, mflag, off, inl, k1, k2, alpha,
+                     ld, hout, sout, hi, lo);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- helpers
 static unsigned grid_for(int64_t n, int per_thread) {
   int64_t g = (n / per_thread + 255) / 256;

@@ -98,6 +98,41 @@ __global__ __launch_bounds__(256) void g_scatter(const BatchTable* __restrict__ 
   }
 }
 
+__global__ __launch_bounds__(256) void g_mutual(const BatchTable* __restrict__ t) {
+  FOR_ITEMS(GS_MUTUAL) {
+    const int p = find_prob(t, GS_MUTUAL, item);
+    const ProbDesc& D = t->p[p];
+    mutual_pair(D.ki, D.n, D.k1, D.mflag, D.cnt, (int64_t)(item - t->start[GS_MUTUAL][p]) * 256 + threadIdx.x);
+  }
+}
+
+__global__ __launch_bounds__(256) void g_scan(const BatchTable* __restrict__ t) {
+  __shared__ int32_t sh[256];
+  FOR_ITEMS(GS_SCAN) {
+    const ProbDesc& D = t->p[find_prob(t, GS_SCAN, item)];
+    scan_offsets(D.cnt, D.n, D.off, sh);
+  }
+}
+
+__global__ __launch_bounds__(256) void g_csr(const BatchTable* __restrict__ t) {
+  FOR_ITEMS(GS_CSR) {
+    const int p = find_prob(t, GS_CSR, item);
+    const ProbDesc& D = t->p[p];
+    csr_pair(D.ki, D.n, D.k1, D.mflag, D.off, D.cnt + D.n, D.inl,
+             (int64_t)(item - t->start[GS_CSR][p]) * 256 + threadIdx.x);
+  }
+}
+
+__global__ __launch_bounds__(256) void g_first(const BatchTable* __restrict__ t) {
+  __shared__ FirstShared sh;
+  FOR_ITEMS(GS_PROP) {
+    const int p = find_prob(t, GS_PROP, item);
+    const ProbDesc& D = t->p[p];
+    first_layer_row(D.ki, D.kv, D.mflag, D.off, D.inl, D.k1, D.k2, D.alpha, D.ldN, D.B, D.sa, nullptr, nullptr,
+                    item - t->start[GS_PROP][p], sh);
+  }
+}
+
 __global__ __launch_bounds__(256) void g_sigma(const BatchTable* __restrict__ t) {
   FOR_ITEMS(GS_SIGMA) {
     const int p = find_prob(t, GS_SIGMA, item);
@@ -206,12 +241,21 @@ hipError_t enqueue_grouped(const BatchKey& key, const BatchTable* d_tab, hipStre
       GTRY(go(g_rescore<4>, kGroupedRowWGs, s, d_tab));
       break;
   }
+  int first = 0;
   if (key.node == RERANK_NODE_ADJ_SYM) {
-    GTRY(go(g_fill, kGroupedRowWGs, s, d_tab));
-    GTRY(go(g_scatter, kGroupedRowWGs, s, d_tab));
-    if (key.layers == 0) GTRY(go(g_sigma, 256, s, d_tab));
+    GTRY(go(g_fill, kGroupedRowWGs, s, d_tab));  // counts (and A* when layers == 0)
+    if (key.layers == 0) {
+      GTRY(go(g_scatter, kGroupedRowWGs, s, d_tab));
+      GTRY(go(g_sigma, 256, s, d_tab));
+    } else {
+      GTRY(go(g_mutual, kGroupedRowWGs, s, d_tab));
+      GTRY(go(g_scan, kMaxBatch, s, d_tab));
+      GTRY(go(g_csr, kGroupedRowWGs, s, d_tab));
+      GTRY(go(g_first, kGroupedRowWGs, s, d_tab));
+      first = 1;
+    }
   }
-  for (int l = 0; l < key.layers; l++) GTRY(go(g_prop, kGroupedRowWGs, s, d_tab, l));
+  for (int l = first; l < key.layers; l++) GTRY(go(g_prop, kGroupedRowWGs, s, d_tab, l));
   GTRY(go(g_final, kGroupedGemmWGs, s, d_tab));
   return hipSuccess;
 }

@@ -67,6 +67,18 @@ hipError_t launch_astar_sigma(const int32_t* cnt, int n, int k1, float* sigma, h
 hipError_t launch_propagate(const float* hin, const float* sin, int n, int64_t ld, int64_t cols,
                             const int32_t* knn_idx, const float* knn_val, int k1, int k2, int alpha,
                             float* hout, float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s);
+// Sparse first layer (A* never stored densely when layers >= 1):
+// mutual flags of every (i, r) pair and non-mutual in-degree counts ...
+hipError_t launch_mutual(const int32_t* knn_idx, int n, int k1, uint8_t* mflag, int32_t* innm, hipStream_t s);
+// ... exclusive prefix sum of the counts (off has n + 1 entries) ...
+hipError_t launch_scan(const int32_t* innm, int n, int32_t* off, hipStream_t s);
+// ... CSR transpose of the non-mutual edges (cursor zeroed beforehand) ...
+hipError_t launch_csr(const int32_t* knn_idx, int n, int k1, const uint8_t* mflag, const int32_t* off,
+                      int32_t* cursor, int32_t* inl, hipStream_t s);
+// ... and layer 1 built from the sparse A* rows (same result as the dense layer).
+hipError_t launch_first_layer(const int32_t* knn_idx, const float* knn_val, const uint8_t* mflag,
+                              const int32_t* off, const int32_t* inl, int n, int k1, int k2, int alpha, int64_t ld,
+                              float* hout, float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s);
 // Split rows of an FP32 matrix into bf16 high/low parts (for L = 0 or raw).
 hipError_t launch_split_bf16(const float* h, int n, int64_t ld, uint16_t* hi, uint16_t* lo, hipStream_t s);
 

@@ -128,24 +128,41 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
   const float* cur;
   const float* csig;
   RR_STAGE(RERANK_STAGE_ADJACENCY, 0);
+  int first = 0;  // layers already done
   if (P.node == RERANK_NODE_ADJ_SYM) {
     int32_t* cnt = at<int32_t>(ws, P.o_cnt);
-    RR_TRY(launch_fill_zero(A, (int64_t)P.n * P.ldN, s));
     RR_TRY(launch_fill_zero((float*)cnt, (int64_t)P.n * 2, s));
-    RR_TRY(launch_astar_scatter(ki, P.n, P.k1, A, P.ldN, cnt, s));
-    cur = A;
-    csig = nullptr;  // h^(0) is the raw A* row (not normalised)
-    if (P.layers == 0) {
-      RR_TRY(launch_astar_sigma(cnt, P.n, P.k1, sa, s));
+    if (P.sparse_first) {
+      uint8_t* mflag = at<uint8_t>(ws, P.o_mflag);
+      int32_t* off = at<int32_t>(ws, P.o_off);
+      int32_t* inl = at<int32_t>(ws, P.o_inl);
+      RR_TRY(launch_mutual(ki, P.n, P.k1, mflag, cnt, s));
+      RR_TRY(launch_scan(cnt, P.n, off, s));
+      RR_TRY(launch_csr(ki, P.n, P.k1, mflag, off, cnt + P.n, inl, s));
+      RR_STAGE(RERANK_STAGE_ADJACENCY, 1);
+      RR_STAGE(RERANK_STAGE_PROPAGATE, 0);
+      const bool last = (P.layers == 1);
+      RR_TRY(launch_first_layer(ki, kv, mflag, off, inl, P.n, P.k1, P.k2, P.alpha, P.ldN, B, sa,
+                                last ? hi : nullptr, last ? lo : nullptr, s));
+      cur = B;
       csig = sa;
+      first = 1;
+    } else {
+      RR_TRY(launch_fill_zero(A, (int64_t)P.n * P.ldN, s));
+      RR_TRY(launch_astar_scatter(ki, P.n, P.k1, A, P.ldN, cnt, s));
+      RR_TRY(launch_astar_sigma(cnt, P.n, P.k1, sa, s));  // layers == 0 here
+      cur = A;
+      csig = sa;
+      RR_STAGE(RERANK_STAGE_ADJACENCY, 1);
+      RR_STAGE(RERANK_STAGE_PROPAGATE, 0);
     }
   } else {
     cur = xp;  // raw features, zero-padded to ldp
     csig = (P.layers == 0) ? rn : nullptr;
+    RR_STAGE(RERANK_STAGE_ADJACENCY, 1);
+    RR_STAGE(RERANK_STAGE_PROPAGATE, 0);
   }
-  RR_STAGE(RERANK_STAGE_ADJACENCY, 1);
-  RR_STAGE(RERANK_STAGE_PROPAGATE, 0);
-  for (int l = 0; l < P.layers; l++) {
+  for (int l = first; l < P.layers; l++) {
     float* out = (cur == A) ? B : A;
     float* osig = (csig == sa) ? sb : sa;
     const bool last = (l == P.layers - 1);

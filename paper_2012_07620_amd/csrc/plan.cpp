@@ -79,7 +79,13 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o) {
     if (P.layers > 0) P.o_b = take(n * P.ldH * 4);
     P.o_sa = take(n * 4);
     P.o_sb = take(n * 4);
-    P.o_cnt = take(n * 8);  // in-degree and mutual counts, 2n int32
+    P.o_cnt = take(n * 8);  // in-degree and mutual counts (or in-degree and cursor), 2n int32
+    P.sparse_first = (P.node == RERANK_NODE_ADJ_SYM && P.layers > 0);
+    if (P.sparse_first) {
+      P.o_mflag = take(n * P.k1);
+      P.o_off = take((n + 1) * 4);
+      P.o_inl = take(n * P.k1 * 4);
+    }
     if (P.fprec == FinalPrec::BF16X3) {
       P.o_hi = take(n * P.ldH * 2);
       P.o_lo = take(n * P.ldH * 2);

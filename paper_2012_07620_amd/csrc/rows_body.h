@@ -4,6 +4,11 @@
 #include "common.h"
 #include "kernels.h"
 
+// Every multiply-add below is written out (explicit FMA or separate
+// operations) so that the direct and grouped launches, and the dense and
+// sparse first layer, round identically.
+#pragma clang fp contract(off)
+
 namespace rr {
 
 // ============================================================== a1: prep
@@ -288,12 +293,30 @@ struct PropShared {
   float red[4];
 };
 
-__device__ __forceinline__ void propagate_row(const float* __restrict__ hin, const float* __restrict__ sin,
-                                              int64_t ld, int64_t cols, const int32_t* __restrict__ knn,
-                                              const float* __restrict__ kv, int k1, int k2, int alpha,
-                                              float* __restrict__ hout, float* __restrict__ sout,
-                                              uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int i,
-                                              PropShared& sh) {
+__device__ __forceinline__ float sq_acc4(float ss, f32x4 a) {
+  ss = __builtin_fmaf(a.x, a.x, ss);
+  ss = __builtin_fmaf(a.y, a.y, ss);
+  ss = __builtin_fmaf(a.z, a.z, ss);
+  return __builtin_fmaf(a.w, a.w, ss);
+}
+
+__device__ __forceinline__ void split_store4(uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int64_t at,
+                                             f32x4 acc) {
+  uint16_t h4[4], l4[4];
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    h4[e] = bf16_rne(acc[e]);
+    l4[e] = bf16_rne(acc[e] - __uint_as_float((uint32_t)h4[e] << 16));
+  }
+  *(uint2*)(hi + at) = make_uint2(h4[0] | ((uint32_t)h4[1] << 16), h4[2] | ((uint32_t)h4[3] << 16));
+  *(uint2*)(lo + at) = make_uint2(l4[0] | ((uint32_t)l4[1] << 16), l4[2] | ((uint32_t)l4[3] << 16));
+}
+
+// Coefficients of row i: member 0 (the row itself) gets residual + self edge,
+// members r > 0 get e_ir^alpha; each times the carried 1/|u_j| of the input.
+__device__ __forceinline__ void load_coefs(const float* __restrict__ sin, const int32_t* __restrict__ knn,
+                                           const float* __restrict__ kv, int k1, int k2, int alpha, int i,
+                                           PropShared& sh) {
   const int tid = threadIdx.x;
   if (tid < k2) {
     const int j = knn[(int64_t)i * k1 + tid];
@@ -303,31 +326,14 @@ __device__ __forceinline__ void propagate_row(const float* __restrict__ hin, con
       for (int a = 0; a < alpha; a++) w *= e;
     }
     const float sj = sin ? sin[j] : 1.0f;
-    // member 0: residual h_i plus the self edge (weight 1)
     sh.cf[tid] = (tid == 0) ? 2.0f * sj : w * sj;
     sh.nb[tid] = j;
   }
   __syncthreads();
-  float ss = 0.f;
-  const int64_t c4 = cols >> 2;
-  for (int64_t c = tid; c < c4; c += 256) {
-    f32x4 acc = sh.cf[0] * ((const f32x4*)(hin + (int64_t)sh.nb[0] * ld))[c];
-    for (int r = 1; r < k2; r++) acc += sh.cf[r] * ((const f32x4*)(hin + (int64_t)sh.nb[r] * ld))[c];
-    ((f32x4*)(hout + (int64_t)i * ld))[c] = acc;
-    ss += acc.x * acc.x + acc.y * acc.y + acc.z * acc.z + acc.w * acc.w;
-    if (hi) {
-      uint16_t h4[4], l4[4];
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        h4[e] = bf16_rne(acc[e]);
-        l4[e] = bf16_rne(acc[e] - __uint_as_float((uint32_t)h4[e] << 16));
-      }
-      uint16_t* ph = hi + (int64_t)i * ld + c * 4;
-      uint16_t* pl = lo + (int64_t)i * ld + c * 4;
-      *(uint2*)ph = make_uint2(h4[0] | ((uint32_t)h4[1] << 16), h4[2] | ((uint32_t)h4[3] << 16));
-      *(uint2*)pl = make_uint2(l4[0] | ((uint32_t)l4[1] << 16), l4[2] | ((uint32_t)l4[3] << 16));
-    }
-  }
+}
+
+__device__ __forceinline__ void finish_norm(float ss, float* __restrict__ sout, int i, PropShared& sh) {
+  const int tid = threadIdx.x;
   ss = wave_sum_f32(ss);
   if ((tid & 63) == 0) sh.red[tid >> 6] = ss;
   __syncthreads();
@@ -336,6 +342,144 @@ __device__ __forceinline__ void propagate_row(const float* __restrict__ hin, con
     sout[i] = __fdiv_rn(1.0f, __fsqrt_rn(t));
   }
   __syncthreads();  // sh is reused by the next row of a persistent workgroup
+}
+
+// One workgroup per output row: gather the row itself and its k2 - 1 other
+// edge rows (Eq. 12: the first k2 members of N(i, k1), member 0 = i), sum
+// with weights (Eq. 14, sum aggregator), reduce the squared norm. Rows are
+// kept unnormalised and the norm is carried as sigma = 1/|u| (the next layer
+// and the final product fold it in), so each layer is one streaming pass.
+// Thread t owns float4 columns t, t + 256, ... (the sparse first layer below
+// uses the same order, so both give identical sums).
+__device__ __forceinline__ void propagate_row(const float* __restrict__ hin, const float* __restrict__ sin,
+                                              int64_t ld, int64_t cols, const int32_t* __restrict__ knn,
+                                              const float* __restrict__ kv, int k1, int k2, int alpha,
+                                              float* __restrict__ hout, float* __restrict__ sout,
+                                              uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int i,
+                                              PropShared& sh) {
+  const int tid = threadIdx.x;
+  load_coefs(sin, knn, kv, k1, k2, alpha, i, sh);
+  float ss = 0.f;
+  const int64_t c4 = cols >> 2;
+  for (int64_t c = tid; c < c4; c += 256) {
+    const f32x4 v0 = ((const f32x4*)(hin + (int64_t)sh.nb[0] * ld))[c];
+    f32x4 acc = {sh.cf[0] * v0.x, sh.cf[0] * v0.y, sh.cf[0] * v0.z, sh.cf[0] * v0.w};
+    for (int r = 1; r < k2; r++) {
+      const f32x4 v = ((const f32x4*)(hin + (int64_t)sh.nb[r] * ld))[c];
+      const float w = sh.cf[r];
+      acc = f32x4{__builtin_fmaf(w, v.x, acc.x), __builtin_fmaf(w, v.y, acc.y), __builtin_fmaf(w, v.z, acc.z),
+                  __builtin_fmaf(w, v.w, acc.w)};
+    }
+    ((f32x4*)(hout + (int64_t)i * ld))[c] = acc;
+    ss = sq_acc4(ss, acc);
+    if (hi) split_store4(hi, lo, (int64_t)i * ld + c * 4, acc);
+  }
+  finish_norm(ss, sout, i, sh);
+}
+
+// ---------------------------------------------------------------- sparse A*
+// A* row j has its out-list N(j, k1) (value 1 when mutual, else 1/2) and its
+// non-mutual in-edges (rows m with j in N(m, k1) but m not in N(j, k1), value
+// 1/2). mflag[m][r] marks whether the pair (m, N(m,k1)[r]) is mutual; the
+// non-mutual in-edges of every row are gathered into a CSR transpose.
+
+// Mutual flag of pair t = (m, r), and the non-mutual in-degree count.
+__device__ __forceinline__ void mutual_pair(const int32_t* __restrict__ knn, int n, int k1, uint8_t* __restrict__ mflag,
+                                            int32_t* __restrict__ innm, int64_t t) {
+  if (t >= (int64_t)n * k1) return;
+  const int m = (int)(t / k1);
+  const int j = knn[t];
+  const int32_t* lj = knn + (int64_t)j * k1;
+  bool mut = false;
+  for (int s = 0; s < k1; s++) mut |= (lj[s] == m);
+  mflag[t] = mut ? 1 : 0;
+  if (!mut) atomicAdd(innm + j, 1);
+}
+
+// Exclusive prefix sum of innm[0..n) into off[0..n], one 256-thread workgroup.
+__device__ __forceinline__ void scan_offsets(const int32_t* __restrict__ innm, int n, int32_t* __restrict__ off,
+                                             int32_t* sh /* 256 ints */) {
+  const int tid = threadIdx.x;
+  const int per = (n + 255) / 256;
+  const int b = tid * per, e = min(n, b + per);
+  int sum = 0;
+  for (int k = b; k < e; k++) sum += innm[k];
+  sh[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int v = tid >= o ? sh[tid - o] : 0;
+    __syncthreads();
+    sh[tid] += v;
+    __syncthreads();
+  }
+  int run = sh[tid] - sum;
+  for (int k = b; k < e; k++) {
+    off[k] = run;
+    run += innm[k];
+  }
+  if (tid == 255) off[n] = sh[255];
+  __syncthreads();
+}
+
+// Place the non-mutual in-edge (m -> j) of pair t into j's CSR segment.
+__device__ __forceinline__ void csr_pair(const int32_t* __restrict__ knn, int n, int k1,
+                                         const uint8_t* __restrict__ mflag, const int32_t* __restrict__ off,
+                                         int32_t* __restrict__ cursor, int32_t* __restrict__ inl, int64_t t) {
+  if (t >= (int64_t)n * k1 || mflag[t]) return;
+  const int j = knn[t];
+  const int pos = atomicAdd(cursor + j, 1);
+  inl[off[j] + pos] = (int)(t / k1);
+}
+
+// First layer without a dense h^(0): u_i = sum_r c_r A*_{j_r}, built in LDS
+// one column chunk at a time from the sparse A* rows, in member order r, with
+// the same FMA sequence and per-thread column order as propagate_row on a
+// dense A* (so the result is identical), then written once.
+constexpr int FIRST_CHUNK = 8192;  // floats of the output row held in LDS
+struct FirstShared {
+  PropShared p;
+  float row[FIRST_CHUNK];
+};
+
+__device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn, const float* __restrict__ kv,
+                                                const uint8_t* __restrict__ mflag, const int32_t* __restrict__ off,
+                                                const int32_t* __restrict__ inl, int k1, int k2, int alpha,
+                                                int64_t ld, float* __restrict__ hout, float* __restrict__ sout,
+                                                uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int i,
+                                                FirstShared& sh) {
+  const int tid = threadIdx.x;
+  load_coefs(nullptr, knn, kv, k1, k2, alpha, i, sh.p);
+  float ss = 0.f;
+  for (int64_t c0 = 0; c0 < ld; c0 += FIRST_CHUNK) {
+    const int width = (int)min((int64_t)FIRST_CHUNK, ld - c0);
+    for (int k = tid; k < FIRST_CHUNK; k += 256) sh.row[k] = 0.f;
+    __syncthreads();
+    for (int r = 0; r < k2; r++) {
+      const int j = sh.p.nb[r];
+      const float c = sh.p.cf[r];
+      const int32_t* lj = knn + (int64_t)j * k1;
+      const uint8_t* fj = mflag + (int64_t)j * k1;
+      for (int s = tid; s < k1; s += 256) {
+        const int64_t m = lj[s] - c0;
+        if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, fj[s] ? 1.0f : 0.5f, sh.row[m]);
+      }
+      const int b = off[j], e = off[j + 1];
+      for (int s = b + tid; s < e; s += 256) {
+        const int64_t m = inl[s] - c0;
+        if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, 0.5f, sh.row[m]);
+      }
+      __syncthreads();
+    }
+    const int w4 = width >> 2;
+    for (int c = tid; c < w4; c += 256) {
+      const f32x4 acc = ((const f32x4*)sh.row)[c];
+      ((f32x4*)(hout + (int64_t)i * ld + c0))[c] = acc;
+      ss = sq_acc4(ss, acc);
+      if (hi) split_store4(hi, lo, (int64_t)i * ld + c0 + c * 4, acc);
+    }
+    __syncthreads();
+  }
+  finish_norm(ss, sout, i, sh.p);
 }
 
 }  // namespace rr

@@ -318,7 +318,7 @@ class Server {
     D.ldl = P.ldl;
     D.ldN = P.ldN;
     D.ldH = P.ldH;
-    D.fill_items_a = ((int64_t)P.n * P.ldN + FILL_ITEM_HOST - 1) / FILL_ITEM_HOST;
+    D.fill_items_a = P.sparse_first ? 0 : ((int64_t)P.n * P.ldN + FILL_ITEM_HOST - 1) / FILL_ITEM_HOST;
     D.x = r.x;
     D.dist = r.dist;
     D.xp = (float*)(ws + P.o_xp);
@@ -334,6 +334,9 @@ class Server {
     D.sa = (float*)(ws + P.o_sa);
     D.sb = (float*)(ws + P.o_sb);
     D.cnt = (int32_t*)(ws + P.o_cnt);
+    D.mflag = P.sparse_first ? (uint8_t*)(ws + P.o_mflag) : nullptr;
+    D.off = P.sparse_first ? (int32_t*)(ws + P.o_off) : nullptr;
+    D.inl = P.sparse_first ? (int32_t*)(ws + P.o_inl) : nullptr;
   }
   static constexpr int64_t FILL_ITEM_HOST = 256 * 4 * 8;
 
@@ -356,6 +359,9 @@ class Server {
       items[GS_SIGMA] = (n + 255) / 256;
       items[GS_PROP] = n;
       items[GS_FINAL] = (int64_t)D.tiles_fin_m * D.tiles_fin_n;
+      items[GS_MUTUAL] = (n * D.k1 + 255) / 256;
+      items[GS_SCAN] = 1;
+      items[GS_CSR] = (n * D.k1 + 255) / 256;
       for (int st = 0; st < GS_COUNT; st++) T.start[st][i + 1] = T.start[st][i] + (int32_t)items[st];
     }
   }
