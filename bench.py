@@ -65,8 +65,8 @@ def roofline_entry(stage, unit, amount, ms, prec):
     return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": ach / PEAK["hbm_gbs"]}
 
 
-def time_path(binding, torch, ctx, x, spec, prec, steps, warmup, out):
-    kw = dict(sim_prec=prec, ctx=ctx, out=out)
+def time_path(binding, torch, ctx, x, spec, prec, steps, warmup, out, final_prec="f32"):
+    kw = dict(sim_prec=prec, ctx=ctx, out=out, final_prec=final_prec)
     for _ in range(warmup):
         binding.run(x, spec.n_query, spec.k1, spec.k2, spec.layers, **kw)
     torch.cuda.synchronize()
@@ -194,16 +194,22 @@ def main() -> int:
 
     lowp = {}
     if not args.no_lowp:
-        for prec in ("bf16", "fp8"):
-            log(f"timing {prec} similarity path")
+        for name, prec, fprec in (("bf16", "bf16", "f32"), ("fp8", "fp8", "f32"),
+                                  ("f32_final_bf16x3", "f32", "bf16x3"), ("bf16_final_bf16x3", "bf16", "bf16x3")):
+            log(f"timing {name} path")
             out_l = torch.empty_like(out)
-            ms_l, st_l = time_path(binding, torch, ctx, x, spec, prec, args.steps, args.warmup, out_l)
+            ms_l, st_l = time_path(binding, torch, ctx, x, spec, prec, args.steps, args.warmup, out_l, fprec)
             wl = stage_work(spec, prec)
-            lowp[prec] = {"ms_per_request": ms_l, "value": spec.n ** 2 / (ms_l * 1e-3),
-                          "speedup_vs_f32": ms / ms_l, "stages_ms": st_l,
-                          "similarity_roofline": roofline_entry("similarity", *wl["similarity"], st_l["similarity"],
-                                                                prec),
-                          "dist": out_l.cpu().numpy()}
+            entry = {"similarity": prec, "final": fprec, "ms_per_request": ms_l, "value": spec.n ** 2 / (ms_l * 1e-3),
+                     "speedup_vs_f32": ms / ms_l, "stages_ms": st_l,
+                     "similarity_roofline": roofline_entry("similarity", *wl["similarity"], st_l["similarity"], prec),
+                     "dist": out_l.cpu().numpy()}
+            if fprec == "bf16x3":
+                fl = wl["final"][1] / (st_l["final"] * 1e-3) / 1e12
+                entry["final_roofline"] = {"bound": "mfma", "achieved": fl, "peak": PEAK["bf16_mfma_tflops"] / 3,
+                                           "unit": "TFLOP/s (FP32-equivalent; 3 bf16 products per FP32 product)",
+                                           "frac": fl / (PEAK["bf16_mfma_tflops"] / 3)}
+            lowp[name] = entry
 
     if args.calibrate_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)

@@ -22,7 +22,8 @@
 namespace rr {
 
 constexpr int BM = 128, BN = 128, BKB = 128, LDSR = BKB + 16, TILEB = BM * LDSR;
-constexpr int GEMM_LDS_BYTES = 4 * TILEB;  // 73728
+constexpr int GEMM_LDS_BYTES = 4 * TILEB;  // 73728: two stage buffers, or one + the mirror-tile staging
+constexpr int GEMM_LDS_1BUF = 2 * TILEB;   // 36864: one stage buffer (EPI_DIST)
 constexpr int TSTRIDE = BM + 1;            // transposed-tile LDS row stride (floats)
 static_assert(BN * TSTRIDE * 4 <= GEMM_LDS_BYTES, "transpose staging must fit the GEMM LDS");
 
@@ -83,11 +84,14 @@ struct GemmArgs {
   int64_t ldo;  // floats
 };
 
-// One 128 x 128 output tile (tm, tn). Uses `lds` (GEMM_LDS_BYTES) and block
-// barriers: every thread of the workgroup must call it with the same tile.
+// One 128 x 128 output tile (tm, tn). Uses `lds` (GEMM_LDS_1BUF bytes for
+// NBUF = 1 with EPI_DIST, else GEMM_LDS_BYTES) and block barriers: every
+// thread of the workgroup must call it with the same tile. NBUF = 1 keeps one
+// LDS stage and prefetches the next into registers (more workgroups per CU;
+// measured faster than NBUF = 2 double buffering on the 19281-row problem).
 // EPI_SIM_SYM (A == B, tm <= tn): also stores the mirrored tile C^T, so only
 // the upper triangle of tiles is computed.
-template <int MODE, int EPI>
+template <int MODE, int EPI, int NBUF = 1>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uint8_t* lds) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -131,24 +135,47 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
   const int fa = (wm * 64 + (lane & 31)) * LDSR + (lane >> 5) * 64;
   const int fb = (wn * 64 + (lane & 31)) * LDSR + (lane >> 5) * 64;
 
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int st = 0; st < g.nst; st++) {
-    const int buf = st & 1;
-    if (st + 1 < g.nst) gload(st + 1);
-    const uint8_t* la = lds + buf * 2 * TILEB;
-    const uint8_t* lb = la + TILEB;
-    u32x4 a[2][4], b[2][4];
+  if (NBUF == 2) {
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int st = 0; st < g.nst; st++) {
+      const int buf = st & 1;
+      if (st + 1 < g.nst) gload(st + 1);
+      const uint8_t* la = lds + buf * 2 * TILEB;
+      const uint8_t* lb = la + TILEB;
+      u32x4 a[2][4], b[2][4];
 #pragma unroll
-    for (int s = 0; s < 2; s++)
+      for (int s = 0; s < 2; s++)
 #pragma unroll
-      for (int c = 0; c < 4; c++) {
-        a[s][c] = *(const u32x4*)(la + fa + s * 32 * LDSR + c * 16);
-        b[s][c] = *(const u32x4*)(lb + fb + s * 32 * LDSR + c * 16);
-      }
-    mfma_stage<MODE>(acc, a, b);
-    if (st + 1 < g.nst) lstore(buf ^ 1);
+        for (int c = 0; c < 4; c++) {
+          a[s][c] = *(const u32x4*)(la + fa + s * 32 * LDSR + c * 16);
+          b[s][c] = *(const u32x4*)(lb + fb + s * 32 * LDSR + c * 16);
+        }
+      mfma_stage<MODE>(acc, a, b);
+      if (st + 1 < g.nst) lstore(buf ^ 1);
+      __syncthreads();
+    }
+  } else {
+    // one stage buffer, next stage prefetched into registers
+    gload(0);
+    for (int st = 0; st < g.nst; st++) {
+      if (st) __syncthreads();
+      lstore(0);
+      __syncthreads();
+      if (st + 1 < g.nst) gload(st + 1);
+      const uint8_t* la = lds;
+      const uint8_t* lb = la + TILEB;
+      u32x4 a[2][4], b[2][4];
+#pragma unroll
+      for (int s = 0; s < 2; s++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+          a[s][c] = *(const u32x4*)(la + fa + s * 32 * LDSR + c * 16);
+          b[s][c] = *(const u32x4*)(lb + fb + s * 32 * LDSR + c * 16);
+        }
+      mfma_stage<MODE>(acc, a, b);
+    }
     __syncthreads();
   }
 
@@ -187,6 +214,114 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
     }
   }
   __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
+}
+
+// ---------------------------------------------------------------- bf16x3
+// FP32-accurate product on bfloat16 matrix cores: each FP32 operand x is held
+// as hi = bf16(x) and lo = bf16(x - hi) (both round-to-nearest-even), and
+// a.b is accumulated in FP32 as hi.hi + hi.lo + lo.hi (Henry, Tang and
+// Heinecke 2019, "bf16x3"); the dropped lo.lo term is below 2^-16 of |a||b|.
+// Operands: four K-major bf16 planes (A hi/lo, B hi/lo), row stride ld
+// elements; 64 K-elements (128 bytes per plane row) per stage. One LDS stage
+// buffer (4 planes, 72 KB, so two workgroups share a CU) with the next stage
+// prefetched into registers while the current one is multiplied.
+constexpr int X3_LDS_BYTES = 4 * TILEB;  // 73728
+
+struct GemmX3Args {
+  const uint16_t* ahi;
+  const uint16_t* alo;
+  const uint16_t* bhi;
+  const uint16_t* blo;
+  int M, Nn;
+  int64_t ld;  // elements
+  int nst;     // 64-element stages
+  const float* sa;
+  const float* sb;
+  float* out;
+  int64_t ldo;
+};
+
+__device__ __forceinline__ void gemm_tile_x3(const GemmX3Args& g, int tm, int tn, uint8_t* lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int64_t ldb = g.ld * 2;  // bytes
+  const uint8_t* src[4] = {(const uint8_t*)g.ahi, (const uint8_t*)g.alo, (const uint8_t*)g.bhi,
+                           (const uint8_t*)g.blo};
+  int64_t roff[4][2];  // [u][A or B] row byte offsets of this thread's chunks
+  int ls[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int f = u * 256 + tid, row = f >> 3, c = f & 7;
+    roff[u][0] = (int64_t)min(m0 + row, g.M - 1) * ldb + c * 16;
+    roff[u][1] = (int64_t)min(n0 + row, g.Nn - 1) * ldb + c * 16;
+    ls[u] = row * LDSR + c * 16;
+  }
+  u32x4 rg[4][4];  // [plane][u]
+  auto gload = [&](int st) {
+#pragma unroll
+    for (int pl = 0; pl < 4; pl++)
+#pragma unroll
+      for (int u = 0; u < 4; u++) rg[pl][u] = *(const u32x4*)(src[pl] + roff[u][pl >> 1] + (int64_t)st * BKB);
+  };
+  auto lstore = [&](int buf) {
+    uint8_t* base = lds + buf * 4 * TILEB;  // buf is always 0: single stage buffer
+#pragma unroll
+    for (int pl = 0; pl < 4; pl++)
+#pragma unroll
+      for (int u = 0; u < 4; u++) *(u32x4*)(base + pl * TILEB + ls[u]) = rg[pl][u];
+  };
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+    for (int sn = 0; sn < 2; sn++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[sm][sn][r] = 0.f;
+  const int fa = (wm * 64 + (lane & 31)) * LDSR + (lane >> 5) * 64;
+  const int fb = (wn * 64 + (lane & 31)) * LDSR + (lane >> 5) * 64;
+
+  gload(0);
+  for (int st = 0; st < g.nst; st++) {
+    __syncthreads();  // every wave is done with the previous stage
+    lstore(0);
+    __syncthreads();
+    if (st + 1 < g.nst) gload(st + 1);  // in flight during the products below
+    const uint8_t* base = lds;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int s = 0; s < 2; s++) {
+        ah[s] = __builtin_bit_cast(bf16x8, *(const u32x4*)(base + 0 * TILEB + fa + s * 32 * LDSR + c * 16));
+        al[s] = __builtin_bit_cast(bf16x8, *(const u32x4*)(base + 1 * TILEB + fa + s * 32 * LDSR + c * 16));
+        bh[s] = __builtin_bit_cast(bf16x8, *(const u32x4*)(base + 2 * TILEB + fb + s * 32 * LDSR + c * 16));
+        bl[s] = __builtin_bit_cast(bf16x8, *(const u32x4*)(base + 3 * TILEB + fb + s * 32 * LDSR + c * 16));
+      }
+#pragma unroll
+      for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+        for (int sn = 0; sn < 2; sn++) {
+          acc[sm][sn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[sm], bh[sn], acc[sm][sn], 0, 0, 0);
+          acc[sm][sn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[sm], bl[sn], acc[sm][sn], 0, 0, 0);
+          acc[sm][sn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[sm], bh[sn], acc[sm][sn], 0, 0, 0);
+        }
+    }
+  }
+#pragma unroll
+  for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+    for (int sn = 0; sn < 2; sn++) {
+      const int col = n0 + wn * 64 + sn * 32 + (lane & 31);
+      if (col >= g.Nn) continue;
+      const float scol = g.sb[col];
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int row = m0 + wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        if (row < g.M) g.out[(int64_t)row * g.ldo + col] = 1.0f - g.sa[row] * scol * acc[sm][sn][r];
+      }
+    }
+  __syncthreads();
 }
 
 // Upper-triangle tile t (0 <= t < T(T+1)/2) of a T x T tile grid, row-major

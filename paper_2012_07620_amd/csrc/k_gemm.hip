@@ -30,7 +30,7 @@ __device__ __forceinline__ TileMap grouped_order(int pid, int tiles_m, int tiles
 
 template <int MODE, int EPI>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g, int tiles_m, int tiles_n) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[GEMM_LDS_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[EPI == EPI_SIM_SYM ? GEMM_LDS_BYTES : GEMM_LDS_1BUF];
   const int pid = xcd_linear(blockIdx.x, gridDim.x);
   int tm, tn;
   if (EPI == EPI_SIM_SYM) {
@@ -72,9 +72,28 @@ hipError_t launch_gemm_dist(const float* a, int M, const float* b, int Nn, int64
   return launch_gemm_t<MODE_F32, EPI_DIST>(a, M, ld_elems * 4, b, Nn, ld_elems * 4, kelems * 4, sa, sb, out, ldo, s);
 }
 
-hipError_t launch_gemm_dist_bf16x3(const uint16_t*, const uint16_t*, int, const uint16_t*, const uint16_t*, int,
-                                   int64_t, int64_t, const float*, const float*, float*, int64_t, hipStream_t) {
-  return hipErrorNotSupported;
+__global__ __launch_bounds__(256) void gemm_x3_kernel(GemmX3Args g, int tiles_m, int tiles_n) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds_x3[];
+  const TileMap t = grouped_order(xcd_linear(blockIdx.x, gridDim.x), tiles_m, tiles_n);
+  gemm_tile_x3(g, t.tm, t.tn, lds_x3);
+}
+
+hipError_t launch_gemm_dist_bf16x3(const uint16_t* a_hi, const uint16_t* a_lo, int M, const uint16_t* b_hi,
+                                   const uint16_t* b_lo, int Nn, int64_t ld_elems, int64_t kelems, const float* sa,
+                                   const float* sb, float* out, int64_t ldo, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)gemm_x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       X3_LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int tm = (M + BM - 1) / BM, tn = (Nn + BN - 1) / BN;
+  const int64_t nwg = (int64_t)tm * tn;
+  if (nwg <= 0 || nwg > 0x7FFFFFFF || kelems % 64 || kelems <= 0 || ld_elems % 64) return hipErrorInvalidValue;
+  GemmX3Args g{a_hi, a_lo, b_hi, b_lo, M, Nn, ld_elems, (int)(kelems / 64), sa, sb, out, ldo};
+  hipLaunchKernelGGL(gemm_x3_kernel, dim3((unsigned)nwg), dim3(256), X3_LDS_BYTES, s, g, tm, tn);
+  return hipGetLastError();
 }
 
 }  // namespace rr

@@ -12,7 +12,7 @@
 namespace rr {
 
 constexpr int kGroupedRowWGs = 2048;
-constexpr int kGroupedGemmWGs = 512;  // two 72 KB-LDS workgroups per CU
+constexpr int kGroupedGemmWGs = 512;  // two workgroups per CU
 
 __device__ __forceinline__ int find_prob(const BatchTable* __restrict__ t, int stage, int item) {
   int p = 0;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void g_prop(const BatchTable* __restrict__ t, 
 }
 
 __global__ __launch_bounds__(256) void g_final(const BatchTable* __restrict__ t) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[GEMM_LDS_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[GEMM_LDS_1BUF];
   const int L = t->layers;
   FOR_ITEMS(GS_FINAL) {
     const int p = find_prob(t, GS_FINAL, item);

@@ -62,8 +62,8 @@ hipError_t launch_astar_sigma(const int32_t* cnt, int n, int k1, float* sigma, h
 // a5 + a6: one propagation layer (Eq. 14, sum aggregator) with lazy
 // normalisation: hout_i = sin_i*hin_i + sum_{r<k2} w_ir * sin_{j_r} * hin_{j_r},
 // w_i0 = 1 for the row itself, w_ir = val_ir^alpha; sout_i = 1/|hout_i|.
-// sin == nullptr means all ones. When hi/lo are non-null the row is also
-// written as bf16 high/low parts (final bf16x3 product).
+// sin == nullptr means all ones. When hi/lo are non-null the row is written
+// as bf16 high/low parts (final bf16x3 product) instead of FP32.
 hipError_t launch_propagate(const float* hin, const float* sin, int n, int64_t ld, int64_t cols,
                             const int32_t* knn_idx, const float* knn_val, int k1, int k2, int alpha,
                             float* hout, float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s);

@@ -53,7 +53,7 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o) {
   if (kc > kMaxCand) kc = kMaxCand;
   P.kc = (int)kc;
   P.rescore = extra > 0;
-  P.ldp = pad_k_elems(P.d, 4);
+  P.ldp = (P.d + 63) / 64 * 64;  // 256-byte rows: whole f32 stages and whole bf16x3 stages in raw mode
   P.lbytes = (P.prec == SimPrec::BF16) ? 2 : (P.prec == SimPrec::FP8 ? 1 : 0);
   P.ldl = P.lbytes ? pad_k_elems(P.d, P.lbytes) : 0;
   P.ldN = pad_n(P.n);

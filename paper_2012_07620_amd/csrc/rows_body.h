@@ -370,9 +370,11 @@ __device__ __forceinline__ void propagate_row(const float* __restrict__ hin, con
       acc = f32x4{__builtin_fmaf(w, v.x, acc.x), __builtin_fmaf(w, v.y, acc.y), __builtin_fmaf(w, v.z, acc.z),
                   __builtin_fmaf(w, v.w, acc.w)};
     }
-    ((f32x4*)(hout + (int64_t)i * ld))[c] = acc;
+    if (hi)
+      split_store4(hi, lo, (int64_t)i * ld + c * 4, acc);
+    else
+      ((f32x4*)(hout + (int64_t)i * ld))[c] = acc;
     ss = sq_acc4(ss, acc);
-    if (hi) split_store4(hi, lo, (int64_t)i * ld + c * 4, acc);
   }
   finish_norm(ss, sout, i, sh);
 }
@@ -473,9 +475,11 @@ __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn,
     const int w4 = width >> 2;
     for (int c = tid; c < w4; c += 256) {
       const f32x4 acc = ((const f32x4*)sh.row)[c];
-      ((f32x4*)(hout + (int64_t)i * ld + c0))[c] = acc;
+      if (hi)
+        split_store4(hi, lo, (int64_t)i * ld + c0 + c * 4, acc);
+      else
+        ((f32x4*)(hout + (int64_t)i * ld + c0))[c] = acc;
       ss = sq_acc4(ss, acc);
-      if (hi) split_store4(hi, lo, (int64_t)i * ld + c0 + c * 4, acc);
     }
     __syncthreads();
   }

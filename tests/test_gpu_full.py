@@ -18,6 +18,19 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 D_TOL = {"f32": 1e-4, "bf16": 2e-2, "fp8": 2e-2}
 
 
+def test_mid_final_bf16x3(gpu_lib, mid):
+    # FP32-accurate split-bf16 final product: same tolerance as the FP32 path
+    p, ref = mid
+    d, ki, kv = _gpu(p, "f32", final_prec="bf16x3")
+    err = np.abs(d - ref.dist)
+    print(f"f32 sim + bf16x3 final: D vs FP64 max {err.max():.3e} mean {err.mean():.3e}", flush=True)
+    assert err.max() <= D_TOL["f32"]
+    d2, _, _ = _gpu(p, "bf16", final_prec="bf16x3")
+    err2 = np.abs(d2 - ref.dist)
+    print(f"bf16 sim + bf16x3 final: D vs FP64 max {err2.max():.3e} mean {err2.mean():.3e}", flush=True)
+    assert err2.max() <= D_TOL["bf16"]
+
+
 @pytest.fixture(scope="module")
 def mid():
     p = synth.make_problem(synth.MID)

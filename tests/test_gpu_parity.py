@@ -156,3 +156,17 @@ def test_low_precision_similarity_error(gpu_lib, prec):
     err = np.abs(s.cpu().numpy() - ref)
     print(f"{prec}: max |S - S64| = {err.max():.3e}, mean {err.mean():.3e}")
     assert err.max() < (0.02 if prec == "bf16" else 0.08)
+
+
+@pytest.mark.parametrize("n,q,d,k1,k2,layers,node", [
+    (1000, 100, 128, 10, 3, 1, "adj"),
+    (300, 100, 40, 12, 5, 0, "adj"),
+    (333, 33, 96, 20, 6, 2, "raw"),
+    (333, 33, 96, 20, 6, 0, "raw"),
+    (130, 30, 64, 9, 4, 3, "adj"),
+])
+def test_final_bf16x3_matches_fp64(gpu_lib, n, q, d, k1, k2, layers, node):
+    # the split-bf16 final product must meet the FP32 path's tolerance
+    x = synth.random_features(n, d, seed=n + d + layers, n_ids=8)
+    mx, mean, excused = _check_full(gpu_lib, x, q, k1, k2, layers, node=node, final_prec="bf16x3")
+    print(f"bf16x3: max err {mx:.2e} mean {mean:.2e}")
