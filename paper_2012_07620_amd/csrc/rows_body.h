@@ -438,9 +438,13 @@ __device__ __forceinline__ void csr_pair(const int32_t* __restrict__ knn, int n,
 // the same FMA sequence and per-thread column order as propagate_row on a
 // dense A* (so the result is identical), then written once.
 constexpr int FIRST_CHUNK = 8192;  // floats of the output row held in LDS
+constexpr int FIRST_ENTRIES = 2048; // sparse A* entries of one row staged in LDS
 struct FirstShared {
   PropShared p;
   float row[FIRST_CHUNK];
+  int col[FIRST_ENTRIES];
+  float val[FIRST_ENTRIES];
+  int start[257];  // entries of member r are [start[r], start[r+1])
 };
 
 __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn, const float* __restrict__ kv,
@@ -451,24 +455,61 @@ __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn,
                                                 FirstShared& sh) {
   const int tid = threadIdx.x;
   load_coefs(nullptr, knn, kv, k1, k2, alpha, i, sh.p);
+  // entry counts per member: out-list (k1) + non-mutual in-list
+  if (tid == 0) {
+    int acc = 0;
+    for (int r = 0; r < k2; r++) {
+      sh.start[r] = acc;
+      const int j = sh.p.nb[r];
+      acc += k1 + (off[j + 1] - off[j]);
+    }
+    sh.start[k2] = acc;
+  }
+  __syncthreads();
+  const bool staged = sh.start[k2] <= FIRST_ENTRIES;
+  if (staged) {
+    for (int r = 0; r < k2; r++) {
+      const int j = sh.p.nb[r];
+      const int base = sh.start[r];
+      const int32_t* lj = knn + (int64_t)j * k1;
+      const uint8_t* fj = mflag + (int64_t)j * k1;
+      for (int s = tid; s < k1; s += 256) {
+        sh.col[base + s] = lj[s];
+        sh.val[base + s] = fj[s] ? 1.0f : 0.5f;
+      }
+      const int b = off[j], n_in = off[j + 1] - b;
+      for (int s = tid; s < n_in; s += 256) {
+        sh.col[base + k1 + s] = inl[b + s];
+        sh.val[base + k1 + s] = 0.5f;
+      }
+    }
+  }
+  __syncthreads();
   float ss = 0.f;
   for (int64_t c0 = 0; c0 < ld; c0 += FIRST_CHUNK) {
     const int width = (int)min((int64_t)FIRST_CHUNK, ld - c0);
     for (int k = tid; k < FIRST_CHUNK; k += 256) sh.row[k] = 0.f;
     __syncthreads();
     for (int r = 0; r < k2; r++) {
-      const int j = sh.p.nb[r];
       const float c = sh.p.cf[r];
-      const int32_t* lj = knn + (int64_t)j * k1;
-      const uint8_t* fj = mflag + (int64_t)j * k1;
-      for (int s = tid; s < k1; s += 256) {
-        const int64_t m = lj[s] - c0;
-        if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, fj[s] ? 1.0f : 0.5f, sh.row[m]);
-      }
-      const int b = off[j], e = off[j + 1];
-      for (int s = b + tid; s < e; s += 256) {
-        const int64_t m = inl[s] - c0;
-        if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, 0.5f, sh.row[m]);
+      if (staged) {
+        for (int s = sh.start[r] + tid; s < sh.start[r + 1]; s += 256) {
+          const int64_t m = sh.col[s] - c0;
+          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, sh.val[s], sh.row[m]);
+        }
+      } else {  // very large in-degree: read the entries from memory
+        const int j = sh.p.nb[r];
+        const int32_t* lj = knn + (int64_t)j * k1;
+        const uint8_t* fj = mflag + (int64_t)j * k1;
+        for (int s = tid; s < k1; s += 256) {
+          const int64_t m = lj[s] - c0;
+          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, fj[s] ? 1.0f : 0.5f, sh.row[m]);
+        }
+        const int b = off[j], e = off[j + 1];
+        for (int s = b + tid; s < e; s += 256) {
+          const int64_t m = inl[s] - c0;
+          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, 0.5f, sh.row[m]);
+        }
       }
       __syncthreads();
     }
