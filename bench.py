@@ -65,6 +65,34 @@ def roofline_entry(stage, unit, amount, ms, prec):
     return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": ach / PEAK["hbm_gbs"]}
 
 
+def kernel_src_hash() -> str:
+    import glob
+    import hashlib
+    src = sorted(glob.glob(os.path.join(ROOT, "paper_2012_07620_amd", "csrc", "*.h")) +
+                 glob.glob(os.path.join(ROOT, "paper_2012_07620_amd", "csrc", "*.hip")))
+    h = hashlib.sha256()
+    for f in src:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, path: str, role: str):
+    """HBM bytes per launch of the kernel playing `role`, from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when that summary is
+    missing or the kernel sources changed since the counters were taken."""
+    f = os.path.join(ROOT, "profiles", f"traffic_{workload}_{path}.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        t = json.load(fh)
+    k = t.get("kernels", {}).get(role)
+    if k is None or t.get("kernel_src_sha256") != kernel_src_hash():
+        return None
+    return {"read_bytes": k["read_bytes"], "write_bytes": k["write_bytes"],
+            "bytes": k["read_bytes"] + k["write_bytes"], "source": os.path.relpath(f, ROOT)}
+
+
 def time_path(binding, torch, ctx, x, spec, prec, steps, warmup, out, final_prec="f32"):
     kw = dict(sim_prec=prec, ctx=ctx, out=out, final_prec=final_prec)
     for _ in range(warmup):
@@ -190,7 +218,9 @@ def main() -> int:
     roof = {k: roofline_entry(k, *work[k], stages[k], "f32") for k in work}
     dominant = max(work, key=lambda k: stages[k])
     dom = dict(roof[dominant])
-    dom.update({"kernel": dominant, "traffic": None, "ms_per_launch": stages[dominant]})
+    tr = measured_traffic(spec.name, "f32", dominant)
+    dom.update({"kernel": dominant, "traffic": tr["bytes"] if tr else None, "traffic_detail": tr,
+                "ms_per_launch": stages[dominant]})
 
     lowp = {}
     if not args.no_lowp:
