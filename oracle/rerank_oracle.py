@@ -37,6 +37,12 @@ Readings taken where the paper is silent (each is also the GPU library's):
   R9  output D_qg = 1 - cos(h_q, h_g) for q < Q <= g < N.
   R10 node mode "raw" uses h^(0)_i = x_i (the Table 1 ablation column with
       original features); with zero layers it gives the initial ranking.
+      Node mode "adj_raw" uses h^(0)_i = row i of A (Table 1, A_i column).
+  R11 aggregators (Eq. 13): "sum" (the paper's choice), "mean" = the sum of
+      the k2 messages divided by k2, "max" = element-wise maximum of the k2
+      messages e_ij^alpha h_j; the residual h_i is added in every case.
+  R12 the ranking list L of Algorithm 1: per query, gallery rows by
+      ascending distance, ties to the lower gallery index.
 """
 from __future__ import annotations
 
@@ -50,7 +56,7 @@ import scipy.sparse as sp
 __all__ = [
     "unit_rows", "similarity_rows", "knn_of_row", "knn_lists", "adjacency",
     "symmetric_adjacency", "edge_weights", "initial_features", "propagate",
-    "row_norms", "distances", "rerank", "Graph", "OracleResult",
+    "row_norms", "distances", "rerank", "ranking", "Graph", "OracleResult",
 ]
 
 
@@ -158,11 +164,14 @@ def edge_weights(idx: np.ndarray, val: np.ndarray, k2: int, alpha: int) -> sp.cs
 
 
 def initial_features(x: np.ndarray, idx: np.ndarray, node: str = "adj"):
-    """h^(0): rows of A* (Eq. 11, node mode "adj") or the raw features x_i
-    (node mode "raw", reading R10). Not normalised (reading R6)."""
+    """h^(0): rows of A* (Eq. 11, node mode "adj"), rows of A (Eq. 8, node
+    mode "adj_raw") or the raw features x_i (node mode "raw", reading R10).
+    Not normalised (reading R6)."""
     n = x.shape[0]
     if node == "adj":
         return symmetric_adjacency(idx, n)
+    if node == "adj_raw":
+        return adjacency(idx, n)
     if node == "raw":
         return np.asarray(x, dtype=np.float64).copy()
     raise ValueError(node)
@@ -180,13 +189,35 @@ def _scale_rows(h, f):
     return h * f[:, None]
 
 
-def propagate(h0, w: sp.csr_matrix, layers: int, keep_all: bool = False):
-    """Eq. 14 with the sum aggregator, ``layers`` times, each followed by the
-    row L2 normalisation. ``keep_all`` also returns every intermediate h."""
+def _aggregate_max(h, w: sp.csr_matrix):
+    """Element-wise maximum over the k2 messages e_ij^alpha h_j of each row
+    (Eq. 13 with aggregate = max); plain loops over rows, dense rows."""
+    hd = h.toarray() if sp.issparse(h) else np.asarray(h)
+    out = np.empty_like(hd)
+    for i in range(w.shape[0]):
+        lo, hi = w.indptr[i], w.indptr[i + 1]
+        msgs = w.data[lo:hi, None] * hd[w.indices[lo:hi]]
+        out[i] = msgs.max(axis=0)
+    return out
+
+
+def propagate(h0, w: sp.csr_matrix, layers: int, keep_all: bool = False, aggregator: str = "sum"):
+    """Eq. 13/14: h <- h + aggregate(e_ij^alpha h_j, j in N(i,k2)), ``layers``
+    times, each followed by the row L2 normalisation. Aggregators per reading
+    R11. ``keep_all`` also returns every intermediate h."""
     h = h0
     hist = [h0]
+    k2 = np.diff(w.indptr)
     for _ in range(layers):
-        u = h + w @ h
+        if aggregator == "sum":
+            u = h + w @ h
+        elif aggregator == "mean":
+            u = h + sp.diags(1.0 / k2) @ (w @ h)
+        elif aggregator == "max":
+            hd = h.toarray() if sp.issparse(h) else np.asarray(h)
+            u = hd + _aggregate_max(hd, w)
+        else:
+            raise ValueError(aggregator)
         if sp.issparse(u):
             u = u.tocsr()
         h = _scale_rows(u, 1.0 / row_norms(u))
@@ -218,8 +249,16 @@ class OracleResult:
     dist: np.ndarray  # (len(q_rows), len(g_rows))
 
 
+def ranking(dist: np.ndarray, r: int) -> np.ndarray:
+    """The first ``r`` entries of the ranking list L (Algorithm 1, reading
+    R12): per query row of ``dist``, gallery positions by ascending distance,
+    ties to the lower position (a stable sort)."""
+    return np.argsort(dist, axis=1, kind="stable")[:, :r]
+
+
 def rerank(x: np.ndarray, n_query: int, k1: int, k2: int, layers: int,
-           alpha: int = 2, node: str = "adj", q_rows=None, g_rows=None) -> OracleResult:
+           alpha: int = 2, node: str = "adj", q_rows=None, g_rows=None,
+           aggregator: str = "sum") -> OracleResult:
     """Algorithm 1 end to end: similarity, k1 lists, A*, h^(0) and k2 edges,
     ``layers`` propagation steps, query x gallery distances."""
     x = np.asarray(x)
@@ -231,5 +270,5 @@ def rerank(x: np.ndarray, n_query: int, k1: int, k2: int, layers: int,
     g = knn_lists(x, k1, k2)
     h0 = initial_features(x, g.idx, node)
     w = edge_weights(g.idx, g.val, k2, alpha)
-    h = propagate(h0, w, layers)
+    h = propagate(h0, w, layers, aggregator=aggregator)
     return OracleResult(g, h, distances(h, n_query, q_rows, g_rows))

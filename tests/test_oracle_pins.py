@@ -265,7 +265,7 @@ def test_planted_mistakes_fail_the_hand_pin(monkeypatch):
     orig_w, orig_prop, orig_adj = orc.edge_weights, orc.propagate, orc.symmetric_adjacency
     mutants = {
         "alpha_dropped": ("edge_weights", lambda idx, val, k2, a: orig_w(idx, val, k2, 1)),
-        "no_residual": ("propagate", lambda h0, w, L, keep_all=False: _prop_no_residual(h0, w, L)),
+        "no_residual": ("propagate", lambda h0, w, L, keep_all=False, aggregator="sum": _prop_no_residual(h0, w, L)),
         "A_not_symmetrised": ("symmetric_adjacency", lambda idx, n: orc.adjacency(idx, n)),
         "transposed_weights": ("edge_weights", lambda idx, val, k2, a: orig_w(idx, val, k2, a).T.tocsr()),
     }
@@ -282,3 +282,65 @@ def _prop_no_residual(h0, w, layers):
         u = (w @ h).tocsr()
         h = (sp.diags(1.0 / orc.row_norms(u)) @ u).tocsr()
     return h
+
+
+# --------------------------------------------- aggregators, A rows, ranking
+@pytest.mark.parametrize("agg,key", [("mean", "D_layers1_mean"), ("max", "D_layers1_max")])
+def test_hand_example_aggregators(agg, key):
+    g = _hand()
+    x = np.array(g["x"], dtype=np.float32)
+    res = orc.rerank(x, g["n_query"], g["k1"], g["k2"], 1, alpha=g["alpha"], aggregator=agg)
+    np.testing.assert_allclose(res.dist, np.array(g[key]), rtol=0, atol=1e-13)
+    u = np.array(g[f"u_layer1_{agg}"])
+    h = res.h.toarray() if hasattr(res.h, "toarray") else res.h
+    np.testing.assert_allclose(h, u / np.linalg.norm(u, axis=1, keepdims=True), atol=1e-14)
+
+
+def test_hand_example_A_rows():
+    g = _hand()
+    x = np.array(g["x"], dtype=np.float32)
+    gr = orc.knn_lists(x, g["k1"])
+    np.testing.assert_array_equal(orc.adjacency(gr.idx, 5).toarray(), np.array(g["A_rows"]))
+    res = orc.rerank(x, g["n_query"], g["k1"], g["k2"], 0, node="adj_raw")
+    np.testing.assert_allclose(res.dist, np.array(g["D_layers0_A"]), atol=1e-14)
+
+
+def test_hand_example_ranking():
+    g = _hand()
+    assert orc.ranking(np.array(g["D_layers1"]), 3).tolist() == g["ranking_layers1"]
+
+
+def test_ranking_matches_counting():
+    rng = np.random.default_rng(4)
+    d = np.round(rng.random((9, 40)) * 8) / 8  # many exact ties
+    r = orc.ranking(d, 40)
+    for q in range(9):
+        for g in range(40):
+            pos = int(((d[q] < d[q, g]) | ((d[q] == d[q, g]) & (np.arange(40) < g))).sum())
+            assert r[q, pos] == g
+
+
+@pytest.mark.parametrize("agg", ["sum", "mean", "max"])
+@pytest.mark.parametrize("node", ["adj", "adj_raw"])
+def test_orthogonal_clusters_every_aggregator(agg, node):
+    c, m = 3, 4
+    x = np.zeros((c * m, c), dtype=np.float32)
+    lab = np.repeat(np.arange(c), m)
+    perm = np.random.default_rng(2).permutation(c * m)
+    x[np.arange(c * m), lab[perm]] = 2.0
+    lab = lab[perm]
+    for layers in (0, 1, 2):
+        res = orc.rerank(x, 5, m, 3, layers, node=node, aggregator=agg)
+        expect = (lab[:5, None] != lab[None, 5:]).astype(np.float64)
+        np.testing.assert_allclose(res.dist, expect, atol=1e-14)
+
+
+def test_mean_is_sum_with_scaled_messages():
+    # mean aggregator == sum aggregator with every message weight divided by k2
+    x = random_features(40, 6, seed=12, n_ids=5)
+    gr = orc.knn_lists(x, 7, 4)
+    h0 = orc.initial_features(x, gr.idx)
+    w = orc.edge_weights(gr.idx, gr.val, 4, 2)
+    a = orc.propagate(h0, w, 2, aggregator="mean").toarray()
+    b = orc.propagate(h0, (w / 4.0).tocsr(), 2, aggregator="sum").toarray()
+    np.testing.assert_allclose(a, b, atol=1e-14)
