@@ -63,10 +63,15 @@ typedef enum { RERANK_IN_F32 = 0, RERANK_IN_BF16 = 1 } rerank_in_dtype;
  * neighbour lists is FP32 in every mode. */
 typedef enum { RERANK_SIM_F32 = 0, RERANK_SIM_BF16 = 1, RERANK_SIM_FP8_E4M3 = 2 } rerank_sim_prec;
 
-/* Vertex feature h^(0) (Table 1 ablation columns): A* rows as in Eq. 11, or
- * the raw features x_i (with zero layers this reproduces the initial
- * cosine ranking). */
-typedef enum { RERANK_NODE_ADJ_SYM = 0, RERANK_NODE_RAW = 1 } rerank_node;
+/* Vertex feature h^(0) (Table 1 ablation columns): A* rows as in Eq. 11, the
+ * raw features x_i (with zero layers this reproduces the initial cosine
+ * ranking), or the rows of the non-symmetrised A of Eq. 8. */
+typedef enum { RERANK_NODE_ADJ_SYM = 0, RERANK_NODE_RAW = 1, RERANK_NODE_ADJ = 2 } rerank_node;
+
+/* Aggregator of Eq. 13 (the paper uses sum). mean divides the sum of the k2
+ * messages e_ij^alpha h_j by k2; max takes their element-wise maximum. The
+ * residual h_i is added in every case. */
+typedef enum { RERANK_AGG_SUM = 0, RERANK_AGG_MEAN = 1, RERANK_AGG_MAX = 2 } rerank_aggregator;
 
 /* Arithmetic of the final query x gallery product. F32 is plain FP32 matrix
  * cores; BF16X3 splits each FP32 operand into a high and a low bfloat16 part
@@ -89,6 +94,7 @@ typedef struct {
                          and at 256. */
   int32_t node;       /* rerank_node */
   int32_t final_prec; /* rerank_final_prec */
+  int32_t aggregator; /* rerank_aggregator */
 } rerank_params;
 
 /* Fill *p with the paper's settings (alpha 2, sum aggregator, A* features,
@@ -137,6 +143,14 @@ rerank_status rerank_knn(rerank_ctx* ctx, const rerank_params* p, const void* d_
  * low-precision S). Stream-ordered like rerank_run. */
 rerank_status rerank_similarity(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype,
                                 float* d_s, int64_t ld_s, void* hip_stream);
+
+/* The first r entries of the ranking list L that Algorithm 1 returns: for
+ * each of the q rows of d_dist (row stride g floats, as rerank_run writes
+ * it), the positions of the r smallest distances in ascending order, ties to
+ * the lower position. d_rank: q x r int32 (gallery position 0 = row Q of the
+ * problem). 1 <= r <= min(g, 256). Stream-ordered; ctx supplies the device. */
+rerank_status rerank_rank(rerank_ctx* ctx, const float* d_dist, int32_t q, int32_t g, int32_t r, int32_t* d_rank,
+                          void* hip_stream);
 
 /* ---- serving: asynchronous requests with admission and continuous batching
  * A submitted request is admitted once its working set (rerank_workspace_bytes)

@@ -18,13 +18,15 @@ LIB_PATH = os.path.join(HERE, "librerank.so")
 OK, E_INVALID, E_NOMEM, E_HIP, E_BUSY, E_TIMEOUT, E_CANCELLED, E_UNSUPPORTED = range(8)
 IN_F32, IN_BF16 = 0, 1
 SIM = {"f32": 0, "bf16": 1, "fp8": 2}
-NODE = {"adj": 0, "raw": 1}
+NODE = {"adj": 0, "raw": 1, "adj_raw": 2}
+AGG = {"sum": 0, "mean": 1, "max": 2}
 FINAL = {"f32": 0, "bf16x3": 1}
 
 EXPORTS = (
     "rerank_default_params", "rerank_validate", "rerank_workspace_bytes", "rerank_create", "rerank_destroy",
     "rerank_run", "rerank_knn", "rerank_similarity", "rerank_submit", "rerank_poll", "rerank_wait",
     "rerank_cancel", "rerank_status_str", "rerank_last_error", "rerank_stage_times", "rerank_stage_name",
+    "rerank_rank",
 )
 CTX_STAGE_TIMING = 1
 STAGES = ("prep", "similarity", "topk", "rescore", "adjacency", "propagate", "final")
@@ -34,7 +36,8 @@ class Params(ctypes.Structure):
     """Mirror of ``rerank_params``."""
 
     _fields_ = [(n, ctypes.c_int32) for n in (
-        "n", "n_query", "dim", "k1", "k2", "layers", "alpha", "sim_prec", "extra_cand", "node", "final_prec")]
+        "n", "n_query", "dim", "k1", "k2", "layers", "alpha", "sim_prec", "extra_cand", "node", "final_prec",
+        "aggregator")]
 
 
 class RerankError(RuntimeError):
@@ -75,6 +78,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
             "rerank_last_error": (ctypes.c_char_p, []),
             "rerank_stage_times": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double)]),
             "rerank_stage_name": (ctypes.c_char_p, [i32]),
+            "rerank_rank": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -91,8 +95,10 @@ def _check(status: int) -> None:
 
 
 def make_params(n: int, n_query: int, dim: int, k1: int, k2: int, layers: int = 2, alpha: int = 2,
-                sim_prec: str = "f32", extra_cand: int = -1, node: str = "adj", final_prec: str = "f32") -> Params:
-    return Params(n, n_query, dim, k1, k2, layers, alpha, SIM[sim_prec], extra_cand, NODE[node], FINAL[final_prec])
+                sim_prec: str = "f32", extra_cand: int = -1, node: str = "adj", final_prec: str = "f32",
+                aggregator: str = "sum") -> Params:
+    return Params(n, n_query, dim, k1, k2, layers, alpha, SIM[sim_prec], extra_cand, NODE[node], FINAL[final_prec],
+                  AGG[aggregator])
 
 
 def validate(p: Params) -> int:
@@ -160,13 +166,13 @@ def _x_args(x):
 
 def run(x, n_query: int, k1: int, k2: int, layers: int = 2, alpha: int = 2, sim_prec: str = "f32",
         extra_cand: int = -1, node: str = "adj", final_prec: str = "f32", return_knn: bool = False,
-        ctx: Optional[Context] = None, out=None):
+        ctx: Optional[Context] = None, out=None, aggregator: str = "sum"):
     """Full method on device tensor ``x`` (N x d, queries first). Returns the
     Q x G distance tensor (and the N x k1 lists and similarities)."""
     import torch
     dt = _x_args(x)
     n, d = x.shape
-    p = make_params(n, n_query, d, k1, k2, layers, alpha, sim_prec, extra_cand, node, final_prec)
+    p = make_params(n, n_query, d, k1, k2, layers, alpha, sim_prec, extra_cand, node, final_prec, aggregator)
     ctx = ctx or default_context(x.device.index or 0)
     dist = out if out is not None else torch.empty((n_query, n - n_query), dtype=torch.float32, device=x.device)
     ki = kv = None
@@ -206,12 +212,27 @@ def similarity(x, sim_prec: str = "f32", ctx: Optional[Context] = None, out=None
     return s
 
 
+def rank(dist, r: int, ctx: Optional[Context] = None):
+    """First r entries of the ranking list per query row of ``dist``
+    (ascending distance, ties to the lower gallery position), int32."""
+    import torch
+    if not dist.is_cuda or dist.dim() != 2 or not dist.is_contiguous() or dist.dtype != torch.float32:
+        raise ValueError("dist must be a contiguous 2-D float32 device tensor")
+    q, g = dist.shape
+    ctx = ctx or default_context(dist.device.index or 0)
+    out = torch.empty((q, r), dtype=torch.int32, device=dist.device)
+    _check(library().rerank_rank(ctx.handle, dist.data_ptr(), q, g, r, out.data_ptr(),
+                                 _stream_ptr(torch, dist.device)))
+    return out
+
+
 def submit(ctx: Context, x, out, n_query: int, k1: int, k2: int, layers: int = 1, alpha: int = 2,
-           sim_prec: str = "f32", extra_cand: int = -1, node: str = "adj", final_prec: str = "f32") -> int:
+           sim_prec: str = "f32", extra_cand: int = -1, node: str = "adj", final_prec: str = "f32",
+           aggregator: str = "sum") -> int:
     """Asynchronous request; ``out`` (Q x G float32) must stay alive until done."""
     dt = _x_args(x)
     n, d = x.shape
-    p = make_params(n, n_query, d, k1, k2, layers, alpha, sim_prec, extra_cand, node, final_prec)
+    p = make_params(n, n_query, d, k1, k2, layers, alpha, sim_prec, extra_cand, node, final_prec, aggregator)
     t = ctypes.c_uint64(0)
     _check(library().rerank_submit(ctx.handle, ctypes.byref(p), x.data_ptr(), dt, out.data_ptr(), ctypes.byref(t)))
     return t.value

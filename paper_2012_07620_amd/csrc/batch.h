@@ -30,7 +30,7 @@ enum GStage : int {
 
 struct ProbDesc {
   int32_t n, q, g, d, k1, k2, kc, alpha, in_bf16, lbytes;
-  int32_t tiles_sim, tiles_fin_m, tiles_fin_n, node;
+  int32_t tiles_sim, tiles_fin_m, tiles_fin_n, node, agg;
   int64_t ldp, ldl, ldN, ldH, fill_items_a;
   const void* x;
   float* dist;
@@ -66,11 +66,13 @@ struct BatchKey {
   int r;       // wave list width for top-k / re-score (kc <= 64 r)
   int layers;  // propagation launches
   int node;    // rerank_node
+  int agg;     // rerank_aggregator
   bool operator<(const BatchKey& o) const {
     if (prec != o.prec) return prec < o.prec;
     if (r != o.r) return r < o.r;
     if (layers != o.layers) return layers < o.layers;
-    return node < o.node;
+    if (node != o.node) return node < o.node;
+    return agg < o.agg;
   }
 };
 

@@ -62,24 +62,25 @@ hipError_t launch_fill_zero(float* buf, int64_t count, hipStream_t s) {
 }
 
 __global__ void astar_scatter_kernel(const int32_t* __restrict__ knn, int n, int k1, float* __restrict__ H,
-                                     int64_t ldH, int32_t* __restrict__ cnt) {
-  scatter_pair(knn, n, k1, H, ldH, cnt, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                                     int64_t ldH, int32_t* __restrict__ cnt, int sym) {
+  scatter_pair(knn, n, k1, H, ldH, cnt, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, sym != 0);
 }
 
 hipError_t launch_astar_scatter(const int32_t* knn_idx, int n, int k1, float* H, int64_t ldH, int32_t* cnt,
-                                hipStream_t s) {
+                                bool sym, hipStream_t s) {
   const int64_t total = (int64_t)n * k1;
   hipLaunchKernelGGL(astar_scatter_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, knn_idx, n, k1, H,
-                     ldH, cnt);
+                     ldH, cnt, (int)sym);
   return hipGetLastError();
 }
 
-__global__ void astar_sigma_kernel(const int32_t* __restrict__ cnt, int n, int k1, float* __restrict__ sigma) {
-  astar_sigma_row(cnt, n, k1, sigma, blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void astar_sigma_kernel(const int32_t* __restrict__ cnt, int n, int k1, float* __restrict__ sigma,
+                                   int sym) {
+  astar_sigma_row(cnt, n, k1, sigma, blockIdx.x * blockDim.x + threadIdx.x, sym != 0);
 }
 
-hipError_t launch_astar_sigma(const int32_t* cnt, int n, int k1, float* sigma, hipStream_t s) {
-  hipLaunchKernelGGL(astar_sigma_kernel, dim3((n + 255) / 256), dim3(256), 0, s, cnt, n, k1, sigma);
+hipError_t launch_astar_sigma(const int32_t* cnt, int n, int k1, float* sigma, bool sym, hipStream_t s) {
+  hipLaunchKernelGGL(astar_sigma_kernel, dim3((n + 255) / 256), dim3(256), 0, s, cnt, n, k1, sigma, (int)sym);
   return hipGetLastError();
 }
 
@@ -87,18 +88,18 @@ hipError_t launch_astar_sigma(const int32_t* cnt, int n, int k1, float* sigma, h
 __global__ __launch_bounds__(256) void propagate_kernel(const float* __restrict__ hin, const float* __restrict__ sin,
                                                         int64_t ld, int64_t cols, const int32_t* __restrict__ knn,
                                                         const float* __restrict__ kv, int k1, int k2, int alpha,
-                                                        float* __restrict__ hout, float* __restrict__ sout,
+                                                        int agg, float* __restrict__ hout, float* __restrict__ sout,
                                                         uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
   __shared__ PropShared sh;
-  propagate_row(hin, sin, ld, cols, knn, kv, k1, k2, alpha, hout, sout, hi, lo, blockIdx.x, sh);
+  propagate_row(hin, sin, ld, cols, knn, kv, k1, k2, alpha, agg, hout, sout, hi, lo, blockIdx.x, sh);
 }
 
 hipError_t launch_propagate(const float* hin, const float* sin, int n, int64_t ld, int64_t cols,
-                            const int32_t* knn_idx, const float* knn_val, int k1, int k2, int alpha, float* hout,
-                            float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s) {
+                            const int32_t* knn_idx, const float* knn_val, int k1, int k2, int alpha, int agg,
+                            float* hout, float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s) {
   if (k2 < 1 || k2 > 256 || (cols & 3) || (ld & 3)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(propagate_kernel, dim3(n), dim3(256), 0, s, hin, sin, ld, cols, knn_idx, knn_val, k1, k2, alpha,
-                     hout, sout, hi, lo);
+                     agg, hout, sout, hi, lo);
   return hipGetLastError();
 }
 
@@ -142,19 +143,20 @@ __global__ __launch_bounds__(256) void first_layer_kernel(const int32_t* __restr
                                                           const uint8_t* __restrict__ mflag,
                                                           const int32_t* __restrict__ off,
                                                           const int32_t* __restrict__ inl, int k1, int k2, int alpha,
-                                                          int64_t ld, float* __restrict__ hout,
+                                                          int agg, int sym, int64_t ld, float* __restrict__ hout,
                                                           float* __restrict__ sout, uint16_t* __restrict__ hi,
                                                           uint16_t* __restrict__ lo) {
   __shared__ FirstShared sh;
-  first_layer_row(knn, kv, mflag, off, inl, k1, k2, alpha, ld, hout, sout, hi, lo, blockIdx.x, sh);
+  first_layer_row(knn, kv, mflag, off, inl, k1, k2, alpha, agg, sym != 0, ld, hout, sout, hi, lo, blockIdx.x, sh);
 }
 
 hipError_t launch_first_layer(const int32_t* knn_idx, const float* knn_val, const uint8_t* mflag,
-                              const int32_t* off, const int32_t* inl, int n, int k1, int k2, int alpha, int64_t ld,
-                              float* hout, float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s) {
-  if (k2 < 1 || k2 > 256 || (ld & 3)) return hipErrorInvalidValue;
+                              const int32_t* off, const int32_t* inl, int n, int k1, int k2, int alpha, int agg,
+                              bool sym, int64_t ld, float* hout, float* sout, uint16_t* hi, uint16_t* lo,
+                              hipStream_t s) {
+  if (k2 < 1 || k2 > 256 || (ld & 3) || agg == RERANK_AGG_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(first_layer_kernel, dim3(n), dim3(256), 0, s, knn_idx, knn_val, mflag, off, inl, k1, k2, alpha,
-                     ld, hout, sout, hi, lo);
+                     agg, (int)sym, ld, hout, sout, hi, lo);
   return hipGetLastError();
 }
 

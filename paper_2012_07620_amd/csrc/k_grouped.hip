@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void g_scatter(const BatchTable* __restrict__ 
     const int p = find_prob(t, GS_SCATTER, item);
     const ProbDesc& D = t->p[p];
     const int64_t pair = (int64_t)(item - t->start[GS_SCATTER][p]) * 256 + threadIdx.x;
-    scatter_pair(D.ki, D.n, D.k1, D.A, D.ldN, D.cnt, pair);
+    scatter_pair(D.ki, D.n, D.k1, D.A, D.ldN, D.cnt, pair, D.node == RERANK_NODE_ADJ_SYM);
   }
 }
 
@@ -128,8 +128,8 @@ __global__ __launch_bounds__(256) void g_first(const BatchTable* __restrict__ t)
   FOR_ITEMS(GS_PROP) {
     const int p = find_prob(t, GS_PROP, item);
     const ProbDesc& D = t->p[p];
-    first_layer_row(D.ki, D.kv, D.mflag, D.off, D.inl, D.k1, D.k2, D.alpha, D.ldN, D.B, D.sa, nullptr, nullptr,
-                    item - t->start[GS_PROP][p], sh);
+    first_layer_row(D.ki, D.kv, D.mflag, D.off, D.inl, D.k1, D.k2, D.alpha, D.agg, D.node == RERANK_NODE_ADJ_SYM,
+                    D.ldN, D.B, D.sa, nullptr, nullptr, item - t->start[GS_PROP][p], sh);
   }
 }
 
@@ -137,7 +137,8 @@ __global__ __launch_bounds__(256) void g_sigma(const BatchTable* __restrict__ t)
   FOR_ITEMS(GS_SIGMA) {
     const int p = find_prob(t, GS_SIGMA, item);
     const ProbDesc& D = t->p[p];
-    astar_sigma_row(D.cnt, D.n, D.k1, D.sa, (item - t->start[GS_SIGMA][p]) * 256 + threadIdx.x);
+    astar_sigma_row(D.cnt, D.n, D.k1, D.sa, (item - t->start[GS_SIGMA][p]) * 256 + threadIdx.x,
+                    D.node == RERANK_NODE_ADJ_SYM);
   }
 }
 
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(256) void g_sigma(const BatchTable* __restrict__ t)
 // between the two spare buffers; the carried norms alternate sa, sb.
 __device__ __forceinline__ void layer_bufs(const ProbDesc& D, int l, const float*& hin, const float*& sin,
                                            float*& hout, float*& sout) {
-  const bool adj = (D.node == RERANK_NODE_ADJ_SYM);
+  const bool adj = (D.node != RERANK_NODE_RAW);
   float* h0 = adj ? D.A : D.xp;
   float* o1 = adj ? D.B : D.A;
   float* o2 = adj ? D.A : D.B;
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(256) void g_prop(const BatchTable* __restrict__ t, 
     float* hout;
     float* sout;
     layer_bufs(D, l, hin, sin, hout, sout);
-    propagate_row(hin, sin, D.ldH, D.ldH, D.ki, D.kv, D.k1, D.k2, D.alpha, hout, sout, nullptr, nullptr,
+    propagate_row(hin, sin, D.ldH, D.ldH, D.ki, D.kv, D.k1, D.k2, D.alpha, D.agg, hout, sout, nullptr, nullptr,
                   item - t->start[GS_PROP][p], sh);
   }
 }
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(256) void g_final(const BatchTable* __restrict__ t)
     const float* h;
     const float* sg;
     if (L == 0) {
-      const bool adj = (D.node == RERANK_NODE_ADJ_SYM);
+      const bool adj = (D.node != RERANK_NODE_RAW);
       h = adj ? D.A : D.xp;
       sg = adj ? D.sa : D.rn;
     } else {
@@ -242,15 +243,17 @@ hipError_t enqueue_grouped(const BatchKey& key, const BatchTable* d_tab, hipStre
       break;
   }
   int first = 0;
-  if (key.node == RERANK_NODE_ADJ_SYM) {
-    GTRY(go(g_fill, kGroupedRowWGs, s, d_tab));  // counts (and A* when layers == 0)
-    if (key.layers == 0) {
+  if (key.node != RERANK_NODE_RAW) {
+    GTRY(go(g_fill, kGroupedRowWGs, s, d_tab));  // counts (and h^(0) when it is dense)
+    if (key.layers == 0 || key.agg == RERANK_AGG_MAX) {
       GTRY(go(g_scatter, kGroupedRowWGs, s, d_tab));
-      GTRY(go(g_sigma, 256, s, d_tab));
+      if (key.layers == 0) GTRY(go(g_sigma, 256, s, d_tab));
     } else {
-      GTRY(go(g_mutual, kGroupedRowWGs, s, d_tab));
-      GTRY(go(g_scan, kMaxBatch, s, d_tab));
-      GTRY(go(g_csr, kGroupedRowWGs, s, d_tab));
+      if (key.node == RERANK_NODE_ADJ_SYM) {
+        GTRY(go(g_mutual, kGroupedRowWGs, s, d_tab));
+        GTRY(go(g_scan, kMaxBatch, s, d_tab));
+        GTRY(go(g_csr, kGroupedRowWGs, s, d_tab));
+      }
       GTRY(go(g_first, kGroupedRowWGs, s, d_tab));
       first = 1;
     }

@@ -27,4 +27,27 @@ hipError_t launch_topk(const float* S, int64_t ldS, int N, int rows, int K, int3
   return hipGetLastError();
 }
 
+// Ranking list (Algorithm 1): per row of D, the r smallest in ascending order.
+template <int R>
+__global__ __launch_bounds__(256) void rank_kernel(const float* __restrict__ D, int q, int g, int r,
+                                                   int32_t* __restrict__ out) {
+  __shared__ uint64_t ring_all[4][128];
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 4 + w;
+  if (i >= q) return;
+  topk_row<R, true>(D, g, g, i, r, out, nullptr, r, ring_all[w]);
+}
+
+hipError_t launch_rank(const float* D, int q, int g, int r, int32_t* out, hipStream_t s) {
+  if (r < 1 || r > 256 || r > g || q < 1) return hipErrorInvalidValue;
+  dim3 grid((q + 3) / 4), block(256);
+  if (r <= 64)
+    hipLaunchKernelGGL(rank_kernel<1>, grid, block, 0, s, D, q, g, r, out);
+  else if (r <= 128)
+    hipLaunchKernelGGL(rank_kernel<2>, grid, block, 0, s, D, q, g, r, out);
+  else
+    hipLaunchKernelGGL(rank_kernel<4>, grid, block, 0, s, D, q, g, r, out);
+  return hipGetLastError();
+}
+
 }  // namespace rr

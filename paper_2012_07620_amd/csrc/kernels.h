@@ -54,18 +54,20 @@ hipError_t launch_take_prefix(const int32_t* cand_idx, const float* cand_val, in
 hipError_t launch_fill_zero(float* buf, int64_t count, hipStream_t s);
 // a4: scatter A* = (A + A^T)/2 into a zeroed N x ldH buffer; cnt[0..n) counts
 // in-degrees and cnt[n..2n) mutual pairs (both zeroed beforehand).
+// sym = false scatters the rows of A instead (H[i][j] = 1, no counts).
 hipError_t launch_astar_scatter(const int32_t* knn_idx, int n, int k1, float* H, int64_t ldH, int32_t* cnt,
-                                hipStream_t s);
-// sigma_i = 1 / |A*_i| from the counts (zero-layer final product).
-hipError_t launch_astar_sigma(const int32_t* cnt, int n, int k1, float* sigma, hipStream_t s);
+                                bool sym, hipStream_t s);
+// sigma_i = 1 / |h^(0)_i| from the counts (A*) or sqrt(k1) (A): zero-layer final product.
+hipError_t launch_astar_sigma(const int32_t* cnt, int n, int k1, float* sigma, bool sym, hipStream_t s);
 
 // a5 + a6: one propagation layer (Eq. 14, sum aggregator) with lazy
 // normalisation: hout_i = sin_i*hin_i + sum_{r<k2} w_ir * sin_{j_r} * hin_{j_r},
 // w_i0 = 1 for the row itself, w_ir = val_ir^alpha; sout_i = 1/|hout_i|.
 // sin == nullptr means all ones. When hi/lo are non-null the row is written
 // as bf16 high/low parts (final bf16x3 product) instead of FP32.
+// agg: rerank_aggregator of Eq. 13.
 hipError_t launch_propagate(const float* hin, const float* sin, int n, int64_t ld, int64_t cols,
-                            const int32_t* knn_idx, const float* knn_val, int k1, int k2, int alpha,
+                            const int32_t* knn_idx, const float* knn_val, int k1, int k2, int alpha, int agg,
                             float* hout, float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s);
 // Sparse first layer (A* never stored densely when layers >= 1):
 // mutual flags of every (i, r) pair and non-mutual in-degree counts ...
@@ -76,9 +78,14 @@ hipError_t launch_scan(const int32_t* innm, int n, int32_t* off, hipStream_t s);
 hipError_t launch_csr(const int32_t* knn_idx, int n, int k1, const uint8_t* mflag, const int32_t* off,
                       int32_t* cursor, int32_t* inl, hipStream_t s);
 // ... and layer 1 built from the sparse A* rows (same result as the dense layer).
+// (sym = false: rows of A; agg: sum or mean)
 hipError_t launch_first_layer(const int32_t* knn_idx, const float* knn_val, const uint8_t* mflag,
-                              const int32_t* off, const int32_t* inl, int n, int k1, int k2, int alpha, int64_t ld,
-                              float* hout, float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s);
+                              const int32_t* off, const int32_t* inl, int n, int k1, int k2, int alpha, int agg,
+                              bool sym, int64_t ld, float* hout, float* sout, uint16_t* hi, uint16_t* lo,
+                              hipStream_t s);
+// Ranking list: per row of D (q rows, stride g), the r smallest positions in
+// ascending order, ties to the lower position (r <= 256).
+hipError_t launch_rank(const float* D, int q, int g, int r, int32_t* out, hipStream_t s);
 // Split rows of an FP32 matrix into bf16 high/low parts (for L = 0 or raw).
 hipError_t launch_split_bf16(const float* h, int n, int64_t ld, uint16_t* hi, uint16_t* lo, hipStream_t s);
 

@@ -129,30 +129,36 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
   const float* csig;
   RR_STAGE(RERANK_STAGE_ADJACENCY, 0);
   int first = 0;  // layers already done
-  if (P.node == RERANK_NODE_ADJ_SYM) {
+  if (P.node != RERANK_NODE_RAW) {
+    const bool sym = (P.node == RERANK_NODE_ADJ_SYM);
     int32_t* cnt = at<int32_t>(ws, P.o_cnt);
     RR_TRY(launch_fill_zero((float*)cnt, (int64_t)P.n * 2, s));
     if (P.sparse_first) {
-      uint8_t* mflag = at<uint8_t>(ws, P.o_mflag);
-      int32_t* off = at<int32_t>(ws, P.o_off);
-      int32_t* inl = at<int32_t>(ws, P.o_inl);
-      RR_TRY(launch_mutual(ki, P.n, P.k1, mflag, cnt, s));
-      RR_TRY(launch_scan(cnt, P.n, off, s));
-      RR_TRY(launch_csr(ki, P.n, P.k1, mflag, off, cnt + P.n, inl, s));
+      uint8_t* mflag = sym ? at<uint8_t>(ws, P.o_mflag) : nullptr;
+      int32_t* off = sym ? at<int32_t>(ws, P.o_off) : nullptr;
+      int32_t* inl = sym ? at<int32_t>(ws, P.o_inl) : nullptr;
+      if (sym) {
+        RR_TRY(launch_mutual(ki, P.n, P.k1, mflag, cnt, s));
+        RR_TRY(launch_scan(cnt, P.n, off, s));
+        RR_TRY(launch_csr(ki, P.n, P.k1, mflag, off, cnt + P.n, inl, s));
+      }
       RR_STAGE(RERANK_STAGE_ADJACENCY, 1);
       RR_STAGE(RERANK_STAGE_PROPAGATE, 0);
       const bool last = (P.layers == 1);
-      RR_TRY(launch_first_layer(ki, kv, mflag, off, inl, P.n, P.k1, P.k2, P.alpha, P.ldN, B, sa,
+      RR_TRY(launch_first_layer(ki, kv, mflag, off, inl, P.n, P.k1, P.k2, P.alpha, P.agg, sym, P.ldN, B, sa,
                                 last ? hi : nullptr, last ? lo : nullptr, s));
       cur = B;
       csig = sa;
       first = 1;
-    } else {
+    } else {  // dense h^(0): zero layers, or the max aggregator
       RR_TRY(launch_fill_zero(A, (int64_t)P.n * P.ldN, s));
-      RR_TRY(launch_astar_scatter(ki, P.n, P.k1, A, P.ldN, cnt, s));
-      RR_TRY(launch_astar_sigma(cnt, P.n, P.k1, sa, s));  // layers == 0 here
+      RR_TRY(launch_astar_scatter(ki, P.n, P.k1, A, P.ldN, cnt, sym, s));
       cur = A;
-      csig = sa;
+      csig = nullptr;  // h^(0) is not normalised
+      if (P.layers == 0) {
+        RR_TRY(launch_astar_sigma(cnt, P.n, P.k1, sa, sym, s));
+        csig = sa;
+      }
       RR_STAGE(RERANK_STAGE_ADJACENCY, 1);
       RR_STAGE(RERANK_STAGE_PROPAGATE, 0);
     }
@@ -166,7 +172,7 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
     float* out = (cur == A) ? B : A;
     float* osig = (csig == sa) ? sb : sa;
     const bool last = (l == P.layers - 1);
-    RR_TRY(launch_propagate(cur, csig, P.n, P.ldH, P.ldH, ki, kv, P.k1, P.k2, P.alpha, out, osig,
+    RR_TRY(launch_propagate(cur, csig, P.n, P.ldH, P.ldH, ki, kv, P.k1, P.k2, P.alpha, P.agg, out, osig,
                             last ? hi : nullptr, last ? lo : nullptr, s));
     cur = out;
     csig = osig;

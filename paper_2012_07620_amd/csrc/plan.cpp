@@ -18,7 +18,9 @@ rerank_status validate_params(const rerank_params* p, std::string* why) {
   if (p->layers < 0 || p->layers > kMaxLayers) return bad(why, "layers must be in [0, 256]");
   if (p->alpha < 0 || p->alpha > kMaxAlpha) return bad(why, "alpha must be an integer in [0, 8]");
   if (p->sim_prec < RERANK_SIM_F32 || p->sim_prec > RERANK_SIM_FP8_E4M3) return bad(why, "unknown sim_prec");
-  if (p->node != RERANK_NODE_ADJ_SYM && p->node != RERANK_NODE_RAW) return bad(why, "unknown node mode");
+  if (p->node != RERANK_NODE_ADJ_SYM && p->node != RERANK_NODE_RAW && p->node != RERANK_NODE_ADJ)
+    return bad(why, "unknown node mode");
+  if (p->aggregator < RERANK_AGG_SUM || p->aggregator > RERANK_AGG_MAX) return bad(why, "unknown aggregator");
   if (p->final_prec != RERANK_FINAL_F32 && p->final_prec != RERANK_FINAL_BF16X3)
     return bad(why, "unknown final_prec");
   if (p->extra_cand < -1) return bad(why, "extra_cand must be >= -1");
@@ -46,6 +48,7 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o) {
   P.prec = (SimPrec)p->sim_prec;
   P.fprec = (FinalPrec)p->final_prec;
   P.node = p->node;
+  P.agg = p->aggregator;
   int extra = p->extra_cand;
   if (extra < 0) extra = (P.prec == SimPrec::F32) ? 8 : (P.prec == SimPrec::BF16 ? 16 : 32);
   int64_t kc = (int64_t)p->k1 + extra;
@@ -80,8 +83,8 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o) {
     P.o_sa = take(n * 4);
     P.o_sb = take(n * 4);
     P.o_cnt = take(n * 8);  // in-degree and mutual counts (or in-degree and cursor), 2n int32
-    P.sparse_first = (P.node == RERANK_NODE_ADJ_SYM && P.layers > 0);
-    if (P.sparse_first) {
+    P.sparse_first = (P.node != RERANK_NODE_RAW && P.layers > 0 && P.agg != RERANK_AGG_MAX);
+    if (P.sparse_first && P.node == RERANK_NODE_ADJ_SYM) {
       P.o_mflag = take(n * P.k1);
       P.o_off = take((n + 1) * 4);
       P.o_inl = take(n * P.k1 * 4);

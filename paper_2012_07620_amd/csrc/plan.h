@@ -20,6 +20,7 @@ struct Plan {
   FinalPrec fprec = FinalPrec::F32;
   bool rescore = false;
   int node = RERANK_NODE_ADJ_SYM;
+  int agg = RERANK_AGG_SUM;
   int64_t ldp = 0;  // fp32 feature copy row stride (elements)
   int64_t ldl = 0;  // low-precision copy row stride (elements)
   int lbytes = 0;   // bytes per low-precision element
@@ -28,7 +29,7 @@ struct Plan {
   // byte offsets into the working set
   size_t o_xp = 0, o_xl = 0, o_rn = 0, o_sl = 0, o_a = 0, o_b = 0, o_ci = 0, o_cv = 0, o_ki = 0, o_kv = 0,
          o_sa = 0, o_sb = 0, o_cnt = 0, o_hi = 0, o_lo = 0, o_mflag = 0, o_off = 0, o_inl = 0;
-  bool sparse_first = false;  // layer 1 built from sparse A* rows (A* mode, layers >= 1)
+  bool sparse_first = false;  // layer 1 built from the sparse A* / A rows (layers >= 1, sum or mean)
   size_t total = 0;
 };
 

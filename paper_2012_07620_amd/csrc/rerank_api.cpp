@@ -119,6 +119,7 @@ void rerank_default_params(rerank_params* p, int32_t n, int32_t q, int32_t d, in
   p->extra_cand = -1;
   p->node = RERANK_NODE_ADJ_SYM;
   p->final_prec = RERANK_FINAL_F32;
+  p->aggregator = RERANK_AGG_SUM;
 }
 
 rerank_status rerank_validate(const rerank_params* p) {
@@ -294,6 +295,27 @@ rerank_status rerank_similarity(rerank_ctx* ctx, const rerank_params* p, const v
     if (e != hipSuccess) *where = "launch_gemm_sim";
     return e;
   });
+}
+
+rerank_status rerank_rank(rerank_ctx* ctx, const float* d_dist, int32_t q, int32_t g, int32_t r, int32_t* d_rank,
+                          void* hip_stream) {
+  if (!ctx || !d_dist || !d_rank || ((uintptr_t)d_dist & 3) || ((uintptr_t)d_rank & 3)) {
+    set_error("ctx / d_dist / d_rank NULL or misaligned");
+    return RERANK_E_INVALID;
+  }
+  if (q < 1 || g < 1 || r < 1 || r > g) {
+    set_error("need q >= 1, g >= 1, 1 <= r <= g");
+    return RERANK_E_INVALID;
+  }
+  if (r > kMaxCand) {
+    set_error("r above 256 is outside this build's limits");
+    return RERANK_E_UNSUPPORTED;
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  e = launch_rank(d_dist, q, g, r, d_rank, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "launch_rank");
+  return RERANK_OK;
 }
 
 rerank_status rerank_stage_times(rerank_ctx* ctx, double* ms_out) {

@@ -1,6 +1,7 @@
 // Per-work-item bodies of the row-parallel kernels (a1, a3, a3b, a4, a6),
 // shared by the direct launches and the persistent grouped launches.
 #pragma once
+#include "../../include/rerank.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -96,7 +97,9 @@ __device__ __forceinline__ void prep_row(const void* __restrict__ x, int i, int 
 // Key = (order-preserving bits of S_ij) << 32 | ~j: one 64-bit compare gives
 // "similarity descending, column ascending" (the tie rule), -0.0 == +0.0.
 // The row's own column gets the largest key, so it is always member 0.
-template <int R>
+// ASC (the ranking list of Algorithm 1): the K smallest values of the row,
+// ties to the lower column, no forced self member; oval may be null.
+template <int R, bool ASC = false>
 __device__ __forceinline__ void topk_row(const float* __restrict__ S, int64_t ldS, int N, int i, int K,
                                          int32_t* __restrict__ oidx, float* __restrict__ oval, int ldo,
                                          uint64_t* ring) {
@@ -117,7 +120,12 @@ __device__ __forceinline__ void topk_row(const float* __restrict__ S, int64_t ld
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int col = c0 + u * 256 + lane * 4;
-      v[u] = (col < N) ? *(const f32x4*)(srow + col) : f32x4{0.f, 0.f, 0.f, 0.f};
+      if (!ASC) {  // S rows: 256-byte aligned, padded to a multiple of 64 columns
+        v[u] = (col < N) ? *(const f32x4*)(srow + col) : f32x4{0.f, 0.f, 0.f, 0.f};
+      } else {  // caller's distance rows: any stride, no padding
+#pragma unroll
+        for (int e = 0; e < 4; e++) v[u][e] = (col + e < N) ? srow[col + e] : 0.f;
+      }
     }
     uint64_t lm = 0;
     if (c0 == 0) {
@@ -126,7 +134,9 @@ __device__ __forceinline__ void topk_row(const float* __restrict__ S, int64_t ld
 #pragma unroll
         for (int e = 0; e < 4; e++) {
           const int col = u * 256 + lane * 4 + e;
-          if (col < N) lm = umax64(lm, col == i ? self_key(i) : sel_key(v[u][e], (uint32_t)col));
+          if (col < N)
+            lm = umax64(lm, ASC ? sel_key(-v[u][e], (uint32_t)col)
+                                : (col == i ? self_key(i) : sel_key(v[u][e], (uint32_t)col)));
         }
       best[0] = lm;
       wave_sort_desc<R>(best);
@@ -138,7 +148,8 @@ __device__ __forceinline__ void topk_row(const float* __restrict__ S, int64_t ld
       for (int e = 0; e < 4; e++) {
         const int col = c0 + u * 256 + lane * 4 + e;
         uint64_t key = 0;
-        if (col < N) key = (col == i) ? self_key(i) : sel_key(v[u][e], (uint32_t)col);
+        if (col < N)
+          key = ASC ? sel_key(-v[u][e], (uint32_t)col) : ((col == i) ? self_key(i) : sel_key(v[u][e], (uint32_t)col));
         const bool pass = key > tau && key != lm;
         const uint64_t m = __ballot(pass);
         if (m) {
@@ -166,7 +177,11 @@ __device__ __forceinline__ void topk_row(const float* __restrict__ S, int64_t ld
     if (e < K) {
       const uint32_t j = key_col(best[r]);
       oidx[(int64_t)i * ldo + e] = (int32_t)j;
-      oval[(int64_t)i * ldo + e] = (j == (uint32_t)i) ? 1.0f : key_val(best[r]);
+      if (ASC) {
+        if (oval) oval[(int64_t)i * ldo + e] = -key_val(best[r]);
+      } else {
+        oval[(int64_t)i * ldo + e] = (j == (uint32_t)i) ? 1.0f : key_val(best[r]);
+      }
     }
   }
 }
@@ -257,11 +272,16 @@ __device__ __forceinline__ void fill_item(float* __restrict__ p, int64_t count, 
 // N(j, k1), else 1/2 (Eq. 10). When both directions exist both writers store
 // the same value, so plain stores suffice. cnt[0..n) counts in-degrees,
 // cnt[n..2n) mutual pairs per row.
+// sym = false (vertex features = rows of A, Eq. 8): H[i][j] = 1 only.
 __device__ __forceinline__ void scatter_pair(const int32_t* __restrict__ knn, int n, int k1, float* __restrict__ H,
-                                             int64_t ldH, int32_t* __restrict__ cnt, int64_t t) {
+                                             int64_t ldH, int32_t* __restrict__ cnt, int64_t t, bool sym = true) {
   if (t >= (int64_t)n * k1) return;
   const int i = (int)(t / k1);
   const int j = knn[t];
+  if (!sym) {
+    H[(int64_t)i * ldH + j] = 1.0f;
+    return;
+  }
   const int32_t* lj = knn + (int64_t)j * k1;
   bool mut = false;
   for (int s = 0; s < k1; s++) mut |= (lj[s] == i);
@@ -273,9 +293,14 @@ __device__ __forceinline__ void scatter_pair(const int32_t* __restrict__ knn, in
 }
 
 // |A*_i|^2 = (#mutual) * 1 + (#one-way) * 1/4, one-way = out-only + in-only.
+// sym = false: every A row holds k1 ones, |A_i| = sqrt(k1).
 __device__ __forceinline__ void astar_sigma_row(const int32_t* __restrict__ cnt, int n, int k1, float* __restrict__ sigma,
-                                                int i) {
+                                                int i, bool sym = true) {
   if (i >= n) return;
+  if (!sym) {
+    sigma[i] = __fdiv_rn(1.0f, __fsqrt_rn((float)k1));
+    return;
+  }
   const int m = cnt[n + i];
   const float sq = (float)m + 0.25f * (float)(k1 - m + cnt[i] - m);
   sigma[i] = __fdiv_rn(1.0f, __fsqrt_rn(sq));
@@ -289,7 +314,8 @@ __device__ __forceinline__ void astar_sigma_row(const int32_t* __restrict__ cnt,
 // and the final product fold it in), so each layer is one streaming pass.
 struct PropShared {
   int nb[256];
-  float cf[256];
+  float cf[256];   // per-member coefficient (sum/mean: residual folded into member 0; max: message only)
+  float res;       // max aggregator: residual coefficient of the row itself
   float red[4];
 };
 
@@ -312,21 +338,32 @@ __device__ __forceinline__ void split_store4(uint16_t* __restrict__ hi, uint16_t
   *(uint2*)(lo + at) = make_uint2(l4[0] | ((uint32_t)l4[1] << 16), l4[2] | ((uint32_t)l4[3] << 16));
 }
 
-// Coefficients of row i: member 0 (the row itself) gets residual + self edge,
-// members r > 0 get e_ir^alpha; each times the carried 1/|u_j| of the input.
+// Coefficients of row i. Message r is e_ir^alpha h_{j_r} (member 0 is the row
+// itself with e_ii = 1), each times the carried 1/|u_j| of its input row.
+// sum: member 0 also takes the residual h_i; mean: messages scaled by 1/k2,
+// residual added to member 0; max: messages kept apart, residual in res.
 __device__ __forceinline__ void load_coefs(const float* __restrict__ sin, const int32_t* __restrict__ knn,
-                                           const float* __restrict__ kv, int k1, int k2, int alpha, int i,
+                                           const float* __restrict__ kv, int k1, int k2, int alpha, int agg, int i,
                                            PropShared& sh) {
   const int tid = threadIdx.x;
   if (tid < k2) {
     const int j = knn[(int64_t)i * k1 + tid];
     float w = 1.0f;
-    if (tid > 0) {  // member 0 is the row itself with e_ii = 1
+    if (tid > 0) {
       const float e = kv[(int64_t)i * k1 + tid];
       for (int a = 0; a < alpha; a++) w *= e;
     }
     const float sj = sin ? sin[j] : 1.0f;
-    sh.cf[tid] = (tid == 0) ? 2.0f * sj : w * sj;
+    const float msg = w * sj;
+    float c = msg;
+    if (agg == RERANK_AGG_MEAN) c = msg / (float)k2;
+    if (tid == 0) {
+      if (agg == RERANK_AGG_MAX)
+        sh.res = sj;
+      else
+        c = sj + c;  // residual + own message (sum: exactly 2 * sj)
+    }
+    sh.cf[tid] = c;
     sh.nb[tid] = j;
   }
   __syncthreads();
@@ -353,22 +390,34 @@ __device__ __forceinline__ void finish_norm(float ss, float* __restrict__ sout, 
 // uses the same order, so both give identical sums).
 __device__ __forceinline__ void propagate_row(const float* __restrict__ hin, const float* __restrict__ sin,
                                               int64_t ld, int64_t cols, const int32_t* __restrict__ knn,
-                                              const float* __restrict__ kv, int k1, int k2, int alpha,
+                                              const float* __restrict__ kv, int k1, int k2, int alpha, int agg,
                                               float* __restrict__ hout, float* __restrict__ sout,
                                               uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int i,
                                               PropShared& sh) {
   const int tid = threadIdx.x;
-  load_coefs(sin, knn, kv, k1, k2, alpha, i, sh);
+  load_coefs(sin, knn, kv, k1, k2, alpha, agg, i, sh);
   float ss = 0.f;
   const int64_t c4 = cols >> 2;
   for (int64_t c = tid; c < c4; c += 256) {
     const f32x4 v0 = ((const f32x4*)(hin + (int64_t)sh.nb[0] * ld))[c];
-    f32x4 acc = {sh.cf[0] * v0.x, sh.cf[0] * v0.y, sh.cf[0] * v0.z, sh.cf[0] * v0.w};
-    for (int r = 1; r < k2; r++) {
-      const f32x4 v = ((const f32x4*)(hin + (int64_t)sh.nb[r] * ld))[c];
-      const float w = sh.cf[r];
-      acc = f32x4{__builtin_fmaf(w, v.x, acc.x), __builtin_fmaf(w, v.y, acc.y), __builtin_fmaf(w, v.z, acc.z),
-                  __builtin_fmaf(w, v.w, acc.w)};
+    const float c0 = sh.cf[0];
+    f32x4 acc = {c0 * v0.x, c0 * v0.y, c0 * v0.z, c0 * v0.w};
+    if (agg == RERANK_AGG_MAX) {
+      for (int r = 1; r < k2; r++) {
+        const f32x4 v = ((const f32x4*)(hin + (int64_t)sh.nb[r] * ld))[c];
+        const float w = sh.cf[r];
+        acc = f32x4{fmaxf(acc.x, w * v.x), fmaxf(acc.y, w * v.y), fmaxf(acc.z, w * v.z), fmaxf(acc.w, w * v.w)};
+      }
+      const float rs = sh.res;
+      acc = f32x4{__builtin_fmaf(rs, v0.x, acc.x), __builtin_fmaf(rs, v0.y, acc.y), __builtin_fmaf(rs, v0.z, acc.z),
+                  __builtin_fmaf(rs, v0.w, acc.w)};
+    } else {
+      for (int r = 1; r < k2; r++) {
+        const f32x4 v = ((const f32x4*)(hin + (int64_t)sh.nb[r] * ld))[c];
+        const float w = sh.cf[r];
+        acc = f32x4{__builtin_fmaf(w, v.x, acc.x), __builtin_fmaf(w, v.y, acc.y), __builtin_fmaf(w, v.z, acc.z),
+                    __builtin_fmaf(w, v.w, acc.w)};
+      }
     }
     if (hi)
       split_store4(hi, lo, (int64_t)i * ld + c * 4, acc);
@@ -447,21 +496,23 @@ struct FirstShared {
   int start[257];  // entries of member r are [start[r], start[r+1])
 };
 
+// sym = false: h^(0) = rows of A (out-list entries only, value 1). The
+// aggregator is sum or mean (max runs the dense layer).
 __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn, const float* __restrict__ kv,
                                                 const uint8_t* __restrict__ mflag, const int32_t* __restrict__ off,
-                                                const int32_t* __restrict__ inl, int k1, int k2, int alpha,
-                                                int64_t ld, float* __restrict__ hout, float* __restrict__ sout,
-                                                uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int i,
-                                                FirstShared& sh) {
+                                                const int32_t* __restrict__ inl, int k1, int k2, int alpha, int agg,
+                                                bool sym, int64_t ld, float* __restrict__ hout,
+                                                float* __restrict__ sout, uint16_t* __restrict__ hi,
+                                                uint16_t* __restrict__ lo, int i, FirstShared& sh) {
   const int tid = threadIdx.x;
-  load_coefs(nullptr, knn, kv, k1, k2, alpha, i, sh.p);
-  // entry counts per member: out-list (k1) + non-mutual in-list
+  load_coefs(nullptr, knn, kv, k1, k2, alpha, agg, i, sh.p);
+  // entry counts per member: out-list (k1) + non-mutual in-list (A* only)
   if (tid == 0) {
     int acc = 0;
     for (int r = 0; r < k2; r++) {
       sh.start[r] = acc;
       const int j = sh.p.nb[r];
-      acc += k1 + (off[j + 1] - off[j]);
+      acc += k1 + (sym ? off[j + 1] - off[j] : 0);
     }
     sh.start[k2] = acc;
   }
@@ -472,12 +523,12 @@ __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn,
       const int j = sh.p.nb[r];
       const int base = sh.start[r];
       const int32_t* lj = knn + (int64_t)j * k1;
-      const uint8_t* fj = mflag + (int64_t)j * k1;
+      const uint8_t* fj = sym ? mflag + (int64_t)j * k1 : nullptr;
       for (int s = tid; s < k1; s += 256) {
         sh.col[base + s] = lj[s];
-        sh.val[base + s] = fj[s] ? 1.0f : 0.5f;
+        sh.val[base + s] = (!sym || fj[s]) ? 1.0f : 0.5f;
       }
-      const int b = off[j], n_in = off[j + 1] - b;
+      const int b = sym ? off[j] : 0, n_in = sym ? off[j + 1] - b : 0;
       for (int s = tid; s < n_in; s += 256) {
         sh.col[base + k1 + s] = inl[b + s];
         sh.val[base + k1 + s] = 0.5f;
@@ -500,12 +551,12 @@ __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn,
       } else {  // very large in-degree: read the entries from memory
         const int j = sh.p.nb[r];
         const int32_t* lj = knn + (int64_t)j * k1;
-        const uint8_t* fj = mflag + (int64_t)j * k1;
+        const uint8_t* fj = sym ? mflag + (int64_t)j * k1 : nullptr;
         for (int s = tid; s < k1; s += 256) {
           const int64_t m = lj[s] - c0;
-          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, fj[s] ? 1.0f : 0.5f, sh.row[m]);
+          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, (!sym || fj[s]) ? 1.0f : 0.5f, sh.row[m]);
         }
-        const int b = off[j], e = off[j + 1];
+        const int b = sym ? off[j] : 0, e = sym ? off[j + 1] : 0;
         for (int s = b + tid; s < e; s += 256) {
           const int64_t m = inl[s] - c0;
           if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, 0.5f, sh.row[m]);

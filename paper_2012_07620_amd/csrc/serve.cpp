@@ -193,7 +193,8 @@ class Server {
     r->dist = dist;
     r->ws_bytes = r->plan.total;
     r->small = p->n <= kSmallN && r->plan.rescore && r->plan.fprec == FinalPrec::F32;
-    r->key = BatchKey{(int)r->plan.prec, r->plan.kc <= 64 ? 1 : (r->plan.kc <= 128 ? 2 : 4), p->layers, p->node};
+    r->key = BatchKey{(int)r->plan.prec, r->plan.kc <= 64 ? 1 : (r->plan.kc <= 128 ? 2 : 4), p->layers, p->node,
+                      p->aggregator};
     r->t_submit = Clock::now();
     {
       std::lock_guard<std::mutex> lk(mu_);
@@ -311,6 +312,7 @@ class Server {
     D.in_bf16 = r.in_bf16;
     D.lbytes = P.lbytes;
     D.node = P.node;
+    D.agg = P.agg;
     D.tiles_sim = 0;
     D.tiles_fin_m = (P.q + 127) / 128;
     D.tiles_fin_n = (P.g + 127) / 128;
@@ -334,9 +336,10 @@ class Server {
     D.sa = (float*)(ws + P.o_sa);
     D.sb = (float*)(ws + P.o_sb);
     D.cnt = (int32_t*)(ws + P.o_cnt);
-    D.mflag = P.sparse_first ? (uint8_t*)(ws + P.o_mflag) : nullptr;
-    D.off = P.sparse_first ? (int32_t*)(ws + P.o_off) : nullptr;
-    D.inl = P.sparse_first ? (int32_t*)(ws + P.o_inl) : nullptr;
+    const bool csr = P.sparse_first && P.node == RERANK_NODE_ADJ_SYM;
+    D.mflag = csr ? (uint8_t*)(ws + P.o_mflag) : nullptr;
+    D.off = csr ? (int32_t*)(ws + P.o_off) : nullptr;
+    D.inl = csr ? (int32_t*)(ws + P.o_inl) : nullptr;
   }
   static constexpr int64_t FILL_ITEM_HOST = 256 * 4 * 8;
 

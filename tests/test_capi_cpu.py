@@ -59,6 +59,8 @@ def _p(**kw):
     (dict(sim_prec="bf16", extra_cand=0), binding.E_INVALID),
     (dict(k1=1000, k2=1000, n=1000), binding.E_UNSUPPORTED),
     (dict(k1=256, k2=7, n=300), binding.OK),
+    (dict(aggregator="mean"), binding.OK),
+    (dict(aggregator="max", node="adj_raw"), binding.OK),
 ])
 def test_validation(kw, status):
     assert binding.validate(_p(**kw)) == status
@@ -86,3 +88,11 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.rerank_create(None, 0, 0, 0) == binding.E_INVALID
     for s in range(8):
         assert lib.rerank_status_str(s)
+
+
+def test_unknown_enums_rejected():
+    lib = binding.library()
+    for field, bad in (("aggregator", 3), ("node", 3), ("sim_prec", 3), ("final_prec", 2)):
+        p = _p()
+        setattr(p, field, bad)
+        assert lib.rerank_validate(ctypes.byref(p)) == binding.E_INVALID, field

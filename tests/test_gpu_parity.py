@@ -170,3 +170,75 @@ def test_final_bf16x3_matches_fp64(gpu_lib, n, q, d, k1, k2, layers, node):
     x = synth.random_features(n, d, seed=n + d + layers, n_ids=8)
     mx, mean, excused = _check_full(gpu_lib, x, q, k1, k2, layers, node=node, final_prec="bf16x3")
     print(f"bf16x3: max err {mx:.2e} mean {mean:.2e}")
+
+
+VARIANTS = [
+    # n, q, d, k1, k2, layers, node, aggregator
+    (300, 60, 48, 12, 5, 1, "adj", "mean"),
+    (300, 60, 48, 12, 5, 2, "adj", "max"),
+    (300, 60, 48, 12, 5, 0, "adj_raw", "sum"),
+    (300, 60, 48, 12, 5, 1, "adj_raw", "sum"),
+    (300, 60, 48, 12, 5, 2, "adj_raw", "mean"),
+    (300, 60, 48, 12, 5, 1, "adj_raw", "max"),
+    (333, 33, 96, 20, 6, 2, "raw", "max"),
+    (333, 33, 96, 20, 6, 1, "raw", "mean"),
+    (1000, 100, 128, 10, 3, 1, "adj", "max"),
+]
+
+
+@pytest.mark.parametrize("n,q,d,k1,k2,layers,node,agg", VARIANTS)
+def test_variants_match_fp64(gpu_lib, n, q, d, k1, k2, layers, node, agg):
+    # Eq. 13 aggregators and the Table 1 node-feature modes
+    x = synth.random_features(n, d, seed=n + 3 * d + layers, n_ids=9)
+    print(f"case {node}/{agg}", flush=True)
+    dg, ki, kv = _run(gpu_lib, x, q, k1, k2, layers, node=node, aggregator=agg)
+    ref = orc.rerank(x, q, k1, k2, layers, node=node, aggregator=agg)
+    f1, f2 = compare_lists(ki, ref.graph, k2)
+    taint = tainted_rows(ref.graph.idx, ki, f1, f2, k2, layers)
+    mx, mean, excused = compare_distances(dg, ref.dist, q, taint, D_TOL_F32)
+    print(f"{node}/{agg} L={layers}: max err {mx:.2e}")
+
+
+def test_hand_example_variants(gpu_lib):
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_5pt.json")))
+    x = np.array(g["x"], dtype=np.float32)
+    for agg, key in (("mean", "D_layers1_mean"), ("max", "D_layers1_max")):
+        dg, _, _ = _run(gpu_lib, x, g["n_query"], g["k1"], g["k2"], 1, aggregator=agg)
+        np.testing.assert_allclose(dg, np.array(g[key]), atol=1e-6)
+    dg, _, _ = _run(gpu_lib, x, g["n_query"], g["k1"], g["k2"], 0, node="adj_raw")
+    np.testing.assert_allclose(dg, np.array(g["D_layers0_A"]), atol=1e-6)
+
+
+@pytest.mark.parametrize("q,g,r", [(1, 1, 1), (7, 300, 5), (33, 1000, 64), (5, 257, 200), (64, 5000, 256)])
+def test_ranking_list(gpu_lib, q, g, r):
+    # seeded distance matrices with many exact ties; the ranking list of
+    # Algorithm 1 (ascending, ties to the lower position) must match exactly
+    import torch
+    from paper_2012_07620_amd import binding
+    rng = np.random.default_rng(q * 1000 + g)
+    d = (np.round(rng.random((q, g)) * 64) / 64).astype(np.float32)
+    d[:, ::7] = 0.0
+    d[:, 1::11] = -0.0
+    got = binding.rank(torch.from_numpy(d).cuda(), r).cpu().numpy()
+    ref = orc.ranking(d.astype(np.float64) + 0.0, r)
+    assert np.array_equal(got, ref)
+
+
+def test_ranking_of_a_rerank(gpu_lib):
+    import torch
+    from paper_2012_07620_amd import binding
+    p = synth.make_problem(synth.TINY)
+    s = p.spec
+    d = binding.run(_dev(p.x32), s.n_query, s.k1, s.k2, s.layers)
+    rk = binding.rank(d, 20).cpu().numpy()
+    ref = orc.rerank(p.x32, s.n_query, s.k1, s.k2, s.layers)
+    dref = ref.dist
+    oref = orc.ranking(dref, 21)
+    for qi in range(s.n_query):
+        # positions whose oracle distances are separated by more than the FP32 error must agree
+        for pos in range(20):
+            a, b = dref[qi, oref[qi, pos]], dref[qi, oref[qi, pos + 1]]
+            prev = dref[qi, oref[qi, pos - 1]] if pos else -np.inf
+            if b - a > 1e-5 and a - prev > 1e-5:
+                assert rk[qi, pos] == oref[qi, pos]

@@ -34,20 +34,20 @@ def _dev(p):
     return torch.from_numpy(p.x32).cuda()
 
 
-def _solo(probs, prec="f32"):
+def _solo(probs, prec="f32", **kw):
     import torch
     from paper_2012_07620_amd import binding
     ctx = binding.Context(0)
     outs = []
     for p in probs:
         s = p.spec
-        outs.append(binding.run(_dev(p), s.n_query, s.k1, s.k2, s.layers, sim_prec=prec, ctx=ctx).cpu().numpy())
+        outs.append(binding.run(_dev(p), s.n_query, s.k1, s.k2, s.layers, sim_prec=prec, ctx=ctx, **kw).cpu().numpy())
     torch.cuda.synchronize()
     ctx.close()
     return outs
 
 
-def _serve(ctx, probs, prec="f32"):
+def _serve(ctx, probs, prec="f32", **kw):
     import torch
     from paper_2012_07620_amd import binding
     xs = [_dev(p) for p in probs]
@@ -56,7 +56,7 @@ def _serve(ctx, probs, prec="f32"):
     tickets = []
     for p, x, o in zip(probs, xs, outs):
         s = p.spec
-        tickets.append(binding.submit(ctx, x, o, s.n_query, s.k1, s.k2, s.layers, sim_prec=prec))
+        tickets.append(binding.submit(ctx, x, o, s.n_query, s.k1, s.k2, s.layers, sim_prec=prec, **kw))
     return xs, outs, tickets
 
 
@@ -150,4 +150,18 @@ def test_injected_allocation_failure_fails_one_request(gpu_lib):
     for st, o, ref in zip(statuses, outs, solo):
         if st == binding.OK:
             assert np.array_equal(o.cpu().numpy(), ref)
+    ctx.close()
+
+
+@pytest.mark.parametrize("kw", [dict(aggregator="mean"), dict(aggregator="max"), dict(node="adj_raw")])
+def test_variants_same_alone_and_in_the_mix(gpu_lib, kw):
+    from paper_2012_07620_amd import binding
+    probs = _requests(51, 6, 300, 2500) + _requests(52, 1, 9000, 9500, dims=(128,))
+    solo = _solo(probs, **kw)
+    ctx = binding.Context(0)
+    xs, outs, tickets = _serve(ctx, probs, **kw)
+    for t in tickets:
+        binding.wait(ctx, t)
+    for o, ref in zip(outs, solo):
+        assert np.array_equal(o.cpu().numpy(), ref)
     ctx.close()
