@@ -65,14 +65,23 @@ def roofline_entry(stage, unit, amount, ms, prec):
     return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": ach / PEAK["hbm_gbs"]}
 
 
-def kernel_src_hash() -> str:
-    import glob
+# Source files each stage's kernels are compiled from: measured counters stay
+# valid while these files are unchanged.
+KERNEL_SOURCES = {
+    "similarity": ("common.h", "gemm_body.h", "k_gemm.hip"),
+    "final": ("common.h", "gemm_body.h", "k_gemm.hip"),
+    "topk": ("common.h", "rows_body.h", "k_topk.hip"),
+    "rescore": ("common.h", "rows_body.h", "k_graph.hip"),
+    "propagate": ("common.h", "rows_body.h", "k_graph.hip"),
+    "prep": ("common.h", "rows_body.h", "k_prep.hip"),
+}
+
+
+def kernel_src_hash(role: str) -> str:
     import hashlib
-    src = sorted(glob.glob(os.path.join(ROOT, "paper_2012_07620_amd", "csrc", "*.h")) +
-                 glob.glob(os.path.join(ROOT, "paper_2012_07620_amd", "csrc", "*.hip")))
     h = hashlib.sha256()
-    for f in src:
-        with open(f, "rb") as fh:
+    for name in KERNEL_SOURCES[role]:
+        with open(os.path.join(ROOT, "paper_2012_07620_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -87,7 +96,7 @@ def measured_traffic(workload: str, path: str, role: str):
     with open(f) as fh:
         t = json.load(fh)
     k = t.get("kernels", {}).get(role)
-    if k is None or t.get("kernel_src_sha256") != kernel_src_hash():
+    if k is None or k.get("src_sha256") != kernel_src_hash(role):
         return None
     return {"read_bytes": k["read_bytes"], "write_bytes": k["write_bytes"],
             "bytes": k["read_bytes"] + k["write_bytes"], "source": os.path.relpath(f, ROOT)}
