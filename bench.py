@@ -234,7 +234,9 @@ def main() -> int:
     lowp = {}
     if not args.no_lowp:
         for name, prec, fprec in (("bf16", "bf16", "f32"), ("fp8", "fp8", "f32"),
-                                  ("f32_final_bf16x3", "f32", "bf16x3"), ("bf16_final_bf16x3", "bf16", "bf16x3")):
+                                  ("f32_final_bf16x3", "f32", "bf16x3"), ("bf16_final_bf16x3", "bf16", "bf16x3"),
+                                  ("f32_final_sparse", "f32", "sparse"), ("bf16_final_sparse", "bf16", "sparse"),
+                                  ("fp8_final_sparse", "fp8", "sparse")):
             log(f"timing {name} path")
             out_l = torch.empty_like(out)
             ms_l, st_l = time_path(binding, torch, ctx, x, spec, prec, args.steps, args.warmup, out_l, fprec)
@@ -248,6 +250,13 @@ def main() -> int:
                 entry["final_roofline"] = {"bound": "mfma", "achieved": fl, "peak": PEAK["bf16_mfma_tflops"] / 3,
                                            "unit": "TFLOP/s (FP32-equivalent; 3 bf16 products per FP32 product)",
                                            "frac": fl / (PEAK["bf16_mfma_tflops"] / 3)}
+            if fprec == "sparse":
+                # given the dense last layer, the sparse product must at least read H once and write D
+                nbytes = 4.0 * spec.n * spec.n + 4.0 * spec.n_query * spec.n_gallery
+                gbs = nbytes / (st_l["final"] * 1e-3) / 1e9
+                entry["final_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                                           "frac": gbs / PEAK["hbm_gbs"],
+                                           "algorithmic_bytes": nbytes}
             lowp[name] = entry
 
     if args.calibrate_copy:
@@ -299,7 +308,7 @@ def main() -> int:
         "stages_ms": stages,
         "phase_ms": {"phase1_graph": phase1, "phase2_propagate_rank": phase2},
         "stage_roofline": roof,
-        "lowp": lowp,
+        "variants": lowp,
         "parity": parity,
         "serving": serving,
     }

@@ -76,8 +76,16 @@ typedef enum { RERANK_AGG_SUM = 0, RERANK_AGG_MEAN = 1, RERANK_AGG_MAX = 2 } rer
 /* Arithmetic of the final query x gallery product. F32 is plain FP32 matrix
  * cores; BF16X3 splits each FP32 operand into a high and a low bfloat16 part
  * and sums the three leading partial products on bfloat16 matrix cores with
- * FP32 accumulation (relative error of each product about 2^-16). */
-typedef enum { RERANK_FINAL_F32 = 0, RERANK_FINAL_BF16X3 = 1 } rerank_final_prec;
+ * FP32 accumulation (relative error of each product about 2^-16). SPARSE
+ * multiplies only the non-zeros of the refined features: A* rows hold O(k1)
+ * non-zeros (Eq. 9-11) and each layer of Eq. 14 widens a row only to its k2
+ * neighbours' supports, so query q's distances are an FP32 sum over q's
+ * non-zero columns c, in ascending c, of h_q[c] times column c of the
+ * gallery features. Not available with RERANK_NODE_RAW (dense features).
+ * When the compacted rows would exceed the spare N x N buffer (average row
+ * density above 1/4) the FP32 matrix-core product runs instead, decided on
+ * the device. */
+typedef enum { RERANK_FINAL_F32 = 0, RERANK_FINAL_BF16X3 = 1, RERANK_FINAL_SPARSE = 2 } rerank_final_prec;
 
 typedef struct {
   int32_t n;          /* N = Q + G rows of X_u, N >= 2 */

@@ -7,7 +7,7 @@
 namespace rr {
 
 enum class SimPrec : int { F32 = 0, BF16 = 1, FP8 = 2 };
-enum class FinalPrec : int { F32 = 0, BF16X3 = 1 };
+enum class FinalPrec : int { F32 = 0, BF16X3 = 1, SPARSE = 2 };
 
 // Row stride (elements) of the padded K-major copies the GEMMs read: every
 // row is a whole number of 128-byte stages.
@@ -86,6 +86,15 @@ hipError_t launch_first_layer(const int32_t* knn_idx, const float* knn_val, cons
 // Ranking list: per row of D (q rows, stride g), the r smallest positions in
 // ascending order, ties to the lower position (r <= 256).
 hipError_t launch_rank(const float* D, int q, int g, int r, int32_t* out, hipStream_t s);
+// a7, sparse form: D[q][g] = 1 - sq[q] * sg[g] * <h_q, h_{Q+g}> from the
+// non-zeros of H (n rows, row stride ld, columns < ld). `pool` (pool_bytes,
+// must not overlap H) holds the compacted rows; `ints` holds
+// sparse_final_ints(n, ld) int32 of counters. When the non-zeros exceed
+// pool_bytes / 16 the FP32 matrix-core product computes D instead (decided on
+// the device). D is q x (n - q), row stride n - q.
+inline int64_t sparse_final_ints(int64_t n, int64_t ld) { return 2 * n + 1 + 3 * ld + 1 + 2; }
+hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const float* sigma, float* dist, void* pool,
+                               int64_t pool_bytes, int32_t* ints, hipStream_t s);
 // Split rows of an FP32 matrix into bf16 high/low parts (for L = 0 or raw).
 hipError_t launch_split_bf16(const float* h, int n, int64_t ld, uint16_t* hi, uint16_t* lo, hipStream_t s);
 

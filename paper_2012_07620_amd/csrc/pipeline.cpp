@@ -117,7 +117,7 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
   float* xp = at<float>(ws, P.o_xp);
   float* rn = at<float>(ws, P.o_rn);
   float* A = at<float>(ws, P.o_a);
-  float* B = P.layers > 0 ? at<float>(ws, P.o_b) : nullptr;
+  float* B = (P.layers > 0 || P.fprec == FinalPrec::SPARSE) ? at<float>(ws, P.o_b) : nullptr;
   int32_t* ki = at<int32_t>(ws, P.o_ki);
   float* kv = at<float>(ws, P.o_kv);
   float* sa = at<float>(ws, P.o_sa);
@@ -183,6 +183,10 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
   const float* hg = cur + (size_t)P.q * P.ldH;
   if (P.fprec == FinalPrec::F32) {
     RR_TRY(launch_gemm_dist(hq, P.q, hg, P.g, P.ldH, P.ldH, csig, csig + P.q, dist, P.g, s));
+  } else if (P.fprec == FinalPrec::SPARSE) {  // adjacency features: cur is A or B, the other one is free
+    float* pool = (cur == A) ? B : A;
+    RR_TRY(launch_sparse_final(cur, P.n, P.q, P.ldH, csig, dist, pool, (int64_t)P.n * P.ldH * 4,
+                               at<int32_t>(ws, P.o_sp), s));
   } else {
     if (P.layers == 0) RR_TRY(launch_split_bf16(cur, P.n, P.ldH, hi, lo, s));
     RR_TRY(launch_gemm_dist_bf16x3(hi, lo, P.q, hi + (size_t)P.q * P.ldH, lo + (size_t)P.q * P.ldH, P.g, P.ldH,

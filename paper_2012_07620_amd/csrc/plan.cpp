@@ -21,8 +21,9 @@ rerank_status validate_params(const rerank_params* p, std::string* why) {
   if (p->node != RERANK_NODE_ADJ_SYM && p->node != RERANK_NODE_RAW && p->node != RERANK_NODE_ADJ)
     return bad(why, "unknown node mode");
   if (p->aggregator < RERANK_AGG_SUM || p->aggregator > RERANK_AGG_MAX) return bad(why, "unknown aggregator");
-  if (p->final_prec != RERANK_FINAL_F32 && p->final_prec != RERANK_FINAL_BF16X3)
-    return bad(why, "unknown final_prec");
+  if (p->final_prec < RERANK_FINAL_F32 || p->final_prec > RERANK_FINAL_SPARSE) return bad(why, "unknown final_prec");
+  if (p->final_prec == RERANK_FINAL_SPARSE && p->node == RERANK_NODE_RAW)
+    return bad(why, "the sparse final product needs adjacency node features (node != RAW)");
   if (p->extra_cand < -1) return bad(why, "extra_cand must be >= -1");
   if (p->extra_cand == 0 && p->sim_prec != RERANK_SIM_F32)
     return bad(why, "low-precision similarity needs FP32 re-scoring (extra_cand != 0)");
@@ -79,7 +80,8 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o) {
   P.o_ki = take(n * P.k1 * 4);
   P.o_kv = take(n * P.k1 * 4);
   if (!knn_only) {
-    if (P.layers > 0) P.o_b = take(n * P.ldH * 4);
+    // the sparse final product compacts into the feature buffer the last layer did not write
+    if (P.layers > 0 || P.fprec == FinalPrec::SPARSE) P.o_b = take(n * P.ldH * 4);
     P.o_sa = take(n * 4);
     P.o_sb = take(n * 4);
     P.o_cnt = take(n * 8);  // in-degree and mutual counts (or in-degree and cursor), 2n int32
@@ -89,6 +91,7 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o) {
       P.o_off = take((n + 1) * 4);
       P.o_inl = take(n * P.k1 * 4);
     }
+    if (P.fprec == FinalPrec::SPARSE) P.o_sp = take(sparse_final_ints(P.n, P.ldN) * 4);
     if (P.fprec == FinalPrec::BF16X3) {
       P.o_hi = take(n * P.ldH * 2);
       P.o_lo = take(n * P.ldH * 2);

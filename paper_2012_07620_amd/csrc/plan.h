@@ -28,7 +28,7 @@ struct Plan {
   int64_t ldH = 0;  // propagated feature row stride (ldN, or ldp in raw mode)
   // byte offsets into the working set
   size_t o_xp = 0, o_xl = 0, o_rn = 0, o_sl = 0, o_a = 0, o_b = 0, o_ci = 0, o_cv = 0, o_ki = 0, o_kv = 0,
-         o_sa = 0, o_sb = 0, o_cnt = 0, o_hi = 0, o_lo = 0, o_mflag = 0, o_off = 0, o_inl = 0;
+         o_sa = 0, o_sb = 0, o_cnt = 0, o_hi = 0, o_lo = 0, o_mflag = 0, o_off = 0, o_inl = 0, o_sp = 0;
   bool sparse_first = false;  // layer 1 built from the sparse A* / A rows (layers >= 1, sum or mean)
   size_t total = 0;
 };

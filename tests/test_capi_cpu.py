@@ -92,7 +92,24 @@ def test_null_arguments_are_rejected_without_a_device():
 
 def test_unknown_enums_rejected():
     lib = binding.library()
-    for field, bad in (("aggregator", 3), ("node", 3), ("sim_prec", 3), ("final_prec", 2)):
+    for field, bad in (("aggregator", 3), ("node", 3), ("sim_prec", 3), ("final_prec", 3), ("final_prec", -1)):
         p = _p()
         setattr(p, field, bad)
         assert lib.rerank_validate(ctypes.byref(p)) == binding.E_INVALID, field
+
+
+def test_sparse_final_needs_adjacency_features():
+    lib = binding.library()
+    for node, want in (("adj", binding.OK), ("adj_raw", binding.OK), ("raw", binding.E_INVALID)):
+        p = binding.make_params(1000, 100, 64, 20, 6, 1, node=node, final_prec="sparse")
+        assert lib.rerank_validate(ctypes.byref(p)) == want, node
+
+
+def test_sparse_final_workspace_holds_both_feature_buffers_and_counters():
+    # zero layers: the sparse product still needs the second N x N buffer for its compacted rows
+    lib = binding.library()
+    n = 1000
+    dense = binding.workspace_bytes(binding.make_params(n, 100, 64, 20, 6, 0))
+    sparse = binding.workspace_bytes(binding.make_params(n, 100, 64, 20, 6, 0, final_prec="sparse"))
+    ldn = (n + 63) // 64 * 64
+    assert sparse - dense >= n * ldn * 4 + (2 * n + 3 * ldn + 4) * 4

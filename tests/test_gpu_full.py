@@ -31,6 +31,22 @@ def test_mid_final_bf16x3(gpu_lib, mid):
     assert err2.max() <= D_TOL["bf16"]
 
 
+def test_mid_final_sparse(gpu_lib, mid):
+    # sparse final product: same distances, FP32 tolerance
+    p, ref = mid
+    s = p.spec
+    for prec in ("f32", "bf16"):
+        d, ki, kv = _gpu(p, prec, final_prec="sparse")
+        err = np.abs(d - ref.dist)
+        print(f"{prec} sim + sparse final: D vs FP64 max {err.max():.3e} mean {err.mean():.3e}", flush=True)
+        if prec == "f32":
+            f1, f2 = compare_lists(ki, ref.graph, s.k2)
+            taint = tainted_rows(ref.graph.idx, ki, f1, f2, s.k2, s.layers)
+            compare_distances(d, ref.dist, s.n_query, taint, D_TOL["f32"])
+        else:
+            assert err.max() <= D_TOL["bf16"]
+
+
 @pytest.fixture(scope="module")
 def mid():
     p = synth.make_problem(synth.MID)
@@ -88,13 +104,14 @@ def test_large_sampled(gpu_lib):
     w = orc.edge_weights(g.idx, g.val, s.k2, 2)
     h = orc.propagate(h0, w, s.layers)
     dref = orc.distances(h, s.n_query, q_rows=q_rows)
-    for prec in ("f32", "bf16"):
-        d, ki, kv = _gpu(p, prec)
+    for prec, fprec in (("f32", "f32"), ("bf16", "f32"), ("f32", "sparse")):
+        print(f"case {s.name} prec={prec} final={fprec}", flush=True)
+        d, ki, kv = _gpu(p, prec, final_prec=fprec)
         f1, f2 = compare_lists(ki, g, s.k2) if prec == "f32" else (None, None)
         if prec == "f32":
             taint = tainted_rows(g.idx, ki, f1, f2, s.k2, s.layers)
             mx, mean, excused = compare_distances(d[q_rows], dref, s.n_query, taint, D_TOL[prec], q_rows=q_rows)
-            print(f"large f32: flipped tied rows {len(f1)}, D max err {mx:.2e} mean {mean:.2e}, excused {excused}")
+            print(f"large f32/{fprec}: flipped tied rows {len(f1)}, D max err {mx:.2e} mean {mean:.2e}, excused {excused}")
         else:
             same = np.mean(np.all(np.sort(ki, 1) == np.sort(g.idx, 1), axis=1))
             err = np.abs(d[q_rows] - dref)

@@ -1,0 +1,113 @@
+"""Sparse final product (RERANK_FINAL_SPARSE) against the FP64 oracle.
+
+The sparse product computes the same distances as the dense one (the cosine
+of the refined features, Section 3.3 and Algorithm 1) from the non-zeros
+only, so it is held to the FP32 path's tolerance. Cases cover several
+gallery chunks of the LDS accumulator, queries with more non-zeros than one
+staging pass, columns longer than one wave, zero layers, the aggregator and
+node-feature variants, and rows too dense for the compacted buffers (where
+the matrix-core product must run instead: bit-identical to the dense path).
+Every call goes through the C-ABI library."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import rerank_oracle as orc
+from paper_2012_07620_amd import synth
+from tests.parity import compare_distances, compare_lists, tainted_rows
+
+pytestmark = pytest.mark.gpu
+
+D_TOL_F32 = 1e-4
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _run(x, q, k1, k2, layers, **kw):
+    import torch
+    from paper_2012_07620_amd import binding
+    d, ki, kv = binding.run(_dev(x), q, k1, k2, layers, return_knn=True, **kw)
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), ki.cpu().numpy(), kv.cpu().numpy()
+
+
+def _check(x, q, k1, k2, layers, node="adj", agg="sum", alpha=2):
+    print(f"case sparse n={len(x)} q={q} d={x.shape[1]} k1={k1} k2={k2} L={layers} node={node} agg={agg}", flush=True)
+    dg, ki, kv = _run(x, q, k1, k2, layers, node=node, aggregator=agg, alpha=alpha, final_prec="sparse")
+    ref = orc.rerank(x, q, k1, k2, layers, alpha=alpha, node=node, aggregator=agg)
+    f1, f2 = compare_lists(ki, ref.graph, k2)
+    taint = tainted_rows(ref.graph.idx, ki, f1, f2, k2, layers)
+    mx, mean, excused = compare_distances(dg, ref.dist, q, taint, D_TOL_F32)
+    print(f"sparse: max err {mx:.2e} mean {mean:.2e} excused {excused}")
+    return dg
+
+
+SPARSE_CASES = [
+    # n, q, d, k1, k2, layers, node, agg, n_ids
+    (2, 1, 3, 1, 1, 0, "adj", "sum", 0),
+    (5, 2, 2, 2, 1, 1, "adj", "sum", 0),
+    (1000, 100, 128, 10, 3, 1, "adj", "sum", 50),
+    (1000, 100, 128, 10, 3, 0, "adj", "sum", 50),
+    (1000, 100, 128, 10, 3, 3, "adj", "sum", 50),
+    (300, 60, 48, 12, 5, 1, "adj", "mean", 9),
+    (300, 60, 48, 12, 5, 2, "adj", "max", 9),
+    (300, 60, 48, 12, 5, 1, "adj_raw", "sum", 9),
+    (300, 60, 48, 12, 5, 0, "adj_raw", "sum", 9),
+    (2049, 333, 64, 20, 6, 2, "adj", "sum", 60),
+    (8000, 700, 64, 120, 8, 1, "adj", "sum", 0),  # rows of ~1000 non-zeros: several staging passes
+    (20000, 300, 32, 10, 3, 1, "adj", "sum", 400),  # gallery of 19700: two accumulator chunks
+]
+
+
+@pytest.mark.parametrize("n,q,d,k1,k2,layers,node,agg,n_ids", SPARSE_CASES)
+def test_sparse_final_matches_fp64(gpu_lib, n, q, d, k1, k2, layers, node, agg, n_ids):
+    x = synth.random_features(n, d, seed=5 * n + d + layers, n_ids=n_ids)
+    _check(x, q, k1, k2, layers, node=node, agg=agg)
+
+
+def test_sparse_final_hand_example(gpu_lib):
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_5pt.json")))
+    x = np.array(g["x"], dtype=np.float32)
+    for layers, key in ((0, "D_layers0"), (1, "D_layers1")):
+        dg, ki, _ = _run(x, g["n_query"], g["k1"], g["k2"], layers, final_prec="sparse")
+        assert ki.tolist() == g["lists"]
+        np.testing.assert_allclose(dg, np.array(g[key]), atol=1e-6)
+
+
+@pytest.mark.parametrize("n,q,d,k1,k2,layers", [(200, 50, 17, 200, 7, 1), (700, 300, 24, 100, 10, 2)])
+def test_dense_rows_fall_back_to_the_matrix_core_product(gpu_lib, n, q, d, k1, k2, layers):
+    # k1 = n makes every A* row full: the compacted rows cannot fit and the gated
+    # dense product must produce exactly the dense path's bits
+    x = synth.random_features(n, d, seed=n * 7 + d, n_ids=7)
+    sparse, _, _ = _run(x, q, k1, k2, layers, final_prec="sparse")
+    dense, _, _ = _run(x, q, k1, k2, layers)
+    if k1 == n:
+        assert np.array_equal(sparse, dense)
+    ref = orc.rerank(x, q, k1, k2, layers)
+    assert np.abs(sparse - ref.dist).max() <= D_TOL_F32
+
+
+def test_sparse_final_repeat_runs_bit_identical(gpu_lib):
+    # the CSC entries are placed with atomics; the sums must not depend on that order
+    import torch
+    from paper_2012_07620_amd import binding
+    x = _dev(synth.random_features(8000, 64, seed=77, n_ids=0))
+    outs = [binding.run(x, 700, 120, 8, 1, final_prec="sparse") for _ in range(3)]
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+def test_sparse_final_with_low_precision_similarity(gpu_lib):
+    p = synth.make_problem(synth.TINY)
+    s = p.spec
+    for prec in ("bf16", "fp8"):
+        dg, _, _ = _run(p.x32, s.n_query, s.k1, s.k2, s.layers, sim_prec=prec, final_prec="sparse")
+        ref = orc.rerank(p.x32, s.n_query, s.k1, s.k2, s.layers)
+        err = np.abs(dg - ref.dist).max()
+        print(f"{prec} + sparse final: D vs FP64 max {err:.2e}")
+        assert err <= 2e-2
