@@ -82,9 +82,13 @@ typedef enum { RERANK_AGG_SUM = 0, RERANK_AGG_MEAN = 1, RERANK_AGG_MAX = 2 } rer
  * neighbours' supports, so query q's distances are an FP32 sum over q's
  * non-zero columns c, in ascending c, of h_q[c] times column c of the
  * gallery features. Not available with RERANK_NODE_RAW (dense features).
- * When the compacted rows would exceed the spare N x N buffer (average row
- * density above 1/4) the FP32 matrix-core product runs instead, decided on
- * the device. */
+ * With the sum or mean aggregator and layers >= 1 the layers themselves are
+ * kept as CSR rows (each row in a slot sized by its members' entry counts),
+ * so no dense N x N row is written; a layer whose slots would not fit in an
+ * N x N buffer is written densely instead. Dense last layers are compacted
+ * before the product; when the compacted rows would exceed the spare N x N
+ * buffer (average row density above 1/4) the FP32 matrix-core product runs
+ * instead. All of these choices are made on the device. */
 typedef enum { RERANK_FINAL_F32 = 0, RERANK_FINAL_BF16X3 = 1, RERANK_FINAL_SPARSE = 2 } rerank_final_prec;
 
 typedef struct {
@@ -121,10 +125,15 @@ rerank_status rerank_workspace_bytes(const rerank_params* p, size_t* bytes);
  * the direct calls (on the call's stream) so rerank_stage_times can report
  * per-stage device time; it adds no synchronisation. */
 #define RERANK_CTX_STAGE_TIMING 1u
+/* DENSE_LAYERS: with RERANK_FINAL_SPARSE, write the propagation layers as dense
+ * rows and compact the last one before the product (the default keeps them as
+ * CSR rows, see rerank_final_prec). The distances are the same either way. */
+#define RERANK_CTX_DENSE_LAYERS 2u
 
 /* Create a context on HIP device `hip_device`. The context never holds more
  * than `hbm_budget_bytes` of device memory (0 = 90% of the device's free
- * memory at creation). flags: 0 or RERANK_CTX_STAGE_TIMING. */
+ * memory at creation). flags: 0 or an OR of RERANK_CTX_STAGE_TIMING and
+ * RERANK_CTX_DENSE_LAYERS. */
 rerank_status rerank_create(rerank_ctx** out, int hip_device, size_t hbm_budget_bytes, uint32_t flags);
 
 /* Wait for all work of the context, stop its scheduler, free its memory. */

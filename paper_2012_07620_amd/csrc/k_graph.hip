@@ -145,18 +145,21 @@ __global__ __launch_bounds__(256) void first_layer_kernel(const int32_t* __restr
                                                           const int32_t* __restrict__ inl, int k1, int k2, int alpha,
                                                           int agg, int sym, int64_t ld, float* __restrict__ hout,
                                                           float* __restrict__ sout, uint16_t* __restrict__ hi,
-                                                          uint16_t* __restrict__ lo) {
+                                                          uint16_t* __restrict__ lo, SlOut sl, int use_sl) {
   __shared__ FirstShared sh;
-  first_layer_row(knn, kv, mflag, off, inl, k1, k2, alpha, agg, sym != 0, ld, hout, sout, hi, lo, blockIdx.x, sh);
+  first_layer_row(knn, kv, mflag, off, inl, k1, k2, alpha, agg, sym != 0, ld, hout, sout, hi, lo, blockIdx.x, sh,
+                  use_sl ? &sl : nullptr);
 }
 
 hipError_t launch_first_layer(const int32_t* knn_idx, const float* knn_val, const uint8_t* mflag,
                               const int32_t* off, const int32_t* inl, int n, int k1, int k2, int alpha, int agg,
                               bool sym, int64_t ld, float* hout, float* sout, uint16_t* hi, uint16_t* lo,
-                              hipStream_t s) {
+                              const SlOut* sl, hipStream_t s) {
   if (k2 < 1 || k2 > 256 || (ld & 3) || agg == RERANK_AGG_MAX) return hipErrorInvalidValue;
+  if (sl && (hi || !sl->rows.col || !sl->gate || !sl->prev)) return hipErrorInvalidValue;
+  const SlOut none{};
   hipLaunchKernelGGL(first_layer_kernel, dim3(n), dim3(256), 0, s, knn_idx, knn_val, mflag, off, inl, k1, k2, alpha,
-                     agg, (int)sym, ld, hout, sout, hi, lo);
+                     agg, (int)sym, ld, hout, sout, hi, lo, sl ? *sl : none, sl ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -18,18 +18,111 @@
 // chunk, so the column loop needs no block barrier; within a wave LDS
 // accesses complete in issue order.
 //
-// The compacted rows live in a spare N x N feature buffer (16 bytes per
-// non-zero: CSR and CSC). If they do not fit, a device flag makes every
-// sparse kernel return at once and the FP32 matrix-core product, launched
-// behind them and gated on the same flag, computes D. No host round trip.
+// When the layers were kept as CSR rows (sparse layers) step 1 is skipped.
+// Otherwise the compacted rows live in a spare N x N feature buffer (16 bytes
+// per non-zero: CSR and CSC). If they do not fit, a device-side selection
+// makes every sparse kernel return at once and the FP32 matrix-core product,
+// launched behind them and gated on the same selection, computes D. No host
+// round trip.
+//
+// The sparse layers themselves (slot bounds, layers >= 2 from CSR rows, the
+// gated dense layer) are launched from here too; their row bodies are in
+// rows_body.h.
 #include "gemm_body.h"
 #include "kernels.h"
+#include "rows_body.h"
 
 namespace rr {
 
+// ================================================================ sparse layers
+// Slot bound of every row of layer l, summed into gates[l].total (one atomic
+// per wave).
+__global__ __launch_bounds__(256) void sl_bound_kernel(const int32_t* __restrict__ knn, int n, int k1, int k2,
+                                                       int first, int sym, const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ cnt_prev, SlGate* gates, int l) {
+  if (gates[l - 1].dense) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  unsigned long long b = 0;
+  if (i < n) {
+    for (int r = 0; r < k2; r++) {
+      const int j = knn[(int64_t)i * k1 + r];
+      b += first ? (unsigned long long)(k1 + (sym ? off[j + 1] - off[j] : 0)) : (unsigned long long)cnt_prev[j];
+    }
+    if (b > (unsigned long long)n) b = n;
+  }
+  for (int m = 32; m > 0; m >>= 1) b += shfl_xor_u64(b, m);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(&gates[l].total, b);
+}
+
+hipError_t launch_sl_bounds(const int32_t* knn_idx, int n, int k1, int k2, bool first, bool sym, const int32_t* off,
+                            const int32_t* cnt_prev, SlGate* gates, int l, hipStream_t s) {
+  if (l < 1 || k2 < 1 || k2 > k1 || (first && sym && !off) || (!first && !cnt_prev)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sl_bound_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, knn_idx, n, k1, k2,
+                     (int)first, (int)sym, off, cnt_prev, gates, l);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void sparse_prop_kernel(SlRows in, const float* __restrict__ sin,
+                                                          const int32_t* __restrict__ knn,
+                                                          const float* __restrict__ kv, int k1, int k2, int alpha,
+                                                          int agg, int64_t ld, float* __restrict__ hout,
+                                                          float* __restrict__ sout, SlOut out) {
+  if (out.prev->dense) return;
+  __shared__ FirstShared sh;
+  sparse_prop_row(in, sin, knn, kv, k1, k2, alpha, agg, ld, hout, sout, &out, blockIdx.x, sh);
+}
+
+hipError_t launch_sparse_prop(SlRows in, const float* sin, const int32_t* knn_idx, const float* knn_val, int n,
+                              int k1, int k2, int alpha, int agg, int64_t ld, float* hout, float* sout, SlOut out,
+                              hipStream_t s) {
+  if (k2 < 1 || k2 > 256 || (ld & 3) || agg == RERANK_AGG_MAX || !out.rows.col || !out.gate || !out.prev)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sparse_prop_kernel, dim3(n), dim3(256), 0, s, in, sin, knn_idx, knn_val, k1, k2, alpha, agg, ld,
+                     hout, sout, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void propagate_gated_kernel(const float* __restrict__ hin,
+                                                              const float* __restrict__ sin, int64_t ld,
+                                                              const int32_t* __restrict__ knn,
+                                                              const float* __restrict__ kv, int k1, int k2, int alpha,
+                                                              int agg, float* __restrict__ hout,
+                                                              float* __restrict__ sout, SlGate* gates, int l) {
+  if (!gates[l - 1].dense) return;
+  __shared__ PropShared sh;
+  if (blockIdx.x == 0 && threadIdx.x == 0) gates[l].dense = 1;
+  propagate_row(hin, sin, ld, ld, knn, kv, k1, k2, alpha, agg, hout, sout, nullptr, nullptr, blockIdx.x, sh);
+}
+
+hipError_t launch_propagate_gated(const float* hin, const float* sin, int n, int64_t ld, const int32_t* knn_idx,
+                                  const float* knn_val, int k1, int k2, int alpha, int agg, float* hout, float* sout,
+                                  SlGate* gates, int l, hipStream_t s) {
+  if (l < 1 || k2 < 1 || k2 > 256 || (ld & 3)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(propagate_gated_kernel, dim3(n), dim3(256), 0, s, hin, sin, ld, knn_idx, knn_val, k1, k2, alpha,
+                     agg, hout, sout, gates, l);
+  return hipGetLastError();
+}
+
+// ================================================================ final product
+// Which rows the final product uses, chosen on the device.
+struct SparseSel {
+  const int32_t* rs;  // row starts
+  const int32_t* rc;  // row counts
+  const int32_t* col;
+  const float* val;
+  int32_t* crow;  // column layout of the gallery rows
+  float* cval;
+  int32_t mode;  // 0: sparse-layer rows, 1: compacted rows, 2: dense product
+  int32_t pad;
+};
+
+// Compaction of dense rows runs unless the last layer is already CSR.
+__device__ __forceinline__ bool input_is_csr(const SlGate* lay) { return lay && !lay->dense; }
+
 // One workgroup per row: number of non-zeros of a dense row (ld % 4 == 0).
 __global__ __launch_bounds__(256) void nnz_count_kernel(const float* __restrict__ H, int64_t ld,
-                                                        int32_t* __restrict__ cnt) {
+                                                        int32_t* __restrict__ cnt, const SlGate* lay) {
+  if (input_is_csr(lay)) return;
   __shared__ int red[4];
   const int i = blockIdx.x, tid = threadIdx.x;
   const f32x4* row = (const f32x4*)(H + (int64_t)i * ld);
@@ -45,10 +138,14 @@ __global__ __launch_bounds__(256) void nnz_count_kernel(const float* __restrict_
 }
 
 // Exclusive scan of cnt[0..n) into off[0..n] (one workgroup). With a flag:
-// flag[0] = 1 (and off all zero) when the total exceeds cap.
+// flag[0] = 1 (and off all zero) when the total exceeds cap. Skipped when
+// `skip_csr` says the rows are already CSR, or `skip_dense` selects the dense
+// product.
 __global__ __launch_bounds__(256) void scan_gate_kernel(const int32_t* __restrict__ cnt, int n,
                                                         int32_t* __restrict__ off, int64_t cap,
-                                                        int32_t* __restrict__ flag) {
+                                                        int32_t* __restrict__ flag, const SlGate* skip_csr,
+                                                        const SparseSel* skip_dense) {
+  if (input_is_csr(skip_csr) || (skip_dense && skip_dense->mode == 2)) return;
   __shared__ int64_t sh[256];
   const int tid = threadIdx.x;
   const int per = (n + 255) / 256;
@@ -79,9 +176,9 @@ __global__ __launch_bounds__(256) void scan_gate_kernel(const int32_t* __restric
 // One workgroup per row: write the row's non-zeros, columns ascending.
 __global__ __launch_bounds__(256) void csr_fill_kernel(const float* __restrict__ H, int64_t ld,
                                                        const int32_t* __restrict__ off,
-                                                       const int32_t* __restrict__ flag, int32_t* __restrict__ col,
-                                                       float* __restrict__ val) {
-  if (flag[0]) return;
+                                                       const int32_t* __restrict__ flag, const SlGate* lay,
+                                                       int32_t* __restrict__ col, float* __restrict__ val) {
+  if (input_is_csr(lay) || flag[0]) return;
   __shared__ int wsum[4];
   const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t n4 = ld >> 2;
@@ -118,68 +215,85 @@ __global__ __launch_bounds__(256) void csr_fill_kernel(const float* __restrict__
   }
 }
 
-// CSC of the gallery rows q..n-1, one wave per row: column counts, then
-// placement (the order inside a column is arbitrary; every entry of a column
-// goes to a different accumulator, so it does not affect the sums).
-__global__ __launch_bounds__(256) void csc_count_kernel(const int32_t* __restrict__ off, int q, int n,
-                                                        const int32_t* __restrict__ col,
-                                                        const int32_t* __restrict__ flag,
-                                                        int32_t* __restrict__ ccnt) {
-  if (flag[0]) return;
-  const int lane = threadIdx.x & 63;
-  for (int r = q + (int)(blockIdx.x * 4 + (threadIdx.x >> 6)); r < n; r += gridDim.x * 4)
-    for (int t = off[r] + lane; t < off[r + 1]; t += 64) atomicAdd(ccnt + col[t], 1);
+// One thread: pick the rows of the final product.
+__global__ void select_kernel(const SlGate* lay, SlRows lrows, const int32_t* flag, const int32_t* off,
+                              const int32_t* cnt, void* pool, int64_t pool_bytes, SparseSel* sel) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  SparseSel o{};
+  if (input_is_csr(lay)) {
+    const int64_t capp = pool_bytes / 8;  // column layout only
+    o = SparseSel{lrows.so, lrows.cnt, lrows.col, lrows.val, (int32_t*)pool, (float*)((char*)pool + capp * 4), 0, 0};
+  } else if (flag[0] == 0) {
+    const int64_t cap = pool_bytes / 16;  // compacted rows + column layout
+    o = SparseSel{off, cnt, (const int32_t*)pool, (const float*)((char*)pool + cap * 4),
+                  (int32_t*)((char*)pool + cap * 8), (float*)((char*)pool + cap * 12), 1, 0};
+  } else {
+    o.mode = 2;
+  }
+  *sel = o;
 }
 
-__global__ __launch_bounds__(256) void csc_fill_kernel(const int32_t* __restrict__ off, int q, int n,
-                                                       const int32_t* __restrict__ col,
-                                                       const float* __restrict__ val,
-                                                       const int32_t* __restrict__ coff,
-                                                       const int32_t* __restrict__ flag,
-                                                       int32_t* __restrict__ cursor, int32_t* __restrict__ crow,
-                                                       float* __restrict__ cval) {
-  if (flag[0]) return;
+// Column layout of the gallery rows q..n-1, one wave per row: column counts,
+// then placement (the order inside a column is arbitrary; every entry of a
+// column goes to a different accumulator, so it does not affect the sums).
+__global__ __launch_bounds__(256) void csc_count_kernel(const SparseSel* __restrict__ sel, int q, int n,
+                                                        int32_t* __restrict__ ccnt) {
+  if (sel->mode == 2) return;
+  const int32_t* rs = sel->rs;
+  const int32_t* rc = sel->rc;
+  const int32_t* col = sel->col;
   const int lane = threadIdx.x & 63;
-  for (int r = q + (int)(blockIdx.x * 4 + (threadIdx.x >> 6)); r < n; r += gridDim.x * 4)
-    for (int t = off[r] + lane; t < off[r + 1]; t += 64) {
+  for (int r = q + (int)(blockIdx.x * 4 + (threadIdx.x >> 6)); r < n; r += gridDim.x * 4) {
+    const int b = rs[r], e = b + rc[r];
+    for (int t = b + lane; t < e; t += 64) atomicAdd(ccnt + col[t], 1);
+  }
+}
+
+__global__ __launch_bounds__(256) void csc_fill_kernel(const SparseSel* __restrict__ sel, int q, int n,
+                                                       const int32_t* __restrict__ coff, int32_t* __restrict__ cursor) {
+  if (sel->mode == 2) return;
+  const int32_t* rs = sel->rs;
+  const int32_t* rc = sel->rc;
+  const int32_t* col = sel->col;
+  const float* val = sel->val;
+  int32_t* crow = sel->crow;
+  float* cval = sel->cval;
+  const int lane = threadIdx.x & 63;
+  for (int r = q + (int)(blockIdx.x * 4 + (threadIdx.x >> 6)); r < n; r += gridDim.x * 4) {
+    const int b = rs[r], e = b + rc[r];
+    for (int t = b + lane; t < e; t += 64) {
       const int c = col[t];
       const int pos = coff[c] + atomicAdd(cursor + c, 1);
       crow[pos] = r - q;
       cval[pos] = val[t];
     }
+  }
 }
 
 constexpr int SF_GCH = 16384;  // gallery accumulators per pass (64 KiB of LDS)
 constexpr int SF_QCH = 512;    // query non-zeros staged per pass
 constexpr int SF_ILP = 4;      // columns whose first 64 entries are loaded together
 
-struct SparseFinalArgs {
-  const int32_t* off;  // CSR row offsets (n + 1)
-  const int32_t* col;
-  const float* val;
-  const int32_t* coff;  // CSC column offsets (ld + 1)
-  const int32_t* crow;  // gallery position of each CSC entry
-  const float* cval;
-  const float* sq;  // sigma of the queries
-  const float* sg;  // sigma of the gallery
-  int g;
-  const int32_t* flag;
-  float* dist;
-  int64_t ldd;
-};
-
-__global__ __launch_bounds__(256) void sparse_final_kernel(SparseFinalArgs a) {
-  if (a.flag[0]) return;
+// One workgroup per query: D[q][g] = 1 - sq * sg * sum_c u_q[c] u_g[c].
+__global__ __launch_bounds__(256) void sparse_final_kernel(const SparseSel* __restrict__ sel,
+                                                           const int32_t* __restrict__ coff,
+                                                           const float* __restrict__ sq, const float* __restrict__ sg,
+                                                           int g, float* __restrict__ dist, int64_t ldd) {
+  if (sel->mode == 2) return;
   __shared__ float acc[SF_GCH];
   __shared__ int cb[SF_QCH], ce[SF_QCH];
   __shared__ float qv[SF_QCH];
+  const int32_t* col = sel->col;
+  const float* val = sel->val;
+  const int32_t* crow = sel->crow;
+  const float* cval = sel->cval;
   const int qi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int b = a.off[qi], nq = a.off[qi + 1] - b;
-  const float sq = a.sq[qi];
-  float* drow = a.dist + (int64_t)qi * a.ldd;
-  for (int g0 = 0; g0 < a.g; g0 += SF_GCH) {
+  const int b = sel->rs[qi], nq = sel->rc[qi];
+  const float sqq = sq[qi];
+  float* drow = dist + (int64_t)qi * ldd;
+  for (int g0 = 0; g0 < g; g0 += SF_GCH) {
     if (g0) __syncthreads();  // the waves' quarters move with the chunk width
-    const int gw = min(SF_GCH, a.g - g0);
+    const int gw = min(SF_GCH, g - g0);
     const int quarter = (gw + 3) >> 2;
     const int lo = min(gw, w * quarter), len = min(gw, lo + quarter) - lo;
     for (int k = lane; k < len; k += 64) acc[lo + k] = 0.f;
@@ -188,10 +302,10 @@ __global__ __launch_bounds__(256) void sparse_final_kernel(SparseFinalArgs a) {
       if (g0 == 0 || nq > SF_QCH) {  // stage the query's columns (once if they fit)
         __syncthreads();
         for (int t = tid; t < tn; t += 256) {
-          const int c = a.col[b + t0 + t];
-          cb[t] = a.coff[c];
-          ce[t] = a.coff[c + 1];
-          qv[t] = a.val[b + t0 + t];
+          const int c = col[b + t0 + t];
+          cb[t] = coff[c];
+          ce[t] = coff[c + 1];
+          qv[t] = val[b + t0 + t];
         }
         __syncthreads();
       }
@@ -206,8 +320,8 @@ __global__ __launch_bounds__(256) void sparse_final_kernel(SparseFinalArgs a) {
           if (t + u < tn) {
             const int s = cb[t + u] + lane;
             if (s < ce[t + u]) {
-              r[u] = a.crow[s] - base;
-              x[u] = a.cval[s];
+              r[u] = crow[s] - base;
+              x[u] = cval[s];
             }
           }
         }
@@ -217,57 +331,64 @@ __global__ __launch_bounds__(256) void sparse_final_kernel(SparseFinalArgs a) {
           const float v = qv[t + u];
           if ((unsigned)r[u] < (unsigned)len) acc[lo + r[u]] = __builtin_fmaf(v, x[u], acc[lo + r[u]]);
           for (int s = cb[t + u] + 64 + lane; s < ce[t + u]; s += 64) {  // columns longer than 64
-            const int rr = a.crow[s] - base;
-            if ((unsigned)rr < (unsigned)len) acc[lo + rr] = __builtin_fmaf(v, a.cval[s], acc[lo + rr]);
+            const int rr = crow[s] - base;
+            if ((unsigned)rr < (unsigned)len) acc[lo + rr] = __builtin_fmaf(v, cval[s], acc[lo + rr]);
           }
         }
       }
     }
-    for (int k = lane; k < len; k += 64) drow[g0 + lo + k] = 1.0f - sq * a.sg[g0 + lo + k] * acc[lo + k];
+    for (int k = lane; k < len; k += 64) drow[g0 + lo + k] = 1.0f - sqq * sg[g0 + lo + k] * acc[lo + k];
   }
 }
 
-// Dense fallback: the FP32 matrix-core product, run only when flag[0] != 0.
+// Dense fallback: the FP32 matrix-core product, run only in mode 2.
 __global__ __launch_bounds__(256) void gemm_dist_gated_kernel(GemmArgs g, int tiles_n,
-                                                              const int32_t* __restrict__ flag) {
+                                                              const SparseSel* __restrict__ sel) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[GEMM_LDS_1BUF];
-  if (flag[0] == 0) return;
+  if (sel->mode != 2) return;
   gemm_tile<MODE_F32, EPI_DIST>(g, (int)blockIdx.x / tiles_n, (int)blockIdx.x % tiles_n, lds);
 }
 
 hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const float* sigma, float* dist, void* pool,
-                               int64_t pool_bytes, int32_t* ints, hipStream_t s) {
+                               int64_t pool_bytes, int32_t* ints, const SlGate* lay_gate, const SlRows* lay,
+                               hipStream_t s) {
   const int g = n - q;
   if (!H || !sigma || !dist || !pool || !ints || n < 2 || q < 1 || g < 1 || ld < n || (ld & 31) || pool_bytes < 16)
     return hipErrorInvalidValue;
+  if ((lay_gate == nullptr) != (lay == nullptr)) return hipErrorInvalidValue;
+  // the pool must not overlap the rows: the last layer's buffer is H (dense n x ld, or CSR in the same bytes)
   if ((const char*)pool < (const char*)(H + (int64_t)n * ld) && (const char*)H < (const char*)pool + pool_bytes)
-    return hipErrorInvalidValue;  // the compacted rows must not overwrite H
-  int32_t* ccnt = ints;            // ld   (cleared here with cursor: 16-byte aligned, ld % 32 == 0)
-  int32_t* cursor = ccnt + ld;     // ld
-  int32_t* coff = cursor + ld;     // ld + 1
-  int32_t* cnt = coff + ld + 1;    // n
-  int32_t* off = cnt + n;          // n + 1
-  int32_t* flag = off + n + 1;     // 2
-  const int64_t cap = pool_bytes / 16;  // entries of each of the four arrays
-  int32_t* col = (int32_t*)pool;
-  float* val = (float*)((char*)pool + cap * 4);
-  int32_t* crow = (int32_t*)((char*)pool + cap * 8);
-  float* cval = (float*)((char*)pool + cap * 12);
+    return hipErrorInvalidValue;
+  if (lay && pool_bytes < (int64_t)n * ld * 4) return hipErrorInvalidValue;  // column layout of up to n*ld/2 entries
+  int32_t* ccnt = ints;          // ld   (cleared here with cursor: 16-byte aligned, ld % 32 == 0)
+  int32_t* cursor = ccnt + ld;   // ld
+  int32_t* coff = cursor + ld;   // ld + 1
+  int32_t* cnt = coff + ld + 1;  // n
+  int32_t* off = cnt + n;        // n + 1
+  int32_t* flag = off + n + 1;   // 2
+  SparseSel* sel = (SparseSel*)(flag + 2);  // 8-byte aligned: 3 ld + 2 n + 4 ints precede it
+  static_assert(sizeof(SparseSel) <= 16 * 4, "selection record");
+  const int64_t cap = pool_bytes / 16;  // compacted entries (CSR and CSC, 16 bytes each)
   hipError_t e = launch_fill_zero((float*)ccnt, 2 * ld, s);  // ccnt and cursor
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(nnz_count_kernel, dim3(n), dim3(256), 0, s, H, ld, cnt);
-  hipLaunchKernelGGL(scan_gate_kernel, dim3(1), dim3(256), 0, s, cnt, n, off, cap, flag);
-  hipLaunchKernelGGL(csr_fill_kernel, dim3(n), dim3(256), 0, s, H, ld, off, flag, col, val);
+  hipLaunchKernelGGL(nnz_count_kernel, dim3(n), dim3(256), 0, s, H, ld, cnt, lay_gate);
+  hipLaunchKernelGGL(scan_gate_kernel, dim3(1), dim3(256), 0, s, cnt, n, off, cap, flag, lay_gate,
+                     (const SparseSel*)nullptr);
+  hipLaunchKernelGGL(csr_fill_kernel, dim3(n), dim3(256), 0, s, H, ld, off, flag, lay_gate, (int32_t*)pool,
+                     (float*)((char*)pool + cap * 4));
+  const SlRows none{};
+  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, lay_gate, lay ? *lay : none, flag, off, cnt, pool,
+                     pool_bytes, sel);
   const unsigned rb = (unsigned)min((g + 3) / 4, 4096);
-  hipLaunchKernelGGL(csc_count_kernel, dim3(rb), dim3(256), 0, s, off, q, n, col, flag, ccnt);
-  hipLaunchKernelGGL(scan_gate_kernel, dim3(1), dim3(256), 0, s, ccnt, (int)ld, coff, cap, (int32_t*)nullptr);
-  hipLaunchKernelGGL(csc_fill_kernel, dim3(rb), dim3(256), 0, s, off, q, n, col, val, coff, flag, cursor, crow, cval);
-  SparseFinalArgs sa{off, col, val, coff, crow, cval, sigma, sigma + q, g, flag, dist, (int64_t)g};
-  hipLaunchKernelGGL(sparse_final_kernel, dim3(q), dim3(256), 0, s, sa);
+  hipLaunchKernelGGL(csc_count_kernel, dim3(rb), dim3(256), 0, s, sel, q, n, ccnt);
+  hipLaunchKernelGGL(scan_gate_kernel, dim3(1), dim3(256), 0, s, ccnt, (int)ld, coff, INT64_MAX, (int32_t*)nullptr,
+                     (const SlGate*)nullptr, sel);
+  hipLaunchKernelGGL(csc_fill_kernel, dim3(rb), dim3(256), 0, s, sel, q, n, coff, cursor);
+  hipLaunchKernelGGL(sparse_final_kernel, dim3(q), dim3(256), 0, s, sel, coff, sigma, sigma + q, g, dist, (int64_t)g);
   const int tm = (q + BM - 1) / BM, tn = (g + BN - 1) / BN;
   GemmArgs ga{(const uint8_t*)H, (const uint8_t*)(H + (int64_t)q * ld), q, g, ld * 4, ld * 4, (int)(ld * 4 / BKB),
               sigma, sigma + q, dist, (int64_t)g};
-  hipLaunchKernelGGL(gemm_dist_gated_kernel, dim3((unsigned)tm * tn), dim3(256), 0, s, ga, tn, flag);
+  hipLaunchKernelGGL(gemm_dist_gated_kernel, dim3((unsigned)tm * tn), dim3(256), 0, s, ga, tn, sel);
   return hipGetLastError();
 }
 

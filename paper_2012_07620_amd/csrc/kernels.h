@@ -9,6 +9,36 @@ namespace rr {
 enum class SimPrec : int { F32 = 0, BF16 = 1, FP8 = 2 };
 enum class FinalPrec : int { F32 = 0, BF16X3 = 1, SPARSE = 2 };
 
+// Sparse layers (used with the sparse final product): every propagated row is
+// stored as CSR entries (columns ascending) in a slot of the layer's output
+// buffer. One gate per layer l (gate 0 = h^(0), always sparse):
+//   total  sum over rows of the slot bound min(n, sum of the k2 members' entry
+//          counts), computed before the layer runs;
+//   cursor slot allocator (rows take their slots in any order; the values do
+//          not depend on where a row is placed);
+//   dense  1 when layer l was written as dense rows instead (its bound total
+//          exceeded the buffer, or an earlier layer was dense).
+struct SlGate {
+  unsigned long long total;
+  int32_t cursor;
+  int32_t dense;
+};
+// CSR rows of one layer: entries of row i are col/val[so[i] .. so[i] + cnt[i]).
+struct SlRows {
+  int32_t* col;
+  float* val;
+  int32_t* so;
+  int32_t* cnt;
+};
+// Output side of a sparse layer: where the rows go and which gates apply.
+struct SlOut {
+  SlRows rows;
+  SlGate* gate;        // gates[l]
+  const SlGate* prev;  // gates[l - 1]
+  int64_t cap;         // entries the buffer holds
+  int n;               // columns of a row (bounds are capped at n)
+};
+
 // Row stride (elements) of the padded K-major copies the GEMMs read: every
 // row is a whole number of 128-byte stages.
 inline int64_t pad_k_elems(int64_t d, int bytes_per_elem) {
@@ -79,10 +109,27 @@ hipError_t launch_csr(const int32_t* knn_idx, int n, int k1, const uint8_t* mfla
                       int32_t* cursor, int32_t* inl, hipStream_t s);
 // ... and layer 1 built from the sparse A* rows (same result as the dense layer).
 // (sym = false: rows of A; agg: sum or mean)
+// sl != nullptr: CSR output (sparse layers) unless the layer's gate says
+// dense, in which case the dense rows go to hout as without sl.
 hipError_t launch_first_layer(const int32_t* knn_idx, const float* knn_val, const uint8_t* mflag,
                               const int32_t* off, const int32_t* inl, int n, int k1, int k2, int alpha, int agg,
                               bool sym, int64_t ld, float* hout, float* sout, uint16_t* hi, uint16_t* lo,
+                              const SlOut* sl, hipStream_t s);
+// Sparse layers. Slot bounds of layer l (first: members' A* / A entry counts
+// from the kNN lists and the in-edge offsets `off` (A* only); otherwise the
+// previous layer's row counts), summed into gates[l].total. No-op when
+// gates[l - 1] is dense.
+hipError_t launch_sl_bounds(const int32_t* knn_idx, int n, int k1, int k2, bool first, bool sym, const int32_t* off,
+                            const int32_t* cnt_prev, SlGate* gates, int l, hipStream_t s);
+// Layer l >= 2 from the CSR rows of layer l - 1 (runs when gates[l - 1] is
+// sparse): CSR out, or dense rows into hout when gates[l] turns dense.
+hipError_t launch_sparse_prop(SlRows in, const float* sin, const int32_t* knn_idx, const float* knn_val, int n,
+                              int k1, int k2, int alpha, int agg, int64_t ld, float* hout, float* sout, SlOut out,
                               hipStream_t s);
+// The dense layer, run only when gates[l - 1] is dense (then marks gates[l]).
+hipError_t launch_propagate_gated(const float* hin, const float* sin, int n, int64_t ld, const int32_t* knn_idx,
+                                  const float* knn_val, int k1, int k2, int alpha, int agg, float* hout, float* sout,
+                                  SlGate* gates, int l, hipStream_t s);
 // Ranking list: per row of D (q rows, stride g), the r smallest positions in
 // ascending order, ties to the lower position (r <= 256).
 hipError_t launch_rank(const float* D, int q, int g, int r, int32_t* out, hipStream_t s);
@@ -92,9 +139,13 @@ hipError_t launch_rank(const float* D, int q, int g, int r, int32_t* out, hipStr
 // sparse_final_ints(n, ld) int32 of counters. When the non-zeros exceed
 // pool_bytes / 16 the FP32 matrix-core product computes D instead (decided on
 // the device). D is q x (n - q), row stride n - q.
-inline int64_t sparse_final_ints(int64_t n, int64_t ld) { return 2 * n + 1 + 3 * ld + 1 + 2; }
+// With `lay` (the gate and rows of the last sparse layer, H then being that
+// layer's buffer): when the gate is sparse the CSR rows are used as they are
+// and only the column layout goes into `pool`.
+inline int64_t sparse_final_ints(int64_t n, int64_t ld) { return 3 * ld + 2 * n + 4 + 16; }
 hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const float* sigma, float* dist, void* pool,
-                               int64_t pool_bytes, int32_t* ints, hipStream_t s);
+                               int64_t pool_bytes, int32_t* ints, const SlGate* lay_gate, const SlRows* lay,
+                               hipStream_t s);
 // Split rows of an FP32 matrix into bf16 high/low parts (for L = 0 or raw).
 hipError_t launch_split_bf16(const float* h, int n, int64_t ld, uint16_t* hi, uint16_t* lo, hipStream_t s);
 

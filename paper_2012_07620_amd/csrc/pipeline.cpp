@@ -110,6 +110,24 @@ hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipS
   return hipSuccess;
 }
 
+// CSR rows of sparse layer l (1..L) in its output buffer `buf` (the N x ldN
+// feature buffer it writes: column indices, then values, n * ldN / 2 entries
+// each) and the gates of l and l - 1. Row starts and counts alternate between
+// two sets by the parity of l.
+static SlOut sl_out(const Plan& P, void* ws, float* buf, int l) {
+  SlGate* gates = at<SlGate>(ws, P.o_slg);
+  int32_t* sets = at<int32_t>(ws, P.o_slr);
+  const int64_t cap = (int64_t)P.n * P.ldN / 2;
+  int32_t* so = sets + (size_t)(l & 1) * 2 * P.n;
+  SlOut o{};
+  o.rows = SlRows{(int32_t*)buf, (float*)((char*)buf + cap * 4), so, so + P.n};
+  o.gate = gates + l;
+  o.prev = gates + (l - 1);
+  o.cap = cap;
+  o.n = P.n;
+  return o;
+}
+
 hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, float* dist, hipStream_t s,
                           const char** where, StageClock* clk) {
   hipError_t e = enqueue_knn(P, ws, x, in_bf16, s, where, clk);
@@ -145,8 +163,17 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
       RR_STAGE(RERANK_STAGE_ADJACENCY, 1);
       RR_STAGE(RERANK_STAGE_PROPAGATE, 0);
       const bool last = (P.layers == 1);
-      RR_TRY(launch_first_layer(ki, kv, mflag, off, inl, P.n, P.k1, P.k2, P.alpha, P.agg, sym, P.ldN, B, sa,
-                                last ? hi : nullptr, last ? lo : nullptr, s));
+      if (P.sparse_layers) {
+        SlGate* gates = at<SlGate>(ws, P.o_slg);
+        RR_TRY(launch_fill_zero((float*)gates, (int64_t)(P.layers + 1) * (sizeof(SlGate) / 4), s));
+        RR_TRY(launch_sl_bounds(ki, P.n, P.k1, P.k2, true, sym, off, nullptr, gates, 1, s));
+        const SlOut o = sl_out(P, ws, B, 1);
+        RR_TRY(launch_first_layer(ki, kv, mflag, off, inl, P.n, P.k1, P.k2, P.alpha, P.agg, sym, P.ldN, B, sa,
+                                  nullptr, nullptr, &o, s));
+      } else {
+        RR_TRY(launch_first_layer(ki, kv, mflag, off, inl, P.n, P.k1, P.k2, P.alpha, P.agg, sym, P.ldN, B, sa,
+                                  last ? hi : nullptr, last ? lo : nullptr, nullptr, s));
+      }
       cur = B;
       csig = sa;
       first = 1;
@@ -172,8 +199,18 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
     float* out = (cur == A) ? B : A;
     float* osig = (csig == sa) ? sb : sa;
     const bool last = (l == P.layers - 1);
-    RR_TRY(launch_propagate(cur, csig, P.n, P.ldH, P.ldH, ki, kv, P.k1, P.k2, P.alpha, P.agg, out, osig,
-                            last ? hi : nullptr, last ? lo : nullptr, s));
+    if (P.sparse_layers) {  // layer l + 1 from the CSR rows of layer l (or dense once a layer turned dense)
+      SlGate* gates = at<SlGate>(ws, P.o_slg);
+      const SlOut prev = sl_out(P, ws, (float*)cur, l);
+      RR_TRY(launch_sl_bounds(ki, P.n, P.k1, P.k2, false, false, nullptr, prev.rows.cnt, gates, l + 1, s));
+      RR_TRY(launch_sparse_prop(prev.rows, csig, ki, kv, P.n, P.k1, P.k2, P.alpha, P.agg, P.ldH, out, osig,
+                                sl_out(P, ws, out, l + 1), s));
+      RR_TRY(launch_propagate_gated(cur, csig, P.n, P.ldH, ki, kv, P.k1, P.k2, P.alpha, P.agg, out, osig, gates, l + 1,
+                                    s));
+    } else {
+      RR_TRY(launch_propagate(cur, csig, P.n, P.ldH, P.ldH, ki, kv, P.k1, P.k2, P.alpha, P.agg, out, osig,
+                              last ? hi : nullptr, last ? lo : nullptr, s));
+    }
     cur = out;
     csig = osig;
   }
@@ -185,8 +222,14 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
     RR_TRY(launch_gemm_dist(hq, P.q, hg, P.g, P.ldH, P.ldH, csig, csig + P.q, dist, P.g, s));
   } else if (P.fprec == FinalPrec::SPARSE) {  // adjacency features: cur is A or B, the other one is free
     float* pool = (cur == A) ? B : A;
-    RR_TRY(launch_sparse_final(cur, P.n, P.q, P.ldH, csig, dist, pool, (int64_t)P.n * P.ldH * 4,
-                               at<int32_t>(ws, P.o_sp), s));
+    if (P.sparse_layers) {
+      const SlOut last = sl_out(P, ws, (float*)cur, P.layers);
+      RR_TRY(launch_sparse_final(cur, P.n, P.q, P.ldH, csig, dist, pool, (int64_t)P.n * P.ldH * 4,
+                                 at<int32_t>(ws, P.o_sp), last.gate, &last.rows, s));
+    } else {
+      RR_TRY(launch_sparse_final(cur, P.n, P.q, P.ldH, csig, dist, pool, (int64_t)P.n * P.ldH * 4,
+                                 at<int32_t>(ws, P.o_sp), nullptr, nullptr, s));
+    }
   } else {
     if (P.layers == 0) RR_TRY(launch_split_bf16(cur, P.n, P.ldH, hi, lo, s));
     RR_TRY(launch_gemm_dist_bf16x3(hi, lo, P.q, hi + (size_t)P.q * P.ldH, lo + (size_t)P.q * P.ldH, P.g, P.ldH,

@@ -35,7 +35,7 @@ rerank_status validate_params(const rerank_params* p, std::string* why) {
 
 static size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-void make_plan(const rerank_params* p, bool knn_only, Plan* o) {
+void make_plan(const rerank_params* p, bool knn_only, Plan* o, bool dense_layers) {
   Plan& P = *o;
   P = Plan{};
   P.n = p->n;
@@ -92,6 +92,11 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o) {
       P.o_inl = take(n * P.k1 * 4);
     }
     if (P.fprec == FinalPrec::SPARSE) P.o_sp = take(sparse_final_ints(P.n, P.ldN) * 4);
+    P.sparse_layers = P.fprec == FinalPrec::SPARSE && P.sparse_first && !dense_layers;
+    if (P.sparse_layers) {
+      P.o_slg = take((size_t)(P.layers + 1) * sizeof(SlGate));
+      P.o_slr = take(n * 4 * 4);  // row starts and counts of two layers
+    }
     if (P.fprec == FinalPrec::BF16X3) {
       P.o_hi = take(n * P.ldH * 2);
       P.o_lo = take(n * P.ldH * 2);

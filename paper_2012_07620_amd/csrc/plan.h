@@ -28,14 +28,17 @@ struct Plan {
   int64_t ldH = 0;  // propagated feature row stride (ldN, or ldp in raw mode)
   // byte offsets into the working set
   size_t o_xp = 0, o_xl = 0, o_rn = 0, o_sl = 0, o_a = 0, o_b = 0, o_ci = 0, o_cv = 0, o_ki = 0, o_kv = 0,
-         o_sa = 0, o_sb = 0, o_cnt = 0, o_hi = 0, o_lo = 0, o_mflag = 0, o_off = 0, o_inl = 0, o_sp = 0;
-  bool sparse_first = false;  // layer 1 built from the sparse A* / A rows (layers >= 1, sum or mean)
+         o_sa = 0, o_sb = 0, o_cnt = 0, o_hi = 0, o_lo = 0, o_mflag = 0, o_off = 0, o_inl = 0, o_sp = 0,
+         o_slg = 0, o_slr = 0;
+  bool sparse_first = false;   // layer 1 built from the sparse A* / A rows (layers >= 1, sum or mean)
+  bool sparse_layers = false;  // layers kept as CSR rows for the sparse final product
   size_t total = 0;
 };
 
 // Returns RERANK_OK or an error with a reason in *why.
 rerank_status validate_params(const rerank_params* p, std::string* why);
-// Fills the layout for valid parameters. knn_only skips propagation buffers.
-void make_plan(const rerank_params* p, bool knn_only, Plan* out);
+// Fills the layout for valid parameters. knn_only skips propagation buffers;
+// dense_layers keeps the layers dense under the sparse final product.
+void make_plan(const rerank_params* p, bool knn_only, Plan* out, bool dense_layers = false);
 
 }  // namespace rr

@@ -152,7 +152,7 @@ rerank_status rerank_create(rerank_ctx** out, int hip_device, size_t hbm_budget_
     return RERANK_E_INVALID;
   }
   *out = nullptr;
-  if (flags & ~RERANK_CTX_STAGE_TIMING) {
+  if (flags & ~(RERANK_CTX_STAGE_TIMING | RERANK_CTX_DENSE_LAYERS)) {
     set_error("unknown flags");
     return RERANK_E_INVALID;
   }
@@ -234,7 +234,7 @@ rerank_status rerank_run(rerank_ctx* ctx, const rerank_params* p, const void* d_
     return RERANK_E_INVALID;
   }
   Plan P;
-  make_plan(p, false, &P);
+  make_plan(p, false, &P, (ctx->flags & RERANK_CTX_DENSE_LAYERS) != 0);
   return with_ws(ctx, P, hip_stream, [&](hipStream_t s, const char** where) -> hipError_t {
     hipError_t e = enqueue_rerank(P, ctx->ws, d_x, in_dtype == RERANK_IN_BF16, d_dist, s, where, ctx->clock);
     if (e != hipSuccess) return e;

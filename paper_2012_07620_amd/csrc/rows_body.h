@@ -494,7 +494,69 @@ struct FirstShared {
   int col[FIRST_ENTRIES];
   float val[FIRST_ENTRIES];
   int start[257];  // entries of member r are [start[r], start[r+1])
+  int wsum[4];     // per-wave counts of a CSR store step
+  int obase;       // first entry of the row's CSR slot
 };
+
+// ---------------------------------------------------------------- CSR rows
+// Sparse-layer output: decide dense or CSR for this layer (the same answer in
+// every workgroup: it reads only gates written by earlier launches), mark the
+// gate from workgroup 0, and take this row's slot of min(n, bound) entries.
+// Returns true for CSR output; *pos is the slot's first entry.
+__device__ __forceinline__ bool sl_begin(const SlOut* o, int bound, int i, FirstShared& sh, int* pos) {
+  if (!o) return false;
+  const unsigned long long total = o->gate->total;
+  const bool dense = o->prev->dense != 0 || total > (unsigned long long)o->cap || total > 0x7FFFFFFFull;
+  if (threadIdx.x == 0) {
+    if (i == 0) o->gate->dense = dense ? 1 : 0;
+    if (!dense) sh.obase = atomicAdd(&o->gate->cursor, min(bound, o->n));
+  }
+  __syncthreads();
+  *pos = sh.obase;
+  return !dense;
+}
+
+// Append the non-zeros of the LDS chunk row[0, width) (columns c0 + k) to the
+// row's CSR slot at *pos, columns ascending, and add their squares to ss in
+// the same per-thread order as the dense store (thread t owns float4 columns
+// t, t + 256, ...). Every thread ends with the same *pos.
+__device__ __forceinline__ void store_chunk_csr(const float* row, int width, int64_t c0, const SlRows& out, int* pos,
+                                                FirstShared& sh, float* ss) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int w4 = width >> 2;
+  for (int cb = 0; cb < w4; cb += 256) {
+    const int c = cb + tid;
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (c < w4) {
+      v = ((const f32x4*)row)[c];
+      *ss = sq_acc4(*ss, v);
+    }
+    const int mine = (v.x != 0.f) + (v.y != 0.f) + (v.z != 0.f) + (v.w != 0.f);
+    int incl = mine;  // inclusive prefix over the wave
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) sh.wsum[w] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int x = 0; x < 4; x++) {
+      before += (x < w) ? sh.wsum[x] : 0;
+      total += sh.wsum[x];
+    }
+    int at = *pos + before + incl - mine;
+    const float e4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+      if (e4[e] != 0.f) {
+        out.col[at] = (int32_t)(c0 + (int64_t)c * 4 + e);
+        out.val[at] = e4[e];
+        at++;
+      }
+    *pos += total;
+    __syncthreads();  // wsum is rewritten by the next step
+  }
+}
 
 // sym = false: h^(0) = rows of A (out-list entries only, value 1). The
 // aggregator is sum or mean (max runs the dense layer).
@@ -503,7 +565,8 @@ __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn,
                                                 const int32_t* __restrict__ inl, int k1, int k2, int alpha, int agg,
                                                 bool sym, int64_t ld, float* __restrict__ hout,
                                                 float* __restrict__ sout, uint16_t* __restrict__ hi,
-                                                uint16_t* __restrict__ lo, int i, FirstShared& sh) {
+                                                uint16_t* __restrict__ lo, int i, FirstShared& sh,
+                                                const SlOut* sl = nullptr) {
   const int tid = threadIdx.x;
   load_coefs(nullptr, knn, kv, k1, k2, alpha, agg, i, sh.p);
   // entry counts per member: out-list (k1) + non-mutual in-list (A* only)
@@ -536,6 +599,9 @@ __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn,
     }
   }
   __syncthreads();
+  int pos = 0;
+  const bool csr = sl_begin(sl, sh.start[k2], i, sh, &pos);
+  const int pos0 = pos;
   float ss = 0.f;
   for (int64_t c0 = 0; c0 < ld; c0 += FIRST_CHUNK) {
     const int width = (int)min((int64_t)FIRST_CHUNK, ld - c0);
@@ -564,16 +630,102 @@ __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn,
       }
       __syncthreads();
     }
-    const int w4 = width >> 2;
-    for (int c = tid; c < w4; c += 256) {
-      const f32x4 acc = ((const f32x4*)sh.row)[c];
-      if (hi)
-        split_store4(hi, lo, (int64_t)i * ld + c0 + c * 4, acc);
-      else
-        ((f32x4*)(hout + (int64_t)i * ld + c0))[c] = acc;
-      ss = sq_acc4(ss, acc);
+    if (csr) {
+      store_chunk_csr(sh.row, width, c0, sl->rows, &pos, sh, &ss);
+    } else {
+      const int w4 = width >> 2;
+      for (int c = tid; c < w4; c += 256) {
+        const f32x4 acc = ((const f32x4*)sh.row)[c];
+        if (hi)
+          split_store4(hi, lo, (int64_t)i * ld + c0 + c * 4, acc);
+        else
+          ((f32x4*)(hout + (int64_t)i * ld + c0))[c] = acc;
+        ss = sq_acc4(ss, acc);
+      }
     }
     __syncthreads();
+  }
+  if (csr && tid == 0) {
+    sl->rows.so[i] = pos0;
+    sl->rows.cnt[i] = pos - pos0;
+  }
+  finish_norm(ss, sout, i, sh.p);
+}
+
+// Layer l >= 2 of the sparse layers: u_i = sum_r c_r h_{j_r} from the CSR
+// rows of layer l - 1 (coefficients from load_coefs with their carried
+// 1/|u_j|), built in LDS column chunks in member order r with one FMA per
+// entry: the same sums, rounding for rounding, as propagate_row on the dense
+// rows (a zero entry there is an FMA that leaves the sum unchanged).
+// Sum and mean aggregators.
+__device__ __forceinline__ void sparse_prop_row(const SlRows& in, const float* __restrict__ sin,
+                                                const int32_t* __restrict__ knn, const float* __restrict__ kv,
+                                                int k1, int k2, int alpha, int agg, int64_t ld,
+                                                float* __restrict__ hout, float* __restrict__ sout, const SlOut* sl,
+                                                int i, FirstShared& sh) {
+  const int tid = threadIdx.x;
+  load_coefs(sin, knn, kv, k1, k2, alpha, agg, i, sh.p);
+  if (tid == 0) {
+    int acc = 0;
+    for (int r = 0; r < k2; r++) {
+      sh.start[r] = acc;
+      acc += in.cnt[sh.p.nb[r]];
+    }
+    sh.start[k2] = acc;
+  }
+  __syncthreads();
+  const bool staged = sh.start[k2] <= FIRST_ENTRIES;
+  if (staged) {
+    for (int r = 0; r < k2; r++) {
+      const int j = sh.p.nb[r];
+      const int b = in.so[j], base = sh.start[r], len = sh.start[r + 1] - base;
+      for (int s = tid; s < len; s += 256) {
+        sh.col[base + s] = in.col[b + s];
+        sh.val[base + s] = in.val[b + s];
+      }
+    }
+  }
+  __syncthreads();
+  int pos = 0;
+  const bool csr = sl_begin(sl, sh.start[k2], i, sh, &pos);
+  const int pos0 = pos;
+  float ss = 0.f;
+  for (int64_t c0 = 0; c0 < ld; c0 += FIRST_CHUNK) {
+    const int width = (int)min((int64_t)FIRST_CHUNK, ld - c0);
+    for (int k = tid; k < FIRST_CHUNK; k += 256) sh.row[k] = 0.f;
+    __syncthreads();
+    for (int r = 0; r < k2; r++) {
+      const float c = sh.p.cf[r];
+      if (staged) {
+        for (int s = sh.start[r] + tid; s < sh.start[r + 1]; s += 256) {
+          const int64_t m = sh.col[s] - c0;
+          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, sh.val[s], sh.row[m]);
+        }
+      } else {
+        const int j = sh.p.nb[r];
+        const int b = in.so[j], e = b + in.cnt[j];
+        for (int s = b + tid; s < e; s += 256) {
+          const int64_t m = in.col[s] - c0;
+          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, in.val[s], sh.row[m]);
+        }
+      }
+      __syncthreads();
+    }
+    if (csr) {
+      store_chunk_csr(sh.row, width, c0, sl->rows, &pos, sh, &ss);
+    } else {
+      const int w4 = width >> 2;
+      for (int c = tid; c < w4; c += 256) {
+        const f32x4 acc = ((const f32x4*)sh.row)[c];
+        ((f32x4*)(hout + (int64_t)i * ld + c0))[c] = acc;
+        ss = sq_acc4(ss, acc);
+      }
+    }
+    __syncthreads();
+  }
+  if (csr && tid == 0) {
+    sl->rows.so[i] = pos0;
+    sl->rows.cnt[i] = pos - pos0;
   }
   finish_norm(ss, sout, i, sh.p);
 }

@@ -183,7 +183,7 @@ class Server {
   rerank_status submit(const rerank_params* p, const void* x, int in_bf16, float* dist, uint64_t* ticket) {
     auto r = std::make_shared<Request>();
     r->params = *p;
-    make_plan(p, false, &r->plan);
+    make_plan(p, false, &r->plan, (ctx_->flags & RERANK_CTX_DENSE_LAYERS) != 0);
     if (r->plan.total > ctx_->budget) {
       set_error("request working set exceeds the context budget");
       return RERANK_E_NOMEM;
