@@ -35,30 +35,68 @@
 namespace rr {
 
 // ================================================================ sparse layers
-// Slot bound of every row of layer l, summed into gates[l].total (one atomic
-// per wave).
-__global__ __launch_bounds__(256) void sl_bound_kernel(const int32_t* __restrict__ knn, int n, int k1, int k2,
-                                                       int first, int sym, const int32_t* __restrict__ off,
-                                                       const int32_t* __restrict__ cnt_prev, SlGate* gates, int l) {
-  if (gates[l - 1].dense) return;
+// Slot size of every row of layer l.
+__global__ __launch_bounds__(256) void sl_size_kernel(const int32_t* __restrict__ knn, int n, int k1, int k2,
+                                                      int first, int sym, const int32_t* __restrict__ off,
+                                                      const int32_t* __restrict__ cnt_prev, const SlGate* prev,
+                                                      int32_t* __restrict__ size) {
+  if (prev->dense) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
-  unsigned long long b = 0;
-  if (i < n) {
-    for (int r = 0; r < k2; r++) {
-      const int j = knn[(int64_t)i * k1 + r];
-      b += first ? (unsigned long long)(k1 + (sym ? off[j + 1] - off[j] : 0)) : (unsigned long long)cnt_prev[j];
-    }
-    if (b > (unsigned long long)n) b = n;
+  if (i >= n) return;
+  int64_t b = 0;
+  for (int r = 0; r < k2; r++) {
+    const int j = knn[(int64_t)i * k1 + r];
+    b += first ? (int64_t)(k1 + (sym ? off[j + 1] - off[j] : 0)) : (int64_t)cnt_prev[j];
   }
-  for (int m = 32; m > 0; m >>= 1) b += shfl_xor_u64(b, m);
-  if ((threadIdx.x & 63) == 0 && b) atomicAdd(&gates[l].total, b);
+  size[i] = (int32_t)min(b, (int64_t)n);
 }
 
-hipError_t launch_sl_bounds(const int32_t* knn_idx, int n, int k1, int k2, bool first, bool sym, const int32_t* off,
-                            const int32_t* cnt_prev, SlGate* gates, int l, hipStream_t s) {
-  if (l < 1 || k2 < 1 || k2 > k1 || (first && sym && !off) || (!first && !cnt_prev)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(sl_bound_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, knn_idx, n, k1, k2,
-                     (int)first, (int)sym, off, cnt_prev, gates, l);
+// Slot starts (exclusive prefix sum of the sizes, one workgroup) and gate l.
+__global__ __launch_bounds__(256) void sl_scan_kernel(const int32_t* __restrict__ size, int n,
+                                                      int32_t* __restrict__ so, int64_t cap, SlGate* gates, int l) {
+  const int tid = threadIdx.x;
+  if (gates[l - 1].dense) {
+    if (tid == 0) gates[l].dense = 1;
+    return;
+  }
+  __shared__ int64_t sh[256];
+  const int per = (n + 255) / 256;
+  const int b = min(n, tid * per), e = min(n, b + per);
+  int64_t sum = 0;
+  for (int k = b; k < e; k++) sum += size[k];
+  sh[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int64_t v = tid >= o ? sh[tid - o] : 0;
+    __syncthreads();
+    sh[tid] += v;
+    __syncthreads();
+  }
+  const int64_t total = sh[255];
+  const bool fits = total <= cap && total <= 0x7FFFFFFF;
+  if (fits) {
+    int64_t run = sh[tid] - sum;
+    for (int k = b; k < e; k++) {
+      so[k] = (int32_t)run;
+      run += size[k];
+    }
+  }
+  if (tid == 0) {
+    gates[l].total = (unsigned long long)total;
+    gates[l].dense = fits ? 0 : 1;
+  }
+}
+
+hipError_t launch_sl_slots(const int32_t* knn_idx, int n, int k1, int k2, bool first, bool sym, const int32_t* off,
+                           const int32_t* cnt_prev, const SlOut& out, hipStream_t s) {
+  if (k2 < 1 || k2 > k1 || (first && sym && !off) || (!first && !cnt_prev) || !out.gate || !out.prev ||
+      out.gate != out.prev + 1 || !out.rows.so || !out.rows.cnt)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sl_size_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, knn_idx, n, k1, k2,
+                     (int)first, (int)sym, off, cnt_prev, out.prev, out.rows.cnt);
+  // gates[l - 1] = out.prev, gates[l] = out.gate
+  hipLaunchKernelGGL(sl_scan_kernel, dim3(1), dim3(256), 0, s, out.rows.cnt, n, out.rows.so, out.cap,
+                     (SlGate*)out.prev, 1);
   return hipGetLastError();
 }
 
@@ -90,7 +128,6 @@ __global__ __launch_bounds__(256) void propagate_gated_kernel(const float* __res
                                                               float* __restrict__ sout, SlGate* gates, int l) {
   if (!gates[l - 1].dense) return;
   __shared__ PropShared sh;
-  if (blockIdx.x == 0 && threadIdx.x == 0) gates[l].dense = 1;
   propagate_row(hin, sin, ld, ld, knn, kv, k1, k2, alpha, agg, hout, sout, nullptr, nullptr, blockIdx.x, sh);
 }
 

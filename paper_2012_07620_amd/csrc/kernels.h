@@ -11,17 +11,16 @@ enum class FinalPrec : int { F32 = 0, BF16X3 = 1, SPARSE = 2 };
 
 // Sparse layers (used with the sparse final product): every propagated row is
 // stored as CSR entries (columns ascending) in a slot of the layer's output
-// buffer. One gate per layer l (gate 0 = h^(0), always sparse):
-//   total  sum over rows of the slot bound min(n, sum of the k2 members' entry
-//          counts), computed before the layer runs;
-//   cursor slot allocator (rows take their slots in any order; the values do
-//          not depend on where a row is placed);
-//   dense  1 when layer l was written as dense rows instead (its bound total
-//          exceeded the buffer, or an earlier layer was dense).
+// buffer. Row i's slot holds min(n, sum of its k2 members' entry counts)
+// entries; the slots are laid out by a prefix sum before the layer runs. One
+// gate per layer l (gate 0 = h^(0), always sparse):
+//   total  the sum of the slot sizes;
+//   dense  1 when layer l is written as dense rows instead (the slots would
+//          not fit in the buffer, or an earlier layer was dense).
 struct SlGate {
   unsigned long long total;
-  int32_t cursor;
   int32_t dense;
+  int32_t pad;
 };
 // CSR rows of one layer: entries of row i are col/val[so[i] .. so[i] + cnt[i]).
 struct SlRows {
@@ -115,18 +114,19 @@ hipError_t launch_first_layer(const int32_t* knn_idx, const float* knn_val, cons
                               const int32_t* off, const int32_t* inl, int n, int k1, int k2, int alpha, int agg,
                               bool sym, int64_t ld, float* hout, float* sout, uint16_t* hi, uint16_t* lo,
                               const SlOut* sl, hipStream_t s);
-// Sparse layers. Slot bounds of layer l (first: members' A* / A entry counts
+// Sparse layers. Slot sizes of layer l (first: members' A* / A entry counts
 // from the kNN lists and the in-edge offsets `off` (A* only); otherwise the
-// previous layer's row counts), summed into gates[l].total. No-op when
-// gates[l - 1] is dense.
-hipError_t launch_sl_bounds(const int32_t* knn_idx, int n, int k1, int k2, bool first, bool sym, const int32_t* off,
-                            const int32_t* cnt_prev, SlGate* gates, int l, hipStream_t s);
+// previous layer's row counts) into out.cnt, their prefix sum into out.so,
+// and gates[l] (dense when the total exceeds out.cap or gates[l - 1] is
+// dense). The layer then overwrites out.cnt with the rows' actual counts.
+hipError_t launch_sl_slots(const int32_t* knn_idx, int n, int k1, int k2, bool first, bool sym, const int32_t* off,
+                           const int32_t* cnt_prev, const SlOut& out, hipStream_t s);
 // Layer l >= 2 from the CSR rows of layer l - 1 (runs when gates[l - 1] is
 // sparse): CSR out, or dense rows into hout when gates[l] turns dense.
 hipError_t launch_sparse_prop(SlRows in, const float* sin, const int32_t* knn_idx, const float* knn_val, int n,
                               int k1, int k2, int alpha, int agg, int64_t ld, float* hout, float* sout, SlOut out,
                               hipStream_t s);
-// The dense layer, run only when gates[l - 1] is dense (then marks gates[l]).
+// The dense layer, run only when gates[l - 1] is dense.
 hipError_t launch_propagate_gated(const float* hin, const float* sin, int n, int64_t ld, const int32_t* knn_idx,
                                   const float* knn_val, int k1, int k2, int alpha, int agg, float* hout, float* sout,
                                   SlGate* gates, int l, hipStream_t s);

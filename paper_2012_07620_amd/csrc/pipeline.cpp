@@ -166,8 +166,8 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
       if (P.sparse_layers) {
         SlGate* gates = at<SlGate>(ws, P.o_slg);
         RR_TRY(launch_fill_zero((float*)gates, (int64_t)(P.layers + 1) * (sizeof(SlGate) / 4), s));
-        RR_TRY(launch_sl_bounds(ki, P.n, P.k1, P.k2, true, sym, off, nullptr, gates, 1, s));
         const SlOut o = sl_out(P, ws, B, 1);
+        RR_TRY(launch_sl_slots(ki, P.n, P.k1, P.k2, true, sym, off, nullptr, o, s));
         RR_TRY(launch_first_layer(ki, kv, mflag, off, inl, P.n, P.k1, P.k2, P.alpha, P.agg, sym, P.ldN, B, sa,
                                   nullptr, nullptr, &o, s));
       } else {
@@ -202,9 +202,10 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
     if (P.sparse_layers) {  // layer l + 1 from the CSR rows of layer l (or dense once a layer turned dense)
       SlGate* gates = at<SlGate>(ws, P.o_slg);
       const SlOut prev = sl_out(P, ws, (float*)cur, l);
-      RR_TRY(launch_sl_bounds(ki, P.n, P.k1, P.k2, false, false, nullptr, prev.rows.cnt, gates, l + 1, s));
-      RR_TRY(launch_sparse_prop(prev.rows, csig, ki, kv, P.n, P.k1, P.k2, P.alpha, P.agg, P.ldH, out, osig,
-                                sl_out(P, ws, out, l + 1), s));
+      const SlOut next = sl_out(P, ws, out, l + 1);
+      RR_TRY(launch_sl_slots(ki, P.n, P.k1, P.k2, false, false, nullptr, prev.rows.cnt, next, s));
+      RR_TRY(launch_sparse_prop(prev.rows, csig, ki, kv, P.n, P.k1, P.k2, P.alpha, P.agg, P.ldH, out, osig, next,
+                                s));
       RR_TRY(launch_propagate_gated(cur, csig, P.n, P.ldH, ki, kv, P.k1, P.k2, P.alpha, P.agg, out, osig, gates, l + 1,
                                     s));
     } else {

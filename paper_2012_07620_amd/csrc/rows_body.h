@@ -482,84 +482,213 @@ __device__ __forceinline__ void csr_pair(const int32_t* __restrict__ knn, int n,
   inl[off[j] + pos] = (int)(t / k1);
 }
 
-// First layer without a dense h^(0): u_i = sum_r c_r A*_{j_r}, built in LDS
-// one column chunk at a time from the sparse A* rows, in member order r, with
-// the same FMA sequence and per-thread column order as propagate_row on a
-// dense A* (so the result is identical), then written once.
-constexpr int FIRST_CHUNK = 8192;  // floats of the output row held in LDS
-constexpr int FIRST_ENTRIES = 2048; // sparse A* entries of one row staged in LDS
+// Rows built from sparse member rows (the first layer from A* / A, and the
+// sparse layers from CSR rows), one LDS column chunk at a time.
+constexpr int FIRST_CHUNK = 8192;    // floats of the output row held in LDS
+constexpr int FIRST_WORDS = FIRST_CHUNK / 32;  // touched-column bitmap of a chunk
+constexpr int FIRST_ENTRIES = 2048;  // member entries of one row staged in LDS
 struct FirstShared {
   PropShared p;
-  float row[FIRST_CHUNK];
+  float row[FIRST_CHUNK];      // sums; valid only where the bitmap is set
+  uint32_t bits[FIRST_WORDS];  // columns of the chunk touched so far
   int col[FIRST_ENTRIES];
   float val[FIRST_ENTRIES];
   int start[257];  // entries of member r are [start[r], start[r+1])
-  int wsum[4];     // per-wave counts of a CSR store step
-  int obase;       // first entry of the row's CSR slot
+  int mcnt[256];   // entry count of member r
+  int mbase[256];  // where member r's entries start in its source
+  int wsum[4];     // per-wave counts of a CSR store
 };
 
-// ---------------------------------------------------------------- CSR rows
-// Sparse-layer output: decide dense or CSR for this layer (the same answer in
-// every workgroup: it reads only gates written by earlier launches), mark the
-// gate from workgroup 0, and take this row's slot of min(n, bound) entries.
-// Returns true for CSR output; *pos is the slot's first entry.
-__device__ __forceinline__ bool sl_begin(const SlOut* o, int bound, int i, FirstShared& sh, int* pos) {
-  if (!o) return false;
-  const unsigned long long total = o->gate->total;
-  const bool dense = o->prev->dense != 0 || total > (unsigned long long)o->cap || total > 0x7FFFFFFFull;
-  if (threadIdx.x == 0) {
-    if (i == 0) o->gate->dense = dense ? 1 : 0;
-    if (!dense) sh.obase = atomicAdd(&o->gate->cursor, min(bound, o->n));
+// ---------------------------------------------------------------- sparse rows
+// Sparse-layer output: CSR unless the layer's gate (set before the layer by
+// the slot layout) says dense. *pos is the first entry of row i's slot.
+__device__ __forceinline__ bool sl_begin(const SlOut* o, int i, int* pos) {
+  if (!o || o->gate->dense) return false;
+  *pos = o->rows.so[i];
+  return true;
+}
+
+// Entries of the vertex feature h^(0)_j: A* row j (sym) is its out-list
+// N(j, k1) (value 1 when the pair is mutual, else 1/2) followed by its
+// non-mutual in-edges (value 1/2); an A row (not sym) is its out-list, value 1.
+struct FirstSrc {
+  const int32_t* knn;
+  const uint8_t* mflag;
+  const int32_t* off;
+  const int32_t* inl;
+  int k1;
+  bool sym;
+  __device__ int count(int j) const { return k1 + (sym ? off[j + 1] - off[j] : 0); }
+  __device__ int base(int j) const { return sym ? off[j] : 0; }
+  __device__ void entry(int j, int mbase, int e, int* c, float* v) const {
+    if (e < k1) {
+      *c = knn[(int64_t)j * k1 + e];
+      *v = (!sym || mflag[(int64_t)j * k1 + e]) ? 1.0f : 0.5f;
+    } else {
+      *c = inl[mbase + e - k1];
+      *v = 0.5f;
+    }
+  }
+};
+
+// Entries of a CSR row of the previous sparse layer.
+struct CsrSrc {
+  SlRows in;
+  __device__ int count(int j) const { return in.cnt[j]; }
+  __device__ int base(int j) const { return in.so[j]; }
+  __device__ void entry(int, int mbase, int e, int* c, float* v) const {
+    *c = in.col[mbase + e];
+    *v = in.val[mbase + e];
+  }
+};
+
+// row[m] += c * v in member order; the first touch of a column starts from 0.
+__device__ __forceinline__ void sparse_add(FirstShared& sh, int m, float c, float v) {
+  const uint32_t bit = 1u << (m & 31);
+  const uint32_t old = atomicOr(&sh.bits[m >> 5], bit);
+  sh.row[m] = __builtin_fmaf(c, v, (old & bit) ? sh.row[m] : 0.0f);
+}
+
+// u_i = sum_r cf_r h_{j_r} over the k2 members (coefficients already in sh.p)
+// from sparse member rows, one LDS column chunk at a time, in member order r
+// with one FMA per entry: the same sums, rounding for rounding, as
+// propagate_row on dense rows (a zero entry there is an FMA that leaves the
+// sum unchanged). Written as dense rows (hout, or bf16 hi/lo planes) or as a
+// CSR row (sl); the squared norm is accumulated in the dense store's
+// per-thread order (thread t owns float4 columns t, t + 256, ... of a chunk),
+// so sigma is identical either way.
+template <class Src>
+__device__ __forceinline__ void sparse_row_core(const Src& src, int k2, int64_t ld, float* __restrict__ hout,
+                                                uint16_t* __restrict__ hi, uint16_t* __restrict__ lo,
+                                                float* __restrict__ sout, const SlOut* sl, int i, FirstShared& sh) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid < k2) {
+    const int j = sh.p.nb[tid];
+    sh.mcnt[tid] = src.count(j);
+    sh.mbase[tid] = src.base(j);
   }
   __syncthreads();
-  *pos = sh.obase;
-  return !dense;
-}
-
-// Append the non-zeros of the LDS chunk row[0, width) (columns c0 + k) to the
-// row's CSR slot at *pos, columns ascending, and add their squares to ss in
-// the same per-thread order as the dense store (thread t owns float4 columns
-// t, t + 256, ...). Every thread ends with the same *pos.
-__device__ __forceinline__ void store_chunk_csr(const float* row, int width, int64_t c0, const SlRows& out, int* pos,
-                                                FirstShared& sh, float* ss) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int w4 = width >> 2;
-  for (int cb = 0; cb < w4; cb += 256) {
-    const int c = cb + tid;
-    f32x4 v = {0.f, 0.f, 0.f, 0.f};
-    if (c < w4) {
-      v = ((const f32x4*)row)[c];
-      *ss = sq_acc4(*ss, v);
+  if (tid == 0) {
+    int acc = 0;
+    for (int r = 0; r < k2; r++) {
+      sh.start[r] = acc;
+      acc += sh.mcnt[r];
     }
-    const int mine = (v.x != 0.f) + (v.y != 0.f) + (v.z != 0.f) + (v.w != 0.f);
-    int incl = mine;  // inclusive prefix over the wave
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t = __shfl_up(incl, o, kWave);
-      if (lane >= o) incl += t;
+    sh.start[k2] = acc;
+  }
+  __syncthreads();
+  const int total_e = sh.start[k2];
+  const bool staged = total_e <= FIRST_ENTRIES;
+  if (staged) {  // all entries at once: member of entry e = last r with start[r] <= e
+    for (int e = tid; e < total_e; e += 256) {
+      int lo_r = 0, hi_r = k2 - 1;
+      while (lo_r < hi_r) {
+        const int mid = (lo_r + hi_r + 1) >> 1;
+        if (sh.start[mid] <= e)
+          lo_r = mid;
+        else
+          hi_r = mid - 1;
+      }
+      int c;
+      float v;
+      src.entry(sh.p.nb[lo_r], sh.mbase[lo_r], e - sh.start[lo_r], &c, &v);
+      sh.col[e] = c;
+      sh.val[e] = v;
     }
-    if (lane == 63) sh.wsum[w] = incl;
+  }
+  __syncthreads();
+  int pos = 0;
+  const bool csr = sl_begin(sl, i, &pos);
+  const int pos0 = pos;
+  float ss = 0.f;
+  for (int64_t c0 = 0; c0 < ld; c0 += FIRST_CHUNK) {
+    const int width = (int)min((int64_t)FIRST_CHUNK, ld - c0);
+    for (int k = tid; k < FIRST_WORDS; k += 256) sh.bits[k] = 0u;
     __syncthreads();
-    int before = 0, total = 0;
-    for (int x = 0; x < 4; x++) {
-      before += (x < w) ? sh.wsum[x] : 0;
-      total += sh.wsum[x];
+    for (int r = 0; r < k2; r++) {
+      const float c = sh.p.cf[r];
+      if (staged) {
+        for (int s = sh.start[r] + tid; s < sh.start[r + 1]; s += 256) {
+          const int64_t m = sh.col[s] - c0;
+          if (m >= 0 && m < width) sparse_add(sh, (int)m, c, sh.val[s]);
+        }
+      } else {  // too many entries to stage: read them from memory for every chunk
+        const int j = sh.p.nb[r], mb = sh.mbase[r];
+        for (int e = tid; e < sh.mcnt[r]; e += 256) {
+          int cc;
+          float v;
+          src.entry(j, mb, e, &cc, &v);
+          const int64_t m = cc - c0;
+          if (m >= 0 && m < width) sparse_add(sh, (int)m, c, v);
+        }
+      }
+      __syncthreads();
     }
-    int at = *pos + before + incl - mine;
-    const float e4[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int e = 0; e < 4; e++)
-      if (e4[e] != 0.f) {
-        out.col[at] = (int32_t)(c0 + (int64_t)c * 4 + e);
-        out.val[at] = e4[e];
+    const int w4 = width >> 2;
+    if (!csr) {
+      for (int c = tid; c < w4; c += 256) {
+        const uint32_t nib = (sh.bits[c >> 3] >> ((c & 7) * 4)) & 0xFu;
+        const f32x4 acc = {(nib & 1u) ? sh.row[4 * c] : 0.f, (nib & 2u) ? sh.row[4 * c + 1] : 0.f,
+                           (nib & 4u) ? sh.row[4 * c + 2] : 0.f, (nib & 8u) ? sh.row[4 * c + 3] : 0.f};
+        if (hi)
+          split_store4(hi, lo, (int64_t)i * ld + c0 + c * 4, acc);
+        else
+          ((f32x4*)(hout + (int64_t)i * ld + c0))[c] = acc;
+        ss = sq_acc4(ss, acc);
+      }
+    } else {
+      for (int c = tid; c < w4; c += 256) {  // squares in the dense order (skipped zeros change nothing)
+        const uint32_t nib = (sh.bits[c >> 3] >> ((c & 7) * 4)) & 0xFu;
+        for (int e = 0; e < 4; e++)
+          if (nib & (1u << e)) {
+            const float v = sh.row[4 * c + e];
+            ss = __builtin_fmaf(v, v, ss);
+          }
+      }
+      // word t of the bitmap = columns 32t .. 32t + 31; keep the non-zero sums
+      uint32_t keep = 0u;
+      if (tid < (width >> 5)) {
+        uint32_t wd = sh.bits[tid];
+        while (wd) {
+          const int b = __builtin_ctz(wd);
+          wd &= wd - 1u;
+          if (sh.row[32 * tid + b] != 0.f) keep |= 1u << b;
+        }
+      }
+      const int mine = __builtin_popcount(keep);
+      int incl = mine;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += t;
+      }
+      if (lane == 63) sh.wsum[w] = incl;
+      __syncthreads();
+      int at = pos + incl - mine, total = 0;
+      for (int x = 0; x < 4; x++) {
+        at += (x < w) ? sh.wsum[x] : 0;
+        total += sh.wsum[x];
+      }
+      while (keep) {
+        const int b = __builtin_ctz(keep);
+        keep &= keep - 1u;
+        sl->rows.col[at] = (int32_t)(c0 + 32 * tid + b);
+        sl->rows.val[at] = sh.row[32 * tid + b];
         at++;
       }
-    *pos += total;
-    __syncthreads();  // wsum is rewritten by the next step
+      pos += total;
+    }
+    __syncthreads();  // bits, row and wsum are reused by the next chunk
   }
+  if (csr && tid == 0) {
+    sl->rows.so[i] = pos0;
+    sl->rows.cnt[i] = pos - pos0;
+  }
+  finish_norm(ss, sout, i, sh.p);
 }
 
-// sym = false: h^(0) = rows of A (out-list entries only, value 1). The
-// aggregator is sum or mean (max runs the dense layer).
+// First layer without a dense h^(0): u_i = sum_r c_r h^(0)_{j_r} from the
+// sparse A* (sym) or A rows. The aggregator is sum or mean (max runs the
+// dense layer).
 __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn, const float* __restrict__ kv,
                                                 const uint8_t* __restrict__ mflag, const int32_t* __restrict__ off,
                                                 const int32_t* __restrict__ inl, int k1, int k2, int alpha, int agg,
@@ -567,167 +696,21 @@ __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn,
                                                 float* __restrict__ sout, uint16_t* __restrict__ hi,
                                                 uint16_t* __restrict__ lo, int i, FirstShared& sh,
                                                 const SlOut* sl = nullptr) {
-  const int tid = threadIdx.x;
   load_coefs(nullptr, knn, kv, k1, k2, alpha, agg, i, sh.p);
-  // entry counts per member: out-list (k1) + non-mutual in-list (A* only)
-  if (tid == 0) {
-    int acc = 0;
-    for (int r = 0; r < k2; r++) {
-      sh.start[r] = acc;
-      const int j = sh.p.nb[r];
-      acc += k1 + (sym ? off[j + 1] - off[j] : 0);
-    }
-    sh.start[k2] = acc;
-  }
-  __syncthreads();
-  const bool staged = sh.start[k2] <= FIRST_ENTRIES;
-  if (staged) {
-    for (int r = 0; r < k2; r++) {
-      const int j = sh.p.nb[r];
-      const int base = sh.start[r];
-      const int32_t* lj = knn + (int64_t)j * k1;
-      const uint8_t* fj = sym ? mflag + (int64_t)j * k1 : nullptr;
-      for (int s = tid; s < k1; s += 256) {
-        sh.col[base + s] = lj[s];
-        sh.val[base + s] = (!sym || fj[s]) ? 1.0f : 0.5f;
-      }
-      const int b = sym ? off[j] : 0, n_in = sym ? off[j + 1] - b : 0;
-      for (int s = tid; s < n_in; s += 256) {
-        sh.col[base + k1 + s] = inl[b + s];
-        sh.val[base + k1 + s] = 0.5f;
-      }
-    }
-  }
-  __syncthreads();
-  int pos = 0;
-  const bool csr = sl_begin(sl, sh.start[k2], i, sh, &pos);
-  const int pos0 = pos;
-  float ss = 0.f;
-  for (int64_t c0 = 0; c0 < ld; c0 += FIRST_CHUNK) {
-    const int width = (int)min((int64_t)FIRST_CHUNK, ld - c0);
-    for (int k = tid; k < FIRST_CHUNK; k += 256) sh.row[k] = 0.f;
-    __syncthreads();
-    for (int r = 0; r < k2; r++) {
-      const float c = sh.p.cf[r];
-      if (staged) {
-        for (int s = sh.start[r] + tid; s < sh.start[r + 1]; s += 256) {
-          const int64_t m = sh.col[s] - c0;
-          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, sh.val[s], sh.row[m]);
-        }
-      } else {  // very large in-degree: read the entries from memory
-        const int j = sh.p.nb[r];
-        const int32_t* lj = knn + (int64_t)j * k1;
-        const uint8_t* fj = sym ? mflag + (int64_t)j * k1 : nullptr;
-        for (int s = tid; s < k1; s += 256) {
-          const int64_t m = lj[s] - c0;
-          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, (!sym || fj[s]) ? 1.0f : 0.5f, sh.row[m]);
-        }
-        const int b = sym ? off[j] : 0, e = sym ? off[j + 1] : 0;
-        for (int s = b + tid; s < e; s += 256) {
-          const int64_t m = inl[s] - c0;
-          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, 0.5f, sh.row[m]);
-        }
-      }
-      __syncthreads();
-    }
-    if (csr) {
-      store_chunk_csr(sh.row, width, c0, sl->rows, &pos, sh, &ss);
-    } else {
-      const int w4 = width >> 2;
-      for (int c = tid; c < w4; c += 256) {
-        const f32x4 acc = ((const f32x4*)sh.row)[c];
-        if (hi)
-          split_store4(hi, lo, (int64_t)i * ld + c0 + c * 4, acc);
-        else
-          ((f32x4*)(hout + (int64_t)i * ld + c0))[c] = acc;
-        ss = sq_acc4(ss, acc);
-      }
-    }
-    __syncthreads();
-  }
-  if (csr && tid == 0) {
-    sl->rows.so[i] = pos0;
-    sl->rows.cnt[i] = pos - pos0;
-  }
-  finish_norm(ss, sout, i, sh.p);
+  const FirstSrc src{knn, mflag, off, inl, k1, sym};
+  sparse_row_core(src, k2, ld, hout, hi, lo, sout, sl, i, sh);
 }
 
-// Layer l >= 2 of the sparse layers: u_i = sum_r c_r h_{j_r} from the CSR
-// rows of layer l - 1 (coefficients from load_coefs with their carried
-// 1/|u_j|), built in LDS column chunks in member order r with one FMA per
-// entry: the same sums, rounding for rounding, as propagate_row on the dense
-// rows (a zero entry there is an FMA that leaves the sum unchanged).
-// Sum and mean aggregators.
+// Layer l >= 2 of the sparse layers from the CSR rows of layer l - 1
+// (coefficients carry the rows' 1/|u_j|). Sum and mean aggregators.
 __device__ __forceinline__ void sparse_prop_row(const SlRows& in, const float* __restrict__ sin,
                                                 const int32_t* __restrict__ knn, const float* __restrict__ kv,
                                                 int k1, int k2, int alpha, int agg, int64_t ld,
                                                 float* __restrict__ hout, float* __restrict__ sout, const SlOut* sl,
                                                 int i, FirstShared& sh) {
-  const int tid = threadIdx.x;
   load_coefs(sin, knn, kv, k1, k2, alpha, agg, i, sh.p);
-  if (tid == 0) {
-    int acc = 0;
-    for (int r = 0; r < k2; r++) {
-      sh.start[r] = acc;
-      acc += in.cnt[sh.p.nb[r]];
-    }
-    sh.start[k2] = acc;
-  }
-  __syncthreads();
-  const bool staged = sh.start[k2] <= FIRST_ENTRIES;
-  if (staged) {
-    for (int r = 0; r < k2; r++) {
-      const int j = sh.p.nb[r];
-      const int b = in.so[j], base = sh.start[r], len = sh.start[r + 1] - base;
-      for (int s = tid; s < len; s += 256) {
-        sh.col[base + s] = in.col[b + s];
-        sh.val[base + s] = in.val[b + s];
-      }
-    }
-  }
-  __syncthreads();
-  int pos = 0;
-  const bool csr = sl_begin(sl, sh.start[k2], i, sh, &pos);
-  const int pos0 = pos;
-  float ss = 0.f;
-  for (int64_t c0 = 0; c0 < ld; c0 += FIRST_CHUNK) {
-    const int width = (int)min((int64_t)FIRST_CHUNK, ld - c0);
-    for (int k = tid; k < FIRST_CHUNK; k += 256) sh.row[k] = 0.f;
-    __syncthreads();
-    for (int r = 0; r < k2; r++) {
-      const float c = sh.p.cf[r];
-      if (staged) {
-        for (int s = sh.start[r] + tid; s < sh.start[r + 1]; s += 256) {
-          const int64_t m = sh.col[s] - c0;
-          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, sh.val[s], sh.row[m]);
-        }
-      } else {
-        const int j = sh.p.nb[r];
-        const int b = in.so[j], e = b + in.cnt[j];
-        for (int s = b + tid; s < e; s += 256) {
-          const int64_t m = in.col[s] - c0;
-          if (m >= 0 && m < width) sh.row[m] = __builtin_fmaf(c, in.val[s], sh.row[m]);
-        }
-      }
-      __syncthreads();
-    }
-    if (csr) {
-      store_chunk_csr(sh.row, width, c0, sl->rows, &pos, sh, &ss);
-    } else {
-      const int w4 = width >> 2;
-      for (int c = tid; c < w4; c += 256) {
-        const f32x4 acc = ((const f32x4*)sh.row)[c];
-        ((f32x4*)(hout + (int64_t)i * ld + c0))[c] = acc;
-        ss = sq_acc4(ss, acc);
-      }
-    }
-    __syncthreads();
-  }
-  if (csr && tid == 0) {
-    sl->rows.so[i] = pos0;
-    sl->rows.cnt[i] = pos - pos0;
-  }
-  finish_norm(ss, sout, i, sh.p);
+  const CsrSrc src{in};
+  sparse_row_core(src, k2, ld, hout, nullptr, nullptr, sout, sl, i, sh);
 }
 
 }  // namespace rr
