@@ -5,6 +5,15 @@
 
 namespace rr {
 
+// Workgroups are dealt to the 8 XCDs round-robin (each XCD has its own L2).
+// Renumber them so each XCD gets a contiguous run of logical indices: work
+// that is close in logical order then shares one L2.
+__device__ __forceinline__ int xcd_linear(int bid, int nwg) {
+  const int q = nwg >> 3, rem = nwg & 7;
+  const int x = bid & 7, local = bid >> 3;
+  return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + local;
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));

@@ -9,14 +9,8 @@ struct TileMap {
   int tm, tn;
 };
 
-// Workgroups are dealt to the 8 XCDs round-robin. Renumber them so each XCD
-// gets a contiguous run of logical tiles, then walk the tiles in groups of 8
+// Tiles are renumbered per XCD (xcd_linear), then walked in groups of 8
 // row-tiles so neighbouring workgroups on an XCD share A and B rows in its L2.
-__device__ __forceinline__ int xcd_linear(int bid, int nwg) {
-  const int q = nwg >> 3, rem = nwg & 7;
-  const int x = bid & 7, local = bid >> 3;
-  return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + local;
-}
 
 __device__ __forceinline__ TileMap grouped_order(int pid, int tiles_m, int tiles_n) {
   constexpr int G = 8;

@@ -7,27 +7,68 @@
 namespace rr {
 
 // ---------------------------------------------------------------- a3b
+// Re-score order: rows whose candidate lists overlap (a cluster of mutual
+// neighbours) share the key min(i, candidates of i); a counting sort by key
+// puts them next to each other, and the re-score walks that order with
+// consecutive rows on one XCD, so a candidate row is fetched into an L2 once
+// for the rows of its cluster instead of once per row.
+__global__ void order_key_kernel(const int32_t* __restrict__ cand, int n, int Kc, int32_t* __restrict__ key,
+                                 int32_t* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int m = i;
+  for (int c = 0; c < Kc; c++) m = min(m, cand[(int64_t)i * Kc + c]);
+  key[i] = m;
+  atomicAdd(cnt + m, 1);
+}
+
+__global__ void order_place_kernel(const int32_t* __restrict__ key, int n, const int32_t* __restrict__ off,
+                                   int32_t* __restrict__ cursor, int32_t* __restrict__ order) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = key[i];
+  order[off[k] + atomicAdd(cursor + k, 1)] = i;
+}
+
 template <int R>
 __global__ __launch_bounds__(256) void rescore_kernel(const float* __restrict__ xp, int64_t ldp,
                                                       const float* __restrict__ rn, int n,
                                                       const int32_t* __restrict__ cand, int Kc, int k1,
-                                                      int32_t* __restrict__ kidx, float* __restrict__ kval) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
+                                                      int32_t* __restrict__ kidx, float* __restrict__ kval,
+                                                      const int32_t* __restrict__ order) {
+  const int p = (order ? xcd_linear(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (p >= n) return;
+  const int i = order ? order[p] : p;
   rescore_row<R>(xp, ldp, rn, i, cand, Kc, k1, kidx, kval);
 }
 
 hipError_t launch_rescore(const float* xp, int64_t ldp, int d, const float* rn, int n, const int32_t* cand, int Kc,
-                          int k1, int32_t* knn_idx, float* knn_val, hipStream_t s) {
+                          int k1, int32_t* knn_idx, float* knn_val, int32_t* scratch, hipStream_t s) {
   (void)d;
   if (Kc < k1 || Kc > 256 || (ldp & 3)) return hipErrorInvalidValue;
+  const int32_t* order = nullptr;
+  if (scratch) {  // cnt[n], cursor[n], key[n], off[n + 1], order[n]
+    int32_t* cnt = scratch;
+    int32_t* cursor = cnt + n;
+    int32_t* key = cursor + n;
+    int32_t* off = key + n;
+    int32_t* ord = off + n + 1;
+    hipError_t e = launch_fill_zero((float*)cnt, 2 * (int64_t)n, s);
+    if (e != hipSuccess) return e;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(order_key_kernel, dim3(g), dim3(256), 0, s, cand, n, Kc, key, cnt);
+    e = launch_scan(cnt, n, off, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(order_place_kernel, dim3(g), dim3(256), 0, s, key, n, off, cursor, ord);
+    order = ord;
+  }
   dim3 grid((n + 3) / 4), block(256);
   if (Kc <= 64)
-    hipLaunchKernelGGL(rescore_kernel<1>, grid, block, 0, s, xp, ldp, rn, n, cand, Kc, k1, knn_idx, knn_val);
+    hipLaunchKernelGGL(rescore_kernel<1>, grid, block, 0, s, xp, ldp, rn, n, cand, Kc, k1, knn_idx, knn_val, order);
   else if (Kc <= 128)
-    hipLaunchKernelGGL(rescore_kernel<2>, grid, block, 0, s, xp, ldp, rn, n, cand, Kc, k1, knn_idx, knn_val);
+    hipLaunchKernelGGL(rescore_kernel<2>, grid, block, 0, s, xp, ldp, rn, n, cand, Kc, k1, knn_idx, knn_val, order);
   else
-    hipLaunchKernelGGL(rescore_kernel<4>, grid, block, 0, s, xp, ldp, rn, n, cand, Kc, k1, knn_idx, knn_val);
+    hipLaunchKernelGGL(rescore_kernel<4>, grid, block, 0, s, xp, ldp, rn, n, cand, Kc, k1, knn_idx, knn_val, order);
   return hipGetLastError();
 }
 

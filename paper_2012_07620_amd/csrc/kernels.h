@@ -73,8 +73,11 @@ hipError_t launch_topk(const float* S, int64_t ldS, int N, int rows, int K, int3
                        int ldo, hipStream_t s);
 
 // a3b: FP32 compensated re-score of Kc candidates per row, then the k1 cut.
+// scratch (5 n + 1 int32, 16-byte aligned) or nullptr: rows are re-scored in
+// an order that keeps rows with shared candidates on one XCD (the results do
+// not depend on the order).
 hipError_t launch_rescore(const float* xp, int64_t ldp, int d, const float* rn, int n, const int32_t* cand,
-                          int Kc, int k1, int32_t* knn_idx, float* knn_val, hipStream_t s);
+                          int Kc, int k1, int32_t* knn_idx, float* knn_val, int32_t* scratch, hipStream_t s);
 // Copy the first k1 of Kc candidates (no re-score).
 hipError_t launch_take_prefix(const int32_t* cand_idx, const float* cand_val, int n, int Kc, int k1,
                               int32_t* knn_idx, float* knn_val, hipStream_t s);
