@@ -1,6 +1,5 @@
 // a2 / a7 -- direct launches of the matrix-core products (one 128 x 128 tile
 // per workgroup); the tile engine is in gemm_body.h.
-#include "gemm_big.h"
 #include "gemm_body.h"
 #include "kernels.h"
 
@@ -49,37 +48,15 @@ static hipError_t launch_gemm_t(const void* a, int M, int64_t lda, const void* b
   return hipGetLastError();
 }
 
-// Low-precision symmetric similarity on 256 x 256 tiles (upper triangle, the
-// mirror written through LDS); one workgroup per CU.
-template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void gemm_big_sym_kernel(GemmArgs g,
-                                                                                                        int tiles) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[BIG_LDS_BYTES];
-  int tm, tn;
-  upper_tile(xcd_linear(blockIdx.x, gridDim.x), tiles, tm, tn);
-  gemm_tile_big<MODE>(g, tm, tn, tm != tn, lds);
-}
-
-template <int MODE>
-static hipError_t launch_gemm_big_sym(const void* a, int M, int64_t lda, int64_t kbytes, const float* sa, float* out,
-                                      int64_t ldo, hipStream_t s) {
-  const int T = (M + BT - 1) / BT;
-  const int64_t nwg = (int64_t)T * (T + 1) / 2;
-  if (nwg <= 0 || nwg > 0x7FFFFFFF || kbytes % BKB || kbytes <= 0) return hipErrorInvalidValue;
-  GemmArgs g{(const uint8_t*)a, (const uint8_t*)a, M, M, lda, lda, (int)(kbytes / BKB), sa, sa, out, ldo};
-  hipLaunchKernelGGL((gemm_big_sym_kernel<MODE>), dim3((unsigned)nwg), dim3(256), 0, s, g, T);
-  return hipGetLastError();
-}
-
 hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes, const float* sa,
                            float* out, int64_t ldo, hipStream_t s) {
   switch (prec) {
     case SimPrec::F32:
       return launch_gemm_t<MODE_F32, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, out, ldo, s);
     case SimPrec::BF16:
-      return launch_gemm_big_sym<MODE_BF16>(a, M, lda_bytes, kbytes, sa, out, ldo, s);
+      return launch_gemm_t<MODE_BF16, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, out, ldo, s);
     case SimPrec::FP8:
-      return launch_gemm_big_sym<MODE_FP8>(a, M, lda_bytes, kbytes, sa, out, ldo, s);
+      return launch_gemm_t<MODE_FP8, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, out, ldo, s);
   }
   return hipErrorInvalidValue;
 }
