@@ -195,7 +195,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-lowp", action="store_true")
+    ap.add_argument("--no-lowp", action="store_true", help="skip every variant line")
+    ap.add_argument("--variants", default="", help="comma-separated variant names to time (default: all)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -237,6 +238,8 @@ def main() -> int:
                                   ("f32_final_bf16x3", "f32", "bf16x3"), ("bf16_final_bf16x3", "bf16", "bf16x3"),
                                   ("f32_final_sparse", "f32", "sparse"), ("bf16_final_sparse", "bf16", "sparse"),
                                   ("fp8_final_sparse", "fp8", "sparse")):
+            if args.variants and name not in args.variants.split(","):
+                continue
             log(f"timing {name} path")
             out_l = torch.empty_like(out)
             ms_l, st_l = time_path(binding, torch, ctx, x, spec, prec, args.steps, args.warmup, out_l, fprec)

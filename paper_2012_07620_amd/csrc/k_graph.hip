@@ -7,27 +7,44 @@
 namespace rr {
 
 // ---------------------------------------------------------------- a3b
-// Re-score order: rows whose candidate lists overlap (a cluster of mutual
-// neighbours) share the key min(i, candidates of i); a counting sort by key
-// puts them next to each other, and the re-score walks that order with
-// consecutive rows on one XCD, so a candidate row is fetched into an L2 once
-// for the rows of its cluster instead of once per row.
-__global__ void order_key_kernel(const int32_t* __restrict__ cand, int n, int Kc, int32_t* __restrict__ key,
+// Cluster order: rows whose lists overlap (a cluster of mutual neighbours)
+// share the key min(i, entries of row i); a counting sort by key puts them
+// next to each other. Kernels that walk rows in this order with consecutive
+// rows on one XCD (xcd_linear) fetch the rows a cluster shares into that
+// XCD's L2 once instead of once per row.
+__global__ void order_key_kernel(const int32_t* __restrict__ lists, int rows, int w, int32_t* __restrict__ key,
                                  int32_t* __restrict__ cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= rows) return;
   int m = i;
-  for (int c = 0; c < Kc; c++) m = min(m, cand[(int64_t)i * Kc + c]);
+  for (int c = 0; c < w; c++) m = min(m, lists[(int64_t)i * w + c]);
   key[i] = m;
   atomicAdd(cnt + m, 1);
 }
 
-__global__ void order_place_kernel(const int32_t* __restrict__ key, int n, const int32_t* __restrict__ off,
+__global__ void order_place_kernel(const int32_t* __restrict__ key, int rows, const int32_t* __restrict__ off,
                                    int32_t* __restrict__ cursor, int32_t* __restrict__ order) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= rows) return;
   const int k = key[i];
   order[off[k] + atomicAdd(cursor + k, 1)] = i;
+}
+
+hipError_t launch_cluster_order(const int32_t* lists, int rows, int w, int n, int32_t* scratch, int32_t* order,
+                                hipStream_t s) {
+  if (rows < 1 || rows > n || w < 1 || ((uintptr_t)scratch & 15)) return hipErrorInvalidValue;
+  int32_t* cnt = scratch;  // cnt[n], cursor[n], key[rows], off[n + 1]
+  int32_t* cursor = cnt + n;
+  int32_t* key = cursor + n;
+  int32_t* off = key + rows;
+  hipError_t e = launch_fill_zero((float*)cnt, 2 * (int64_t)n, s);
+  if (e != hipSuccess) return e;
+  const unsigned g = (unsigned)((rows + 255) / 256);
+  hipLaunchKernelGGL(order_key_kernel, dim3(g), dim3(256), 0, s, lists, rows, w, key, cnt);
+  e = launch_scan(cnt, n, off, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(order_place_kernel, dim3(g), dim3(256), 0, s, key, rows, off, cursor, order);
+  return hipGetLastError();
 }
 
 template <int R>
@@ -47,19 +64,10 @@ hipError_t launch_rescore(const float* xp, int64_t ldp, int d, const float* rn, 
   (void)d;
   if (Kc < k1 || Kc > 256 || (ldp & 3)) return hipErrorInvalidValue;
   const int32_t* order = nullptr;
-  if (scratch) {  // cnt[n], cursor[n], key[n], off[n + 1], order[n]
-    int32_t* cnt = scratch;
-    int32_t* cursor = cnt + n;
-    int32_t* key = cursor + n;
-    int32_t* off = key + n;
-    int32_t* ord = off + n + 1;
-    hipError_t e = launch_fill_zero((float*)cnt, 2 * (int64_t)n, s);
+  if (scratch) {  // cluster order of the rows by their candidates, then order[n]
+    int32_t* ord = scratch + cluster_order_ints(n, n);
+    hipError_t e = launch_cluster_order(cand, n, Kc, n, scratch, ord, s);
     if (e != hipSuccess) return e;
-    const unsigned g = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(order_key_kernel, dim3(g), dim3(256), 0, s, cand, n, Kc, key, cnt);
-    e = launch_scan(cnt, n, off, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(order_place_kernel, dim3(g), dim3(256), 0, s, key, n, off, cursor, ord);
     order = ord;
   }
   dim3 grid((n + 3) / 4), block(256);

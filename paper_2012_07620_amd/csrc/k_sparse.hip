@@ -178,8 +178,7 @@ __global__ __launch_bounds__(256) void nnz_count_kernel(const float* __restrict_
 // flag[0] = 1 (and off all zero) when the total exceeds cap. Skipped when
 // `skip_csr` says the rows are already CSR, or `skip_dense` selects the dense
 // product.
-__global__ __launch_bounds__(256) void scan_gate_kernel(const int32_t* __restrict__ cnt, int n,
-                                                        int32_t* __restrict__ off, int64_t cap,
+__global__ __launch_bounds__(256) void scan_gate_kernel(const int32_t* cnt, int n, int32_t* off, int64_t cap,
                                                         int32_t* __restrict__ flag, const SlGate* skip_csr,
                                                         const SparseSel* skip_dense) {
   if (input_is_csr(skip_csr) || (skip_dense && skip_dense->mode == 2)) return;
@@ -200,9 +199,10 @@ __global__ __launch_bounds__(256) void scan_gate_kernel(const int32_t* __restric
   const int64_t total = sh[255];
   const bool fits = total <= cap && total <= 0x7FFFFFFF;
   int64_t run = sh[tid] - sum;
-  for (int k = b; k < e; k++) {
+  for (int k = b; k < e; k++) {  // read before write: off may be cnt (in place)
+    const int32_t v = cnt[k];
     off[k] = fits ? (int32_t)run : 0;
-    run += cnt[k];
+    run += v;
   }
   if (tid == 0) {
     off[n] = fits ? (int32_t)total : 0;
@@ -270,10 +270,15 @@ __global__ void select_kernel(const SlGate* lay, SlRows lrows, const int32_t* fl
   *sel = o;
 }
 
-// Column layout of the gallery rows q..n-1, one wave per row: column counts,
-// then placement (the order inside a column is arbitrary; every entry of a
-// column goes to a different accumulator, so it does not affect the sums).
-__global__ __launch_bounds__(256) void csc_count_kernel(const SparseSel* __restrict__ sel, int q, int n,
+// Column layout of the gallery rows q..n-1, split by gallery chunk (the
+// accumulator width of one pass of the product): entry (g, c) goes to bucket
+// (g / SF_GCH) * ld + c, so a pass over one chunk reads only its own entries.
+// One wave per row: bucket counts, then placement (the order inside a bucket
+// is arbitrary; every entry of a bucket goes to a different accumulator, so
+// it does not affect the sums).
+constexpr int SF_GCH = kSparseChunk;  // gallery accumulators per pass (64 KiB of LDS)
+
+__global__ __launch_bounds__(256) void csc_count_kernel(const SparseSel* __restrict__ sel, int q, int n, int64_t ld,
                                                         int32_t* __restrict__ ccnt) {
   if (sel->mode == 2) return;
   const int32_t* rs = sel->rs;
@@ -282,11 +287,12 @@ __global__ __launch_bounds__(256) void csc_count_kernel(const SparseSel* __restr
   const int lane = threadIdx.x & 63;
   for (int r = q + (int)(blockIdx.x * 4 + (threadIdx.x >> 6)); r < n; r += gridDim.x * 4) {
     const int b = rs[r], e = b + rc[r];
-    for (int t = b + lane; t < e; t += 64) atomicAdd(ccnt + col[t], 1);
+    int32_t* cb = ccnt + (int64_t)((r - q) / SF_GCH) * ld;
+    for (int t = b + lane; t < e; t += 64) atomicAdd(cb + col[t], 1);
   }
 }
 
-__global__ __launch_bounds__(256) void csc_fill_kernel(const SparseSel* __restrict__ sel, int q, int n,
+__global__ __launch_bounds__(256) void csc_fill_kernel(const SparseSel* __restrict__ sel, int q, int n, int64_t ld,
                                                        const int32_t* __restrict__ coff, int32_t* __restrict__ cursor) {
   if (sel->mode == 2) return;
   const int32_t* rs = sel->rs;
@@ -298,8 +304,9 @@ __global__ __launch_bounds__(256) void csc_fill_kernel(const SparseSel* __restri
   const int lane = threadIdx.x & 63;
   for (int r = q + (int)(blockIdx.x * 4 + (threadIdx.x >> 6)); r < n; r += gridDim.x * 4) {
     const int b = rs[r], e = b + rc[r];
+    const int64_t cb = (int64_t)((r - q) / SF_GCH) * ld;
     for (int t = b + lane; t < e; t += 64) {
-      const int c = col[t];
+      const int64_t c = cb + col[t];
       const int pos = coff[c] + atomicAdd(cursor + c, 1);
       crow[pos] = r - q;
       cval[pos] = val[t];
@@ -307,13 +314,61 @@ __global__ __launch_bounds__(256) void csc_fill_kernel(const SparseSel* __restri
   }
 }
 
-constexpr int SF_GCH = 16384;  // gallery accumulators per pass (64 KiB of LDS)
+// Exclusive prefix sum over many counts (the chunked column layout): block
+// sums, a scan of the block sums, then each block's local scan plus its base.
+constexpr int SCAN_BLOCK = 1024;  // counts per block (4 per thread)
+
+__global__ __launch_bounds__(256) void scan_sums_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                        int32_t* __restrict__ part, const SparseSel* __restrict__ sel) {
+  if (sel->mode == 2) return;
+  __shared__ int red[4];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + tid * 4;
+  int v = 0;
+  for (int e = 0; e < 4; e++) v += (base + e < n) ? in[base + e] : 0;
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, kWave);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void scan_apply_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                         const int32_t* __restrict__ part_off,
+                                                         int32_t* __restrict__ out, const SparseSel* __restrict__ sel) {
+  if (sel->mode == 2) return;
+  __shared__ int wsum[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + tid * 4;
+  int v[4], mine = 0;
+  for (int e = 0; e < 4; e++) {
+    v[e] = (base + e < n) ? in[base + e] : 0;
+    mine += v[e];
+  }
+  int incl = mine;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int run = part_off[blockIdx.x] + incl - mine;
+  for (int x = 0; x < w; x++) run += wsum[x];
+  for (int e = 0; e < 4; e++) {
+    if (base + e < n) out[base + e] = run;
+    run += v[e];
+  }
+  if (blockIdx.x == gridDim.x - 1 && tid == 255) out[n] = part_off[gridDim.x];
+}
+
 constexpr int SF_QCH = 512;    // query non-zeros staged per pass
 constexpr int SF_ILP = 4;      // columns whose first 64 entries are loaded together
 
-// One workgroup per query: D[q][g] = 1 - sq * sg * sum_c u_q[c] u_g[c].
+// D[q][g] = 1 - sq * sg * sum_c u_q[c] u_g[c]. One workgroup per query, the
+// queries in cluster order with consecutive ones on one XCD (they read the
+// same gallery columns).
 __global__ __launch_bounds__(256) void sparse_final_kernel(const SparseSel* __restrict__ sel,
-                                                           const int32_t* __restrict__ coff,
+                                                           const int32_t* __restrict__ coff, int64_t ld,
+                                                           const int32_t* __restrict__ qorder,
                                                            const float* __restrict__ sq, const float* __restrict__ sg,
                                                            int g, float* __restrict__ dist, int64_t ldd) {
   if (sel->mode == 2) return;
@@ -324,7 +379,7 @@ __global__ __launch_bounds__(256) void sparse_final_kernel(const SparseSel* __re
   const float* val = sel->val;
   const int32_t* crow = sel->crow;
   const float* cval = sel->cval;
-  const int qi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int qi = qorder[xcd_linear(blockIdx.x, gridDim.x)], tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int b = sel->rs[qi], nq = sel->rc[qi];
   const float sqq = sq[qi];
   float* drow = dist + (int64_t)qi * ldd;
@@ -334,14 +389,15 @@ __global__ __launch_bounds__(256) void sparse_final_kernel(const SparseSel* __re
     const int quarter = (gw + 3) >> 2;
     const int lo = min(gw, w * quarter), len = min(gw, lo + quarter) - lo;
     for (int k = lane; k < len; k += 64) acc[lo + k] = 0.f;
+    const int32_t* cof = coff + (int64_t)(g0 / SF_GCH) * ld;  // this chunk's buckets
     for (int t0 = 0; t0 < nq; t0 += SF_QCH) {
       const int tn = min(SF_QCH, nq - t0);
-      if (g0 == 0 || nq > SF_QCH) {  // stage the query's columns (once if they fit)
+      {  // stage the query's columns: bucket ranges of this chunk
         __syncthreads();
         for (int t = tid; t < tn; t += 256) {
           const int c = col[b + t0 + t];
-          cb[t] = coff[c];
-          ce[t] = coff[c + 1];
+          cb[t] = cof[c];
+          ce[t] = cof[c + 1];
           qv[t] = val[b + t0 + t];
         }
         __syncthreads();
@@ -388,7 +444,7 @@ __global__ __launch_bounds__(256) void gemm_dist_gated_kernel(GemmArgs g, int ti
 
 hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const float* sigma, float* dist, void* pool,
                                int64_t pool_bytes, int32_t* ints, const SlGate* lay_gate, const SlRows* lay,
-                               hipStream_t s) {
+                               const int32_t* knn, int k1, hipStream_t s) {
   const int g = n - q;
   if (!H || !sigma || !dist || !pool || !ints || n < 2 || q < 1 || g < 1 || ld < n || (ld & 31) || pool_bytes < 16)
     return hipErrorInvalidValue;
@@ -397,16 +453,28 @@ hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const f
   if ((const char*)pool < (const char*)(H + (int64_t)n * ld) && (const char*)H < (const char*)pool + pool_bytes)
     return hipErrorInvalidValue;
   if (lay && pool_bytes < (int64_t)n * ld * 4) return hipErrorInvalidValue;  // column layout of up to n*ld/2 entries
-  int32_t* ccnt = ints;          // ld   (cleared here with cursor: 16-byte aligned, ld % 32 == 0)
-  int32_t* cursor = ccnt + ld;   // ld
-  int32_t* coff = cursor + ld;   // ld + 1
-  int32_t* cnt = coff + ld + 1;  // n
-  int32_t* off = cnt + n;        // n + 1
-  int32_t* flag = off + n + 1;   // 2
-  SparseSel* sel = (SparseSel*)(flag + 2);  // 8-byte aligned: 3 ld + 2 n + 4 ints precede it
+  const int64_t nchm = sparse_chunks(n);  // layout size (chunks of any gallery of this n)
+  const int64_t nb = (int64_t)((g + SF_GCH - 1) / SF_GCH) * ld;  // buckets in use
+  int32_t* ccnt = ints;               // nchm * ld (cleared here with cursor: 16-byte aligned, ld % 32 == 0)
+  int32_t* cursor = ccnt + nchm * ld; // nchm * ld
+  int32_t* coff = cursor + nchm * ld; // nchm * ld + 1
+  int32_t* cnt = coff + nchm * ld + 1;  // n
+  int32_t* off = cnt + n;             // n + 1
+  int32_t* flag = off + n + 1;        // 2
+  SparseSel* sel = (SparseSel*)(flag + 2);  // 8-byte aligned: 3 nchm ld + 2 n + 4 ints precede it
+  int32_t* part = (int32_t*)sel + 16;       // scan block sums
+  int32_t* oscr = ints + (3 * nchm * ld + 2 * n + 4 + 16 + sparse_scan_parts(n, ld) + 3) / 4 * 4;
+  int32_t* qorder = oscr + cluster_order_ints(n, n);  // queries in cluster order
   static_assert(sizeof(SparseSel) <= 16 * 4, "selection record");
   const int64_t cap = pool_bytes / 16;  // compacted entries (CSR and CSC, 16 bytes each)
-  hipError_t e = launch_fill_zero((float*)ccnt, 2 * ld, s);  // ccnt and cursor
+  const int64_t sblocks = (nb + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  if (sblocks + 1 > sparse_scan_parts(n, ld)) return hipErrorInvalidValue;
+  if (!knn || k1 < 1) return hipErrorInvalidValue;
+  hipError_t e = launch_cluster_order(knn, q, k1, n, oscr, qorder, s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_zero((float*)ccnt, nb, s);  // the buckets in use
+  if (e != hipSuccess) return e;
+  e = launch_fill_zero((float*)cursor, nb, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(nnz_count_kernel, dim3(n), dim3(256), 0, s, H, ld, cnt, lay_gate);
   hipLaunchKernelGGL(scan_gate_kernel, dim3(1), dim3(256), 0, s, cnt, n, off, cap, flag, lay_gate,
@@ -417,11 +485,14 @@ hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const f
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, lay_gate, lay ? *lay : none, flag, off, cnt, pool,
                      pool_bytes, sel);
   const unsigned rb = (unsigned)min((g + 3) / 4, 4096);
-  hipLaunchKernelGGL(csc_count_kernel, dim3(rb), dim3(256), 0, s, sel, q, n, ccnt);
-  hipLaunchKernelGGL(scan_gate_kernel, dim3(1), dim3(256), 0, s, ccnt, (int)ld, coff, INT64_MAX, (int32_t*)nullptr,
-                     (const SlGate*)nullptr, sel);
-  hipLaunchKernelGGL(csc_fill_kernel, dim3(rb), dim3(256), 0, s, sel, q, n, coff, cursor);
-  hipLaunchKernelGGL(sparse_final_kernel, dim3(q), dim3(256), 0, s, sel, coff, sigma, sigma + q, g, dist, (int64_t)g);
+  hipLaunchKernelGGL(csc_count_kernel, dim3(rb), dim3(256), 0, s, sel, q, n, ld, ccnt);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)sblocks), dim3(256), 0, s, ccnt, nb, part, sel);
+  hipLaunchKernelGGL(scan_gate_kernel, dim3(1), dim3(256), 0, s, part, (int)sblocks, part, INT64_MAX,
+                     (int32_t*)nullptr, (const SlGate*)nullptr, sel);  // in place: block bases and the total
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)sblocks), dim3(256), 0, s, ccnt, nb, part, coff, sel);
+  hipLaunchKernelGGL(csc_fill_kernel, dim3(rb), dim3(256), 0, s, sel, q, n, ld, coff, cursor);
+  hipLaunchKernelGGL(sparse_final_kernel, dim3(q), dim3(256), 0, s, sel, coff, ld, qorder, sigma, sigma + q, g, dist,
+                     (int64_t)g);
   const int tm = (q + BM - 1) / BM, tn = (g + BN - 1) / BN;
   GemmArgs ga{(const uint8_t*)H, (const uint8_t*)(H + (int64_t)q * ld), q, g, ld * 4, ld * 4, (int)(ld * 4 / BKB),
               sigma, sigma + q, dist, (int64_t)g};

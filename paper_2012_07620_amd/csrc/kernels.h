@@ -72,8 +72,15 @@ hipError_t launch_gemm_dist_bf16x3(const uint16_t* a_hi, const uint16_t* a_lo, i
 hipError_t launch_topk(const float* S, int64_t ldS, int N, int rows, int K, int32_t* idx, float* val,
                        int ldo, hipStream_t s);
 
+// Cluster order of rows [0, rows) of `lists` (row width w, entries < n):
+// the rows sorted by the key min(i, entries of row i), rows of one key in
+// arbitrary order. scratch: cluster_order_ints(rows, n) int32, 16-byte
+// aligned. Writes order[0, rows).
+inline int64_t cluster_order_ints(int64_t rows, int64_t n) { return (3 * n + rows + 1 + 3) / 4 * 4; }
+hipError_t launch_cluster_order(const int32_t* lists, int rows, int w, int n, int32_t* scratch, int32_t* order,
+                                hipStream_t s);
 // a3b: FP32 compensated re-score of Kc candidates per row, then the k1 cut.
-// scratch (5 n + 1 int32, 16-byte aligned) or nullptr: rows are re-scored in
+// scratch (cluster_order_ints(n, n) + n int32, 16-byte aligned) or nullptr: rows are re-scored in
 // an order that keeps rows with shared candidates on one XCD (the results do
 // not depend on the order).
 hipError_t launch_rescore(const float* xp, int64_t ldp, int d, const float* rn, int n, const int32_t* cand,
@@ -145,10 +152,17 @@ hipError_t launch_rank(const float* D, int q, int g, int r, int32_t* out, hipStr
 // With `lay` (the gate and rows of the last sparse layer, H then being that
 // layer's buffer): when the gate is sparse the CSR rows are used as they are
 // and only the column layout goes into `pool`.
-inline int64_t sparse_final_ints(int64_t n, int64_t ld) { return 3 * ld + 2 * n + 4 + 16; }
+constexpr int kSparseChunk = 16384;  // gallery accumulators per pass of the sparse product
+inline int64_t sparse_chunks(int64_t n) { return (n + kSparseChunk - 1) / kSparseChunk; }
+inline int64_t sparse_scan_parts(int64_t n, int64_t ld) { return (sparse_chunks(n) * ld + 1023) / 1024 + 1; }
+inline int64_t sparse_final_ints(int64_t n, int64_t ld) {
+  const int64_t head = (3 * sparse_chunks(n) * ld + 2 * n + 4 + 16 + sparse_scan_parts(n, ld) + 3) / 4 * 4;
+  return head + cluster_order_ints(n, n) + n;  // + the queries' cluster order
+}
+// knn (n x k1, the kNN lists) orders the queries by cluster.
 hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const float* sigma, float* dist, void* pool,
                                int64_t pool_bytes, int32_t* ints, const SlGate* lay_gate, const SlRows* lay,
-                               hipStream_t s);
+                               const int32_t* knn, int k1, hipStream_t s);
 // Split rows of an FP32 matrix into bf16 high/low parts (for L = 0 or raw).
 hipError_t launch_split_bf16(const float* h, int n, int64_t ld, uint16_t* hi, uint16_t* lo, hipStream_t s);
 

@@ -226,10 +226,10 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
     if (P.sparse_layers) {
       const SlOut last = sl_out(P, ws, (float*)cur, P.layers);
       RR_TRY(launch_sparse_final(cur, P.n, P.q, P.ldH, csig, dist, pool, (int64_t)P.n * P.ldH * 4,
-                                 at<int32_t>(ws, P.o_sp), last.gate, &last.rows, s));
+                                 at<int32_t>(ws, P.o_sp), last.gate, &last.rows, ki, P.k1, s));
     } else {
       RR_TRY(launch_sparse_final(cur, P.n, P.q, P.ldH, csig, dist, pool, (int64_t)P.n * P.ldH * 4,
-                                 at<int32_t>(ws, P.o_sp), nullptr, nullptr, s));
+                                 at<int32_t>(ws, P.o_sp), nullptr, nullptr, ki, P.k1, s));
     }
   } else {
     if (P.layers == 0) RR_TRY(launch_split_bf16(cur, P.n, P.ldH, hi, lo, s));
