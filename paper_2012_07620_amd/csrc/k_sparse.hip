@@ -7,7 +7,8 @@
 // dense product multiplies mostly zeros. Here (Gustavson's row-by-row sparse
 // product with a dense accumulator):
 //   1. every row of H is compacted into CSR (columns ascending);
-//   2. the gallery rows are also laid out by column (CSC);
+//   2. the gallery rows are also laid out by column (CSC), in buckets of
+//      (gallery chunk, quarter of the chunk, column);
 //   3. one workgroup per query keeps the gallery accumulators of a chunk of
 //      the gallery in LDS and, for each non-zero column c of the query in
 //      ascending c, adds h_q[c] * h_g[c] for every gallery row g that is
@@ -15,8 +16,9 @@
 //      only on the data, so results are deterministic);
 //   4. D[q][g] = 1 - sq * sg * acc, the dense epilogue's expression.
 // The four waves of a workgroup own disjoint quarters of the accumulator
-// chunk, so the column loop needs no block barrier; within a wave LDS
-// accesses complete in issue order.
+// chunk and read only their quarter's buckets, so the column loop needs no
+// block barrier; within a wave LDS accesses complete in issue order. Queries
+// are walked in cluster order (queries of one cluster read the same columns).
 //
 // When the layers were kept as CSR rows (sparse layers) step 1 is skipped.
 // Otherwise the compacted rows live in a spare N x N feature buffer (16 bytes
@@ -271,12 +273,20 @@ __global__ void select_kernel(const SlGate* lay, SlRows lrows, const int32_t* fl
 }
 
 // Column layout of the gallery rows q..n-1, split by gallery chunk (the
-// accumulator width of one pass of the product): entry (g, c) goes to bucket
-// (g / SF_GCH) * ld + c, so a pass over one chunk reads only its own entries.
-// One wave per row: bucket counts, then placement (the order inside a bucket
-// is arbitrary; every entry of a bucket goes to a different accumulator, so
-// it does not affect the sums).
+// accumulator width of one pass of the product) and by quarter of the chunk
+// (the slots one wave owns): entry (g, c) goes to bucket
+// (g / SF_GCH * 4 + quarter) * ld + c, so each wave of a pass reads only the
+// entries it adds. One wave per row: bucket counts, then placement (the order
+// inside a bucket is arbitrary; every entry of a bucket goes to a different
+// accumulator, so it does not affect the sums).
 constexpr int SF_GCH = kSparseChunk;  // gallery accumulators per pass (64 KiB of LDS)
+
+__device__ __forceinline__ int64_t csc_bucket(int gp, int g) {
+  const int ch = gp / SF_GCH, in = gp - ch * SF_GCH;
+  const int gw = min(SF_GCH, g - ch * SF_GCH);
+  const int quarter = (gw + 3) >> 2;
+  return (int64_t)ch * 4 + in / quarter;
+}
 
 __global__ __launch_bounds__(256) void csc_count_kernel(const SparseSel* __restrict__ sel, int q, int n, int64_t ld,
                                                         int32_t* __restrict__ ccnt) {
@@ -287,7 +297,7 @@ __global__ __launch_bounds__(256) void csc_count_kernel(const SparseSel* __restr
   const int lane = threadIdx.x & 63;
   for (int r = q + (int)(blockIdx.x * 4 + (threadIdx.x >> 6)); r < n; r += gridDim.x * 4) {
     const int b = rs[r], e = b + rc[r];
-    int32_t* cb = ccnt + (int64_t)((r - q) / SF_GCH) * ld;
+    int32_t* cb = ccnt + csc_bucket(r - q, n - q) * ld;
     for (int t = b + lane; t < e; t += 64) atomicAdd(cb + col[t], 1);
   }
 }
@@ -304,7 +314,7 @@ __global__ __launch_bounds__(256) void csc_fill_kernel(const SparseSel* __restri
   const int lane = threadIdx.x & 63;
   for (int r = q + (int)(blockIdx.x * 4 + (threadIdx.x >> 6)); r < n; r += gridDim.x * 4) {
     const int b = rs[r], e = b + rc[r];
-    const int64_t cb = (int64_t)((r - q) / SF_GCH) * ld;
+    const int64_t cb = csc_bucket(r - q, n - q) * ld;
     for (int t = b + lane; t < e; t += 64) {
       const int64_t c = cb + col[t];
       const int pos = coff[c] + atomicAdd(cursor + c, 1);
@@ -360,12 +370,13 @@ __global__ __launch_bounds__(256) void scan_apply_kernel(const int32_t* __restri
   if (blockIdx.x == gridDim.x - 1 && tid == 255) out[n] = part_off[gridDim.x];
 }
 
-constexpr int SF_QCH = 512;    // query non-zeros staged per pass
-constexpr int SF_ILP = 4;      // columns whose first 64 entries are loaded together
+constexpr int SF_QCH = 256;  // query non-zeros staged per pass
+constexpr int SF_ILP = 4;    // columns whose first 64 entries are loaded together
 
 // D[q][g] = 1 - sq * sg * sum_c u_q[c] u_g[c]. One workgroup per query, the
 // queries in cluster order with consecutive ones on one XCD (they read the
-// same gallery columns).
+// same gallery columns). Wave w owns quarter w of each gallery chunk and reads
+// only that quarter's buckets.
 __global__ __launch_bounds__(256) void sparse_final_kernel(const SparseSel* __restrict__ sel,
                                                            const int32_t* __restrict__ coff, int64_t ld,
                                                            const int32_t* __restrict__ qorder,
@@ -373,7 +384,7 @@ __global__ __launch_bounds__(256) void sparse_final_kernel(const SparseSel* __re
                                                            int g, float* __restrict__ dist, int64_t ldd) {
   if (sel->mode == 2) return;
   __shared__ float acc[SF_GCH];
-  __shared__ int cb[SF_QCH], ce[SF_QCH];
+  __shared__ int cb[4][SF_QCH], ce[4][SF_QCH];
   __shared__ float qv[SF_QCH];
   const int32_t* col = sel->col;
   const float* val = sel->val;
@@ -384,37 +395,38 @@ __global__ __launch_bounds__(256) void sparse_final_kernel(const SparseSel* __re
   const float sqq = sq[qi];
   float* drow = dist + (int64_t)qi * ldd;
   for (int g0 = 0; g0 < g; g0 += SF_GCH) {
-    if (g0) __syncthreads();  // the waves' quarters move with the chunk width
+    if (g0) __syncthreads();  // the quarters move with the chunk width: previous write-outs first
     const int gw = min(SF_GCH, g - g0);
     const int quarter = (gw + 3) >> 2;
     const int lo = min(gw, w * quarter), len = min(gw, lo + quarter) - lo;
-    for (int k = lane; k < len; k += 64) acc[lo + k] = 0.f;
-    const int32_t* cof = coff + (int64_t)(g0 / SF_GCH) * ld;  // this chunk's buckets
+    for (int k = lane; k < len; k += 64) acc[lo + k] = 0.f;  // own quarter
+    const int32_t* cof = coff + (int64_t)(g0 / SF_GCH) * 4 * ld;  // this chunk's buckets
+    const int base = g0 + lo;  // gallery position of acc[lo]
     for (int t0 = 0; t0 < nq; t0 += SF_QCH) {
       const int tn = min(SF_QCH, nq - t0);
-      {  // stage the query's columns: bucket ranges of this chunk
-        __syncthreads();
-        for (int t = tid; t < tn; t += 256) {
-          const int c = col[b + t0 + t];
-          cb[t] = cof[c];
-          ce[t] = cof[c + 1];
-          qv[t] = val[b + t0 + t];
+      __syncthreads();  // every wave is done with the previous staging
+      for (int t = tid; t < tn; t += 256) {
+        const int c = col[b + t0 + t];
+        qv[t] = val[b + t0 + t];
+#pragma unroll
+        for (int x = 0; x < 4; x++) {
+          cb[x][t] = cof[x * ld + c];
+          ce[x][t] = cof[x * ld + c + 1];
         }
-        __syncthreads();
       }
-      const int base = g0 + lo;  // gallery position of acc[lo]
+      __syncthreads();
       for (int t = 0; t < tn; t += SF_ILP) {
         int r[SF_ILP];
-        float x[SF_ILP];
+        float xv[SF_ILP];
 #pragma unroll
         for (int u = 0; u < SF_ILP; u++) {
           r[u] = -1;
-          x[u] = 0.f;
+          xv[u] = 0.f;
           if (t + u < tn) {
-            const int s = cb[t + u] + lane;
-            if (s < ce[t + u]) {
+            const int s = cb[w][t + u] + lane;
+            if (s < ce[w][t + u]) {
               r[u] = crow[s] - base;
-              x[u] = cval[s];
+              xv[u] = cval[s];
             }
           }
         }
@@ -422,8 +434,8 @@ __global__ __launch_bounds__(256) void sparse_final_kernel(const SparseSel* __re
         for (int u = 0; u < SF_ILP; u++) {
           if (t + u >= tn) break;
           const float v = qv[t + u];
-          if ((unsigned)r[u] < (unsigned)len) acc[lo + r[u]] = __builtin_fmaf(v, x[u], acc[lo + r[u]]);
-          for (int s = cb[t + u] + 64 + lane; s < ce[t + u]; s += 64) {  // columns longer than 64
+          if ((unsigned)r[u] < (unsigned)len) acc[lo + r[u]] = __builtin_fmaf(v, xv[u], acc[lo + r[u]]);
+          for (int s = cb[w][t + u] + 64 + lane; s < ce[w][t + u]; s += 64) {  // buckets longer than 64
             const int rr = crow[s] - base;
             if ((unsigned)rr < (unsigned)len) acc[lo + rr] = __builtin_fmaf(v, cval[s], acc[lo + rr]);
           }
@@ -453,17 +465,17 @@ hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const f
   if ((const char*)pool < (const char*)(H + (int64_t)n * ld) && (const char*)H < (const char*)pool + pool_bytes)
     return hipErrorInvalidValue;
   if (lay && pool_bytes < (int64_t)n * ld * 4) return hipErrorInvalidValue;  // column layout of up to n*ld/2 entries
-  const int64_t nchm = sparse_chunks(n);  // layout size (chunks of any gallery of this n)
-  const int64_t nb = (int64_t)((g + SF_GCH - 1) / SF_GCH) * ld;  // buckets in use
-  int32_t* ccnt = ints;               // nchm * ld (cleared here with cursor: 16-byte aligned, ld % 32 == 0)
-  int32_t* cursor = ccnt + nchm * ld; // nchm * ld
-  int32_t* coff = cursor + nchm * ld; // nchm * ld + 1
-  int32_t* cnt = coff + nchm * ld + 1;  // n
+  const int64_t nbm = sparse_buckets(n, ld);  // layout size (buckets of any gallery of this n)
+  const int64_t nb = (int64_t)((g + SF_GCH - 1) / SF_GCH) * 4 * ld;  // buckets in use
+  int32_t* ccnt = ints;            // nbm (cleared here with cursor: 16-byte aligned, ld % 32 == 0)
+  int32_t* cursor = ccnt + nbm;    // nbm
+  int32_t* coff = cursor + nbm;    // nbm + 1
+  int32_t* cnt = coff + nbm + 1;   // n
   int32_t* off = cnt + n;             // n + 1
   int32_t* flag = off + n + 1;        // 2
-  SparseSel* sel = (SparseSel*)(flag + 2);  // 8-byte aligned: 3 nchm ld + 2 n + 4 ints precede it
+  SparseSel* sel = (SparseSel*)(flag + 2);  // 8-byte aligned: 3 nbm + 2 n + 4 ints precede it
   int32_t* part = (int32_t*)sel + 16;       // scan block sums
-  int32_t* oscr = ints + (3 * nchm * ld + 2 * n + 4 + 16 + sparse_scan_parts(n, ld) + 3) / 4 * 4;
+  int32_t* oscr = ints + sparse_final_head(n, ld);
   int32_t* qorder = oscr + cluster_order_ints(n, n);  // queries in cluster order
   static_assert(sizeof(SparseSel) <= 16 * 4, "selection record");
   const int64_t cap = pool_bytes / 16;  // compacted entries (CSR and CSC, 16 bytes each)

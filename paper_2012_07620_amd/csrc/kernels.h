@@ -154,10 +154,14 @@ hipError_t launch_rank(const float* D, int q, int g, int r, int32_t* out, hipStr
 // and only the column layout goes into `pool`.
 constexpr int kSparseChunk = 16384;  // gallery accumulators per pass of the sparse product
 inline int64_t sparse_chunks(int64_t n) { return (n + kSparseChunk - 1) / kSparseChunk; }
-inline int64_t sparse_scan_parts(int64_t n, int64_t ld) { return (sparse_chunks(n) * ld + 1023) / 1024 + 1; }
+// column buckets: (gallery chunk, quarter of the chunk, column)
+inline int64_t sparse_buckets(int64_t n, int64_t ld) { return sparse_chunks(n) * 4 * ld; }
+inline int64_t sparse_scan_parts(int64_t n, int64_t ld) { return (sparse_buckets(n, ld) + 1023) / 1024 + 1; }
+inline int64_t sparse_final_head(int64_t n, int64_t ld) {
+  return (3 * sparse_buckets(n, ld) + 2 * n + 4 + 16 + sparse_scan_parts(n, ld) + 3) / 4 * 4;
+}
 inline int64_t sparse_final_ints(int64_t n, int64_t ld) {
-  const int64_t head = (3 * sparse_chunks(n) * ld + 2 * n + 4 + 16 + sparse_scan_parts(n, ld) + 3) / 4 * 4;
-  return head + cluster_order_ints(n, n) + n;  // + the queries' cluster order
+  return sparse_final_head(n, ld) + cluster_order_ints(n, n) + n;  // + the queries' cluster order
 }
 // knn (n x k1, the kNN lists) orders the queries by cluster.
 hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const float* sigma, float* dist, void* pool,

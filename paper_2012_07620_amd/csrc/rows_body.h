@@ -487,10 +487,19 @@ __device__ __forceinline__ void csr_pair(const int32_t* __restrict__ knn, int n,
 constexpr int FIRST_CHUNK = 8192;    // floats of the output row held in LDS
 constexpr int FIRST_WORDS = FIRST_CHUNK / 32;  // touched-column bitmap of a chunk
 constexpr int FIRST_ENTRIES = 2048;  // member entries of one row staged in LDS
+constexpr int HASH_SLOTS = 4096;     // hashed sums of one CSR row (load factor at most 1/2)
+constexpr int ROW_WORDS = 2048;      // touched-column bitmap of a whole row (rows up to 65536 columns)
+struct HashTab {
+  int key[HASH_SLOTS];  // column, or -1
+  float val[HASH_SLOTS];
+};
 struct FirstShared {
   PropShared p;
-  float row[FIRST_CHUNK];      // sums; valid only where the bitmap is set
-  uint32_t bits[FIRST_WORDS];  // columns of the chunk touched so far
+  union {
+    float row[FIRST_CHUNK];  // chunked path: sums; valid only where the bitmap is set
+    HashTab ht;              // hashed path
+  };
+  uint32_t bits[ROW_WORDS];  // touched columns (of the chunk, or of the whole row)
   int col[FIRST_ENTRIES];
   float val[FIRST_ENTRIES];
   int start[257];  // entries of member r are [start[r], start[r+1])
@@ -549,6 +558,102 @@ __device__ __forceinline__ void sparse_add(FirstShared& sh, int m, float c, floa
   sh.row[m] = __builtin_fmaf(c, v, (old & bit) ? sh.row[m] : 0.0f);
 }
 
+// CSR rows whose staged entries fit the hash table skip the column chunks:
+// sums live in an LDS hash table keyed by column (first touch starts from 0,
+// then one FMA per entry in member order, exactly as in the chunks) and a
+// bitmap of the whole row marks the touched columns, which gives the
+// ascending column order for the output and the dense store's per-thread
+// order for the squared norm (thread t owns float4 columns t, t + 256, ...).
+__device__ __forceinline__ uint32_t hash_col(int c) { return ((uint32_t)c * 2654435761u) >> 20; }
+
+__device__ __forceinline__ float hash_get(const FirstShared& sh, int c) {
+  uint32_t h = hash_col(c);
+  while (sh.ht.key[h] != c) h = (h + 1) & (HASH_SLOTS - 1);
+  return sh.ht.val[h];
+}
+
+// Returns the end of the written entries; *ss receives the squared norm.
+__device__ __forceinline__ int hashed_row(FirstShared& sh, int k2, int64_t ld, const SlRows& out, int pos,
+                                          float* ss) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int words = (int)(ld >> 5);
+  for (int k = tid; k < words; k += 256) sh.bits[k] = 0u;
+  for (int k = tid; k < HASH_SLOTS; k += 256) sh.ht.key[k] = -1;
+  __syncthreads();
+  for (int r = 0; r < k2; r++) {
+    const float c = sh.p.cf[r];
+    for (int s = sh.start[r] + tid; s < sh.start[r + 1]; s += 256) {  // distinct columns within a member
+      const int col = sh.col[s];
+      const float v = sh.val[s];
+      uint32_t h = hash_col(col);
+      while (true) {
+        const int old = atomicCAS(&sh.ht.key[h], -1, col);
+        if (old == -1) {
+          sh.ht.val[h] = __builtin_fmaf(c, v, 0.0f);
+          atomicOr(&sh.bits[col >> 5], 1u << (col & 31));
+          break;
+        }
+        if (old == col) {
+          sh.ht.val[h] = __builtin_fmaf(c, v, sh.ht.val[h]);
+          break;
+        }
+        h = (h + 1) & (HASH_SLOTS - 1);
+      }
+    }
+    __syncthreads();
+  }
+  float acc = 0.f;
+  for (int f = tid; f < (int)(ld >> 2); f += 256) {
+    const uint32_t nib = (sh.bits[f >> 3] >> ((f & 7) * 4)) & 0xFu;
+    if (nib)
+      for (int e = 0; e < 4; e++)
+        if (nib & (1u << e)) {
+          const float v = hash_get(sh, 4 * f + e);
+          acc = __builtin_fmaf(v, v, acc);
+        }
+  }
+  *ss = acc;
+  // thread t emits a contiguous run of bitmap words: counts, block scan, writes
+  const int per = (words + 255) / 256;
+  const int w0 = min(words, tid * per), w1 = min(words, w0 + per);
+  int mine = 0;
+  for (int x = w0; x < w1; x++) {
+    uint32_t wd = sh.bits[x];
+    while (wd) {
+      const int b = __builtin_ctz(wd);
+      wd &= wd - 1u;
+      mine += hash_get(sh, 32 * x + b) != 0.f;
+    }
+  }
+  int incl = mine;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) sh.wsum[w] = incl;
+  __syncthreads();
+  int at = pos + incl - mine, total = 0;
+  for (int x = 0; x < 4; x++) {
+    at += (x < w) ? sh.wsum[x] : 0;
+    total += sh.wsum[x];
+  }
+  for (int x = w0; x < w1; x++) {
+    uint32_t wd = sh.bits[x];
+    while (wd) {
+      const int b = __builtin_ctz(wd);
+      wd &= wd - 1u;
+      const float v = hash_get(sh, 32 * x + b);
+      if (v != 0.f) {
+        out.col[at] = 32 * x + b;
+        out.val[at] = v;
+        at++;
+      }
+    }
+  }
+  __syncthreads();  // wsum, bits and the table are reused by the caller
+  return pos + total;
+}
+
 // u_i = sum_r cf_r h_{j_r} over the k2 members (coefficients already in sh.p)
 // from sparse member rows, one LDS column chunk at a time, in member order r
 // with one FMA per entry: the same sums, rounding for rounding, as
@@ -601,6 +706,15 @@ __device__ __forceinline__ void sparse_row_core(const Src& src, int k2, int64_t 
   const bool csr = sl_begin(sl, i, &pos);
   const int pos0 = pos;
   float ss = 0.f;
+  if (csr && staged && (ld >> 5) <= ROW_WORDS) {
+    const int end = hashed_row(sh, k2, ld, sl->rows, pos, &ss);
+    if (tid == 0) {
+      sl->rows.so[i] = pos0;
+      sl->rows.cnt[i] = end - pos0;
+    }
+    finish_norm(ss, sout, i, sh.p);
+    return;
+  }
   for (int64_t c0 = 0; c0 < ld; c0 += FIRST_CHUNK) {
     const int width = (int)min((int64_t)FIRST_CHUNK, ld - c0);
     for (int k = tid; k < FIRST_WORDS; k += 256) sh.bits[k] = 0u;

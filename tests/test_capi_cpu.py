@@ -113,3 +113,14 @@ def test_sparse_final_workspace_holds_both_feature_buffers_and_counters():
     sparse = binding.workspace_bytes(binding.make_params(n, 100, 64, 20, 6, 0, final_prec="sparse"))
     ldn = (n + 63) // 64 * 64
     assert sparse - dense >= n * ldn * 4 + (2 * n + 3 * ldn + 4) * 4
+
+
+def test_context_flags_checked_before_any_device_call():
+    # the flag check needs no GPU: unknown bits are rejected, known ones pass it
+    lib = binding.library()
+    h = ctypes.c_void_p()
+    assert lib.rerank_create(ctypes.byref(h), 0, 0, 4) == binding.E_INVALID
+    assert lib.rerank_create(ctypes.byref(h), 0, 0, 1 << 31) == binding.E_INVALID
+    assert binding.CTX_STAGE_TIMING == 1 and binding.CTX_DENSE_LAYERS == 2
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "rerank.h")).read()
+    assert "#define RERANK_CTX_STAGE_TIMING 1u" in hdr and "#define RERANK_CTX_DENSE_LAYERS 2u" in hdr
