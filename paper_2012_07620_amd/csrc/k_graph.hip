@@ -33,15 +33,16 @@ __global__ void order_place_kernel(const int32_t* __restrict__ key, int rows, co
 hipError_t launch_cluster_order(const int32_t* lists, int rows, int w, int n, int32_t* scratch, int32_t* order,
                                 hipStream_t s) {
   if (rows < 1 || rows > n || w < 1 || ((uintptr_t)scratch & 15)) return hipErrorInvalidValue;
-  int32_t* cnt = scratch;  // cnt[n], cursor[n], key[rows], off[n + 1]
+  int32_t* cnt = scratch;  // cnt[n], cursor[n], key[rows], off[n + 1], scan parts
   int32_t* cursor = cnt + n;
   int32_t* key = cursor + n;
   int32_t* off = key + rows;
+  int32_t* part = off + n + 1;
   hipError_t e = launch_fill_zero((float*)cnt, 2 * (int64_t)n, s);
   if (e != hipSuccess) return e;
   const unsigned g = (unsigned)((rows + 255) / 256);
   hipLaunchKernelGGL(order_key_kernel, dim3(g), dim3(256), 0, s, lists, rows, w, key, cnt);
-  e = launch_scan(cnt, n, off, s);
+  e = launch_scan(cnt, n, off, part, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(order_place_kernel, dim3(g), dim3(256), 0, s, key, rows, off, cursor, order);
   return hipGetLastError();
@@ -165,13 +166,91 @@ hipError_t launch_mutual(const int32_t* knn_idx, int n, int k1, uint8_t* mflag, 
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void scan_kernel(const int32_t* __restrict__ innm, int n, int32_t* __restrict__ off) {
-  __shared__ int32_t sh[256];
-  scan_offsets(innm, n, off, sh);
+// ---------------------------------------------------------------- prefix sums
+constexpr int SCAN_BLOCK = 1024;  // counts per block (4 per thread)
+
+__device__ __forceinline__ bool scan_skipped(const int32_t* skip, int32_t skip_val) {
+  return skip && *skip == skip_val;
 }
 
-hipError_t launch_scan(const int32_t* innm, int n, int32_t* off, hipStream_t s) {
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(256), 0, s, innm, n, off);
+__global__ __launch_bounds__(256) void scan_sums_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                        int32_t* __restrict__ part, const int32_t* skip,
+                                                        int32_t skip_val) {
+  if (scan_skipped(skip, skip_val)) return;
+  __shared__ int red[4];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + tid * 4;
+  int v = 0;
+  for (int e = 0; e < 4; e++) v += (base + e < n) ? in[base + e] : 0;
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, kWave);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// One workgroup: part[0, nb) -> exclusive prefix in place, part[nb] = total.
+__global__ __launch_bounds__(256) void scan_parts_kernel(int32_t* part, int nb, const int32_t* skip,
+                                                         int32_t skip_val) {
+  if (scan_skipped(skip, skip_val)) return;
+  __shared__ int32_t sh[256];
+  const int tid = threadIdx.x;
+  const int per = (nb + 255) / 256;
+  const int b = min(nb, tid * per), e = min(nb, b + per);
+  int sum = 0;
+  for (int k = b; k < e; k++) sum += part[k];
+  sh[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int v = tid >= o ? sh[tid - o] : 0;
+    __syncthreads();
+    sh[tid] += v;
+    __syncthreads();
+  }
+  int run = sh[tid] - sum;
+  for (int k = b; k < e; k++) {  // read before write (in place)
+    const int v = part[k];
+    part[k] = run;
+    run += v;
+  }
+  if (tid == 255) part[nb] = sh[255];
+}
+
+__global__ __launch_bounds__(256) void scan_apply_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                         const int32_t* __restrict__ part, int32_t* __restrict__ out,
+                                                         const int32_t* skip, int32_t skip_val) {
+  if (scan_skipped(skip, skip_val)) return;
+  __shared__ int wsum[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + tid * 4;
+  int v[4], mine = 0;
+  for (int e = 0; e < 4; e++) {
+    v[e] = (base + e < n) ? in[base + e] : 0;
+    mine += v[e];
+  }
+  int incl = mine;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int run = part[blockIdx.x] + incl - mine;
+  for (int x = 0; x < w; x++) run += wsum[x];
+  for (int e = 0; e < 4; e++) {
+    if (base + e < n) out[base + e] = run;
+    run += v[e];
+  }
+  if (blockIdx.x == gridDim.x - 1 && tid == 255) out[n] = part[gridDim.x];
+}
+
+hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* part, hipStream_t s,
+                       const int32_t* skip, int32_t skip_val) {
+  if (n < 1 || !in || !out || !part) return hipErrorInvalidValue;
+  const int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(256), 0, s, in, n, part, skip, skip_val);
+  hipLaunchKernelGGL(scan_parts_kernel, dim3(1), dim3(256), 0, s, part, (int)nb, skip, skip_val);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(256), 0, s, in, n, part, out, skip, skip_val);
   return hipGetLastError();
 }
 

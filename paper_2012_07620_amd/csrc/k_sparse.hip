@@ -37,68 +37,49 @@
 namespace rr {
 
 // ================================================================ sparse layers
-// Slot size of every row of layer l.
+// Slot size of every row of layer l, and their 64-bit total into gates[l]
+// (one atomic per wave).
 __global__ __launch_bounds__(256) void sl_size_kernel(const int32_t* __restrict__ knn, int n, int k1, int k2,
                                                       int first, int sym, const int32_t* __restrict__ off,
-                                                      const int32_t* __restrict__ cnt_prev, const SlGate* prev,
+                                                      const int32_t* __restrict__ cnt_prev, SlGate* gates,
                                                       int32_t* __restrict__ size) {
-  if (prev->dense) return;
+  if (gates[0].dense) return;  // gates[0] = layer l - 1
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
   int64_t b = 0;
-  for (int r = 0; r < k2; r++) {
-    const int j = knn[(int64_t)i * k1 + r];
-    b += first ? (int64_t)(k1 + (sym ? off[j + 1] - off[j] : 0)) : (int64_t)cnt_prev[j];
+  if (i < n) {
+    for (int r = 0; r < k2; r++) {
+      const int j = knn[(int64_t)i * k1 + r];
+      b += first ? (int64_t)(k1 + (sym ? off[j + 1] - off[j] : 0)) : (int64_t)cnt_prev[j];
+    }
+    b = min(b, (int64_t)n);
+    size[i] = (int32_t)b;
   }
-  size[i] = (int32_t)min(b, (int64_t)n);
+  uint64_t t = (uint64_t)b;
+  for (int m = 32; m > 0; m >>= 1) t += shfl_xor_u64(t, m);
+  if ((threadIdx.x & 63) == 0 && t) atomicAdd(&gates[1].total, (unsigned long long)t);
 }
 
-// Slot starts (exclusive prefix sum of the sizes, one workgroup) and gate l.
-__global__ __launch_bounds__(256) void sl_scan_kernel(const int32_t* __restrict__ size, int n,
-                                                      int32_t* __restrict__ so, int64_t cap, SlGate* gates, int l) {
-  const int tid = threadIdx.x;
-  if (gates[l - 1].dense) {
-    if (tid == 0) gates[l].dense = 1;
-    return;
-  }
-  __shared__ int64_t sh[256];
-  const int per = (n + 255) / 256;
-  const int b = min(n, tid * per), e = min(n, b + per);
-  int64_t sum = 0;
-  for (int k = b; k < e; k++) sum += size[k];
-  sh[tid] = sum;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const int64_t v = tid >= o ? sh[tid - o] : 0;
-    __syncthreads();
-    sh[tid] += v;
-    __syncthreads();
-  }
-  const int64_t total = sh[255];
-  const bool fits = total <= cap && total <= 0x7FFFFFFF;
-  if (fits) {
-    int64_t run = sh[tid] - sum;
-    for (int k = b; k < e; k++) {
-      so[k] = (int32_t)run;
-      run += size[k];
-    }
-  }
-  if (tid == 0) {
-    gates[l].total = (unsigned long long)total;
-    gates[l].dense = fits ? 0 : 1;
-  }
+// Gate l from the slot total: dense when the slots do not fit (or layer
+// l - 1 was dense).
+__global__ void sl_gate_kernel(int64_t cap, SlGate* gates, int l) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const unsigned long long total = gates[l].total;
+  const bool dense = gates[l - 1].dense || total > (unsigned long long)cap || total > 0x7FFFFFFFull;
+  gates[l].dense = dense ? 1 : 0;  // sparse only when the int32 slot starts are exact
 }
 
 hipError_t launch_sl_slots(const int32_t* knn_idx, int n, int k1, int k2, bool first, bool sym, const int32_t* off,
-                           const int32_t* cnt_prev, const SlOut& out, hipStream_t s) {
+                           const int32_t* cnt_prev, const SlOut& out, int32_t* part, hipStream_t s) {
   if (k2 < 1 || k2 > k1 || (first && sym && !off) || (!first && !cnt_prev) || !out.gate || !out.prev ||
-      out.gate != out.prev + 1 || !out.rows.so || !out.rows.cnt)
+      out.gate != out.prev + 1 || !out.rows.so || !out.rows.cnt || !part)
     return hipErrorInvalidValue;
+  // gates[l - 1] = out.prev, gates[l] = out.gate (gates start zeroed: total accumulates here)
   hipLaunchKernelGGL(sl_size_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, knn_idx, n, k1, k2,
-                     (int)first, (int)sym, off, cnt_prev, out.prev, out.rows.cnt);
-  // gates[l - 1] = out.prev, gates[l] = out.gate
-  hipLaunchKernelGGL(sl_scan_kernel, dim3(1), dim3(256), 0, s, out.rows.cnt, n, out.rows.so, out.cap,
-                     (SlGate*)out.prev, 1);
+                     (int)first, (int)sym, off, cnt_prev, (SlGate*)out.prev, out.rows.cnt);
+  hipLaunchKernelGGL(sl_gate_kernel, dim3(1), dim3(64), 0, s, out.cap, (SlGate*)out.prev, 1);
+  // slot starts (int32, exact whenever the gate is sparse); skipped after a dense layer
+  hipError_t e = launch_scan(out.rows.cnt, n, out.rows.so, part, s, &out.prev->dense, 1);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -324,52 +305,6 @@ __global__ __launch_bounds__(256) void csc_fill_kernel(const SparseSel* __restri
   }
 }
 
-// Exclusive prefix sum over many counts (the chunked column layout): block
-// sums, a scan of the block sums, then each block's local scan plus its base.
-constexpr int SCAN_BLOCK = 1024;  // counts per block (4 per thread)
-
-__global__ __launch_bounds__(256) void scan_sums_kernel(const int32_t* __restrict__ in, int64_t n,
-                                                        int32_t* __restrict__ part, const SparseSel* __restrict__ sel) {
-  if (sel->mode == 2) return;
-  __shared__ int red[4];
-  const int tid = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + tid * 4;
-  int v = 0;
-  for (int e = 0; e < 4; e++) v += (base + e < n) ? in[base + e] : 0;
-  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, kWave);
-  if ((tid & 63) == 0) red[tid >> 6] = v;
-  __syncthreads();
-  if (tid == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-__global__ __launch_bounds__(256) void scan_apply_kernel(const int32_t* __restrict__ in, int64_t n,
-                                                         const int32_t* __restrict__ part_off,
-                                                         int32_t* __restrict__ out, const SparseSel* __restrict__ sel) {
-  if (sel->mode == 2) return;
-  __shared__ int wsum[4];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + tid * 4;
-  int v[4], mine = 0;
-  for (int e = 0; e < 4; e++) {
-    v[e] = (base + e < n) ? in[base + e] : 0;
-    mine += v[e];
-  }
-  int incl = mine;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += t;
-  }
-  if (lane == 63) wsum[w] = incl;
-  __syncthreads();
-  int run = part_off[blockIdx.x] + incl - mine;
-  for (int x = 0; x < w; x++) run += wsum[x];
-  for (int e = 0; e < 4; e++) {
-    if (base + e < n) out[base + e] = run;
-    run += v[e];
-  }
-  if (blockIdx.x == gridDim.x - 1 && tid == 255) out[n] = part_off[gridDim.x];
-}
-
 constexpr int SF_QCH = 256;  // query non-zeros staged per pass
 constexpr int SF_ILP = 4;    // columns whose first 64 entries are loaded together
 
@@ -479,8 +414,7 @@ hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const f
   int32_t* qorder = oscr + cluster_order_ints(n, n);  // queries in cluster order
   static_assert(sizeof(SparseSel) <= 16 * 4, "selection record");
   const int64_t cap = pool_bytes / 16;  // compacted entries (CSR and CSC, 16 bytes each)
-  const int64_t sblocks = (nb + SCAN_BLOCK - 1) / SCAN_BLOCK;
-  if (sblocks + 1 > sparse_scan_parts(n, ld)) return hipErrorInvalidValue;
+  if (scan_parts(nb) > sparse_scan_parts(n, ld)) return hipErrorInvalidValue;
   if (!knn || k1 < 1) return hipErrorInvalidValue;
   hipError_t e = launch_cluster_order(knn, q, k1, n, oscr, qorder, s);
   if (e != hipSuccess) return e;
@@ -498,10 +432,8 @@ hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const f
                      pool_bytes, sel);
   const unsigned rb = (unsigned)min((g + 3) / 4, 4096);
   hipLaunchKernelGGL(csc_count_kernel, dim3(rb), dim3(256), 0, s, sel, q, n, ld, ccnt);
-  hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)sblocks), dim3(256), 0, s, ccnt, nb, part, sel);
-  hipLaunchKernelGGL(scan_gate_kernel, dim3(1), dim3(256), 0, s, part, (int)sblocks, part, INT64_MAX,
-                     (int32_t*)nullptr, (const SlGate*)nullptr, sel);  // in place: block bases and the total
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)sblocks), dim3(256), 0, s, ccnt, nb, part, coff, sel);
+  e = launch_scan(ccnt, nb, coff, part, s, &sel->mode, 2);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(csc_fill_kernel, dim3(rb), dim3(256), 0, s, sel, q, n, ld, coff, cursor);
   hipLaunchKernelGGL(sparse_final_kernel, dim3(q), dim3(256), 0, s, sel, coff, ld, qorder, sigma, sigma + q, g, dist,
                      (int64_t)g);

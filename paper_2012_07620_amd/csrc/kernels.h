@@ -38,6 +38,9 @@ struct SlOut {
   int n;               // columns of a row (bounds are capped at n)
 };
 
+// Block sums needed by launch_scan over n counts (1024 counts per block, plus the total).
+inline int64_t scan_parts(int64_t n) { return (n + 1023) / 1024 + 1; }
+
 // Row stride (elements) of the padded K-major copies the GEMMs read: every
 // row is a whole number of 128-byte stages.
 inline int64_t pad_k_elems(int64_t d, int bytes_per_elem) {
@@ -76,7 +79,7 @@ hipError_t launch_topk(const float* S, int64_t ldS, int N, int rows, int K, int3
 // the rows sorted by the key min(i, entries of row i), rows of one key in
 // arbitrary order. scratch: cluster_order_ints(rows, n) int32, 16-byte
 // aligned. Writes order[0, rows).
-inline int64_t cluster_order_ints(int64_t rows, int64_t n) { return (3 * n + rows + 1 + 3) / 4 * 4; }
+inline int64_t cluster_order_ints(int64_t rows, int64_t n) { return (3 * n + rows + 1 + scan_parts(n) + 3) / 4 * 4; }
 hipError_t launch_cluster_order(const int32_t* lists, int rows, int w, int n, int32_t* scratch, int32_t* order,
                                 hipStream_t s);
 // a3b: FP32 compensated re-score of Kc candidates per row, then the k1 cut.
@@ -112,7 +115,12 @@ hipError_t launch_propagate(const float* hin, const float* sin, int n, int64_t l
 // mutual flags of every (i, r) pair and non-mutual in-degree counts ...
 hipError_t launch_mutual(const int32_t* knn_idx, int n, int k1, uint8_t* mflag, int32_t* innm, hipStream_t s);
 // ... exclusive prefix sum of the counts (off has n + 1 entries) ...
-hipError_t launch_scan(const int32_t* innm, int n, int32_t* off, hipStream_t s);
+// Exclusive prefix sum of in[0, n) into out[0, n], out[n] = the total, in
+// three launches (block sums, a scan of the block sums, block scans). part
+// holds scan_parts(n) int32. With `skip`, nothing runs when *skip == skip_val
+// (read on the device). The total must fit in int32.
+hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* part, hipStream_t s,
+                       const int32_t* skip = nullptr, int32_t skip_val = 0);
 // ... CSR transpose of the non-mutual edges (cursor zeroed beforehand) ...
 hipError_t launch_csr(const int32_t* knn_idx, int n, int k1, const uint8_t* mflag, const int32_t* off,
                       int32_t* cursor, int32_t* inl, hipStream_t s);
@@ -129,8 +137,9 @@ hipError_t launch_first_layer(const int32_t* knn_idx, const float* knn_val, cons
 // previous layer's row counts) into out.cnt, their prefix sum into out.so,
 // and gates[l] (dense when the total exceeds out.cap or gates[l - 1] is
 // dense). The layer then overwrites out.cnt with the rows' actual counts.
+// out.rows.so must hold n + 1 entries; part holds scan_parts(n) int32.
 hipError_t launch_sl_slots(const int32_t* knn_idx, int n, int k1, int k2, bool first, bool sym, const int32_t* off,
-                           const int32_t* cnt_prev, const SlOut& out, hipStream_t s);
+                           const int32_t* cnt_prev, const SlOut& out, int32_t* part, hipStream_t s);
 // Layer l >= 2 from the CSR rows of layer l - 1 (runs when gates[l - 1] is
 // sparse): CSR out, or dense rows into hout when gates[l] turns dense.
 hipError_t launch_sparse_prop(SlRows in, const float* sin, const int32_t* knn_idx, const float* knn_val, int n,
@@ -156,7 +165,7 @@ constexpr int kSparseChunk = 16384;  // gallery accumulators per pass of the spa
 inline int64_t sparse_chunks(int64_t n) { return (n + kSparseChunk - 1) / kSparseChunk; }
 // column buckets: (gallery chunk, quarter of the chunk, column)
 inline int64_t sparse_buckets(int64_t n, int64_t ld) { return sparse_chunks(n) * 4 * ld; }
-inline int64_t sparse_scan_parts(int64_t n, int64_t ld) { return (sparse_buckets(n, ld) + 1023) / 1024 + 1; }
+inline int64_t sparse_scan_parts(int64_t n, int64_t ld) { return scan_parts(sparse_buckets(n, ld)); }
 inline int64_t sparse_final_head(int64_t n, int64_t ld) {
   return (3 * sparse_buckets(n, ld) + 2 * n + 4 + 16 + sparse_scan_parts(n, ld) + 3) / 4 * 4;
 }

@@ -112,15 +112,15 @@ hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipS
 
 // CSR rows of sparse layer l (1..L) in its output buffer `buf` (the N x ldN
 // feature buffer it writes: column indices, then values, n * ldN / 2 entries
-// each) and the gates of l and l - 1. Row starts and counts alternate between
-// two sets by the parity of l.
+// each) and the gates of l and l - 1. Row starts (n + 1) and counts (n)
+// alternate between two sets by the parity of l.
 static SlOut sl_out(const Plan& P, void* ws, float* buf, int l) {
   SlGate* gates = at<SlGate>(ws, P.o_slg);
   int32_t* sets = at<int32_t>(ws, P.o_slr);
   const int64_t cap = (int64_t)P.n * P.ldN / 2;
-  int32_t* so = sets + (size_t)(l & 1) * 2 * P.n;
+  int32_t* so = sets + (size_t)(l & 1) * (2 * P.n + 4);
   SlOut o{};
-  o.rows = SlRows{(int32_t*)buf, (float*)((char*)buf + cap * 4), so, so + P.n};
+  o.rows = SlRows{(int32_t*)buf, (float*)((char*)buf + cap * 4), so, so + P.n + 1};
   o.gate = gates + l;
   o.prev = gates + (l - 1);
   o.cap = cap;
@@ -157,7 +157,7 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
       int32_t* inl = sym ? at<int32_t>(ws, P.o_inl) : nullptr;
       if (sym) {
         RR_TRY(launch_mutual(ki, P.n, P.k1, mflag, cnt, s));
-        RR_TRY(launch_scan(cnt, P.n, off, s));
+        RR_TRY(launch_scan(cnt, P.n, off, at<int32_t>(ws, P.o_part), s));
         RR_TRY(launch_csr(ki, P.n, P.k1, mflag, off, cnt + P.n, inl, s));
       }
       RR_STAGE(RERANK_STAGE_ADJACENCY, 1);
@@ -167,7 +167,7 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
         SlGate* gates = at<SlGate>(ws, P.o_slg);
         RR_TRY(launch_fill_zero((float*)gates, (int64_t)(P.layers + 1) * (sizeof(SlGate) / 4), s));
         const SlOut o = sl_out(P, ws, B, 1);
-        RR_TRY(launch_sl_slots(ki, P.n, P.k1, P.k2, true, sym, off, nullptr, o, s));
+        RR_TRY(launch_sl_slots(ki, P.n, P.k1, P.k2, true, sym, off, nullptr, o, at<int32_t>(ws, P.o_part), s));
         RR_TRY(launch_first_layer(ki, kv, mflag, off, inl, P.n, P.k1, P.k2, P.alpha, P.agg, sym, P.ldN, B, sa,
                                   nullptr, nullptr, &o, s));
       } else {
@@ -203,7 +203,8 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
       SlGate* gates = at<SlGate>(ws, P.o_slg);
       const SlOut prev = sl_out(P, ws, (float*)cur, l);
       const SlOut next = sl_out(P, ws, out, l + 1);
-      RR_TRY(launch_sl_slots(ki, P.n, P.k1, P.k2, false, false, nullptr, prev.rows.cnt, next, s));
+      RR_TRY(launch_sl_slots(ki, P.n, P.k1, P.k2, false, false, nullptr, prev.rows.cnt, next,
+                             at<int32_t>(ws, P.o_part), s));
       RR_TRY(launch_sparse_prop(prev.rows, csig, ki, kv, P.n, P.k1, P.k2, P.alpha, P.agg, P.ldH, out, osig, next,
                                 s));
       RR_TRY(launch_propagate_gated(cur, csig, P.n, P.ldH, ki, kv, P.k1, P.k2, P.alpha, P.agg, out, osig, gates, l + 1,

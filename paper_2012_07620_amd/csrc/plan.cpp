@@ -85,6 +85,7 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o, bool dense_layers
     P.o_sa = take(n * 4);
     P.o_sb = take(n * 4);
     P.o_cnt = take(n * 8);  // in-degree and mutual counts (or in-degree and cursor), 2n int32
+    P.o_part = take((size_t)scan_parts(P.n) * 4);  // block sums of the prefix sums over rows
     P.sparse_first = (P.node != RERANK_NODE_RAW && P.layers > 0 && P.agg != RERANK_AGG_MAX);
     if (P.sparse_first && P.node == RERANK_NODE_ADJ_SYM) {
       P.o_mflag = take(n * P.k1);
@@ -95,7 +96,7 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o, bool dense_layers
     P.sparse_layers = P.fprec == FinalPrec::SPARSE && P.sparse_first && !dense_layers;
     if (P.sparse_layers) {
       P.o_slg = take((size_t)(P.layers + 1) * sizeof(SlGate));
-      P.o_slr = take(n * 4 * 4);  // row starts and counts of two layers
+      P.o_slr = take(2 * (2 * n + 4) * 4);  // row starts (n + 1) and counts (n) of two layers
     }
     if (P.fprec == FinalPrec::BF16X3) {
       P.o_hi = take(n * P.ldH * 2);
