@@ -5,6 +5,18 @@
 
 namespace rr {
 
+// Global-memory view of a pointer the compiler cannot prove global (one read
+// from memory), so its accesses become global loads and stores, counted on
+// vmcnt only, instead of flat ones, which also hold up every LDS wait.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin (each XCD has its own L2).
 // Renumber them so each XCD gets a contiguous run of logical indices: work
 // that is close in logical order then shares one L2.

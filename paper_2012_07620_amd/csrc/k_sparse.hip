@@ -12,9 +12,11 @@
 //   3. one workgroup per query keeps the gallery accumulators of a chunk of
 //      the gallery in LDS and, for each non-zero column c of the query in
 //      ascending c, adds h_q[c] * h_g[c] for every gallery row g that is
-//      non-zero in c (one FMA per slot per column: the FP32 sum order depends
-//      only on the data, so results are deterministic);
-//   4. D[q][g] = 1 - sq * sg * acc, the dense epilogue's expression.
+//      non-zero in c (one product and one LDS add per slot per column: the
+//      FP32 sum order depends only on the data, so results are
+//      deterministic);
+//   4. D[q][g] = 1 - sq * acc, the gallery values having been stored times
+//      their row's sg in step 2.
 // The four waves of a workgroup own disjoint quarters of the accumulator
 // chunk and read only their quarter's buckets, so the column loop needs no
 // block barrier; within a wave LDS accesses complete in issue order. Queries
@@ -272,9 +274,9 @@ __device__ __forceinline__ int64_t csc_bucket(int gp, int g) {
 __global__ __launch_bounds__(256) void csc_count_kernel(const SparseSel* __restrict__ sel, int q, int n, int64_t ld,
                                                         int32_t* __restrict__ ccnt) {
   if (sel->mode == 2) return;
-  const int32_t* rs = sel->rs;
-  const int32_t* rc = sel->rc;
-  const int32_t* col = sel->col;
+  const auto rs = gmem(sel->rs);
+  const auto rc = gmem(sel->rc);
+  const auto col = gmem(sel->col);
   const int lane = threadIdx.x & 63;
   for (int r = q + (int)(blockIdx.x * 4 + (threadIdx.x >> 6)); r < n; r += gridDim.x * 4) {
     const int b = rs[r], e = b + rc[r];
@@ -283,50 +285,54 @@ __global__ __launch_bounds__(256) void csc_count_kernel(const SparseSel* __restr
   }
 }
 
+// The gallery values are stored times their row's sigma (sg), so the product
+// ends with D = 1 - sq * acc and reads no per-column scale.
 __global__ __launch_bounds__(256) void csc_fill_kernel(const SparseSel* __restrict__ sel, int q, int n, int64_t ld,
-                                                       const int32_t* __restrict__ coff, int32_t* __restrict__ cursor) {
+                                                       const int32_t* __restrict__ coff, const float* __restrict__ sg,
+                                                       int32_t* __restrict__ cursor) {
   if (sel->mode == 2) return;
-  const int32_t* rs = sel->rs;
-  const int32_t* rc = sel->rc;
-  const int32_t* col = sel->col;
-  const float* val = sel->val;
-  int32_t* crow = sel->crow;
-  float* cval = sel->cval;
+  const auto rs = gmem(sel->rs);
+  const auto rc = gmem(sel->rc);
+  const auto col = gmem(sel->col);
+  const auto val = gmem(sel->val);
+  const auto crow = gmem(sel->crow);
+  const auto cval = gmem(sel->cval);
   const int lane = threadIdx.x & 63;
   for (int r = q + (int)(blockIdx.x * 4 + (threadIdx.x >> 6)); r < n; r += gridDim.x * 4) {
     const int b = rs[r], e = b + rc[r];
     const int64_t cb = csc_bucket(r - q, n - q) * ld;
+    const float sr = sg[r - q];
     for (int t = b + lane; t < e; t += 64) {
       const int64_t c = cb + col[t];
       const int pos = coff[c] + atomicAdd(cursor + c, 1);
       crow[pos] = r - q;
-      cval[pos] = val[t];
+      cval[pos] = val[t] * sr;
     }
   }
 }
 
 constexpr int SF_QCH = 256;  // query non-zeros staged per pass
-constexpr int SF_ILP = 4;    // columns whose first 64 entries are loaded together
+constexpr int SF_ILP = 16;   // columns whose first 64 entries are loaded together
 
-// D[q][g] = 1 - sq * sg * sum_c u_q[c] u_g[c]. One workgroup per query, the
+// D[q][g] = 1 - sq * sum_c u_q[c] (sg u_g[c]). One workgroup per query, the
 // queries in cluster order with consecutive ones on one XCD (they read the
 // same gallery columns). Wave w owns quarter w of each gallery chunk and reads
 // only that quarter's buckets.
 __global__ __launch_bounds__(256) void sparse_final_kernel(const SparseSel* __restrict__ sel,
                                                            const int32_t* __restrict__ coff, int64_t ld,
                                                            const int32_t* __restrict__ qorder,
-                                                           const float* __restrict__ sq, const float* __restrict__ sg,
-                                                           int g, float* __restrict__ dist, int64_t ldd) {
+                                                           const float* __restrict__ sq, int g,
+                                                           float* __restrict__ dist, int64_t ldd) {
   if (sel->mode == 2) return;
   __shared__ float acc[SF_GCH];
   __shared__ int cb[4][SF_QCH], ce[4][SF_QCH];
   __shared__ float qv[SF_QCH];
-  const int32_t* col = sel->col;
-  const float* val = sel->val;
-  const int32_t* crow = sel->crow;
-  const float* cval = sel->cval;
+  const auto col = gmem(sel->col);
+  const auto val = gmem(sel->val);
+  const auto crow = gmem(sel->crow);
+  const auto cval = gmem(sel->cval);
   const int qi = qorder[xcd_linear(blockIdx.x, gridDim.x)], tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int b = sel->rs[qi], nq = sel->rc[qi];
+  const int b = gmem(sel->rs)[qi], nq = gmem(sel->rc)[qi];
   const float sqq = sq[qi];
   float* drow = dist + (int64_t)qi * ldd;
   for (int g0 = 0; g0 < g; g0 += SF_GCH) {
@@ -351,33 +357,43 @@ __global__ __launch_bounds__(256) void sparse_final_kernel(const SparseSel* __re
       }
       __syncthreads();
       for (int t = 0; t < tn; t += SF_ILP) {
+        // bucket bounds of SF_ILP columns, then their first 64 entries: loads
+        // without branches (a load inside a divergent block is waited for at
+        // the block's end), invalid lanes read entry 0 and drop it
+        int bb[SF_ILP], be[SF_ILP];
+#pragma unroll
+        for (int u = 0; u < SF_ILP; u++) {
+          const int tt = min(t + u, tn - 1);
+          bb[u] = cb[w][tt];
+          be[u] = (t + u < tn) ? ce[w][tt] : bb[u];
+        }
         int r[SF_ILP];
         float xv[SF_ILP];
 #pragma unroll
         for (int u = 0; u < SF_ILP; u++) {
-          r[u] = -1;
-          xv[u] = 0.f;
-          if (t + u < tn) {
-            const int s = cb[w][t + u] + lane;
-            if (s < ce[w][t + u]) {
-              r[u] = crow[s] - base;
-              xv[u] = cval[s];
-            }
-          }
+          const int s = bb[u] + lane;
+          const bool ok = s < be[u];
+          const int si = ok ? s : 0;
+          const int rv = crow[si];
+          xv[u] = cval[si];
+          r[u] = ok ? rv - base : -1;
         }
+        // one LDS add per entry (no return value, so nothing waits); a
+        // wave's LDS operations run in issue order, so every slot gets its
+        // columns' terms in ascending column order
 #pragma unroll
         for (int u = 0; u < SF_ILP; u++) {
           if (t + u >= tn) break;
           const float v = qv[t + u];
-          if ((unsigned)r[u] < (unsigned)len) acc[lo + r[u]] = __builtin_fmaf(v, xv[u], acc[lo + r[u]]);
-          for (int s = cb[w][t + u] + 64 + lane; s < ce[w][t + u]; s += 64) {  // buckets longer than 64
+          if ((unsigned)r[u] < (unsigned)len) atomicAdd(&acc[lo + r[u]], v * xv[u]);
+          for (int s = bb[u] + 64 + lane; s < be[u]; s += 64) {  // buckets longer than 64
             const int rr = crow[s] - base;
-            if ((unsigned)rr < (unsigned)len) acc[lo + rr] = __builtin_fmaf(v, cval[s], acc[lo + rr]);
+            if ((unsigned)rr < (unsigned)len) atomicAdd(&acc[lo + rr], v * cval[s]);
           }
         }
       }
     }
-    for (int k = lane; k < len; k += 64) drow[g0 + lo + k] = 1.0f - sqq * sg[g0 + lo + k] * acc[lo + k];
+    for (int k = lane; k < len; k += 64) drow[g0 + lo + k] = 1.0f - sqq * acc[lo + k];
   }
 }
 
@@ -434,9 +450,8 @@ hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const f
   hipLaunchKernelGGL(csc_count_kernel, dim3(rb), dim3(256), 0, s, sel, q, n, ld, ccnt);
   e = launch_scan(ccnt, nb, coff, part, s, &sel->mode, 2);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(csc_fill_kernel, dim3(rb), dim3(256), 0, s, sel, q, n, ld, coff, cursor);
-  hipLaunchKernelGGL(sparse_final_kernel, dim3(q), dim3(256), 0, s, sel, coff, ld, qorder, sigma, sigma + q, g, dist,
-                     (int64_t)g);
+  hipLaunchKernelGGL(csc_fill_kernel, dim3(rb), dim3(256), 0, s, sel, q, n, ld, coff, sigma + q, cursor);
+  hipLaunchKernelGGL(sparse_final_kernel, dim3(q), dim3(256), 0, s, sel, coff, ld, qorder, sigma, g, dist, (int64_t)g);
   const int tm = (q + BM - 1) / BM, tn = (g + BN - 1) / BN;
   GemmArgs ga{(const uint8_t*)H, (const uint8_t*)(H + (int64_t)q * ld), q, g, ld * 4, ld * 4, (int)(ld * 4 / BKB),
               sigma, sigma + q, dist, (int64_t)g};
