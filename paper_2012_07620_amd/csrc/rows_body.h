@@ -342,30 +342,36 @@ __device__ __forceinline__ void split_store4(uint16_t* __restrict__ hi, uint16_t
 // itself with e_ii = 1), each times the carried 1/|u_j| of its input row.
 // sum: member 0 also takes the residual h_i; mean: messages scaled by 1/k2,
 // residual added to member 0; max: messages kept apart, residual in res.
+// Coefficient of member r (thread r < k2); returns its row j.
+__device__ __forceinline__ int coef_member(const float* __restrict__ sin, const int32_t* __restrict__ knn,
+                                           const float* __restrict__ kv, int k1, int k2, int alpha, int agg, int i,
+                                           int r, PropShared& sh) {
+  const int j = knn[(int64_t)i * k1 + r];
+  float w = 1.0f;
+  if (r > 0) {
+    const float e = kv[(int64_t)i * k1 + r];
+    for (int a = 0; a < alpha; a++) w *= e;
+  }
+  const float sj = sin ? sin[j] : 1.0f;
+  const float msg = w * sj;
+  float c = msg;
+  if (agg == RERANK_AGG_MEAN) c = msg / (float)k2;
+  if (r == 0) {
+    if (agg == RERANK_AGG_MAX)
+      sh.res = sj;
+    else
+      c = sj + c;  // residual + own message (sum: exactly 2 * sj)
+  }
+  sh.cf[r] = c;
+  sh.nb[r] = j;
+  return j;
+}
+
 __device__ __forceinline__ void load_coefs(const float* __restrict__ sin, const int32_t* __restrict__ knn,
                                            const float* __restrict__ kv, int k1, int k2, int alpha, int agg, int i,
                                            PropShared& sh) {
   const int tid = threadIdx.x;
-  if (tid < k2) {
-    const int j = knn[(int64_t)i * k1 + tid];
-    float w = 1.0f;
-    if (tid > 0) {
-      const float e = kv[(int64_t)i * k1 + tid];
-      for (int a = 0; a < alpha; a++) w *= e;
-    }
-    const float sj = sin ? sin[j] : 1.0f;
-    const float msg = w * sj;
-    float c = msg;
-    if (agg == RERANK_AGG_MEAN) c = msg / (float)k2;
-    if (tid == 0) {
-      if (agg == RERANK_AGG_MAX)
-        sh.res = sj;
-      else
-        c = sj + c;  // residual + own message (sum: exactly 2 * sj)
-    }
-    sh.cf[tid] = c;
-    sh.nb[tid] = j;
-  }
+  if (tid < k2) coef_member(sin, knn, kv, k1, k2, alpha, agg, i, tid, sh);
   __syncthreads();
 }
 
@@ -486,18 +492,17 @@ __device__ __forceinline__ void csr_pair(const int32_t* __restrict__ knn, int n,
 // sparse layers from CSR rows), one LDS column chunk at a time.
 constexpr int FIRST_CHUNK = 8192;    // floats of the output row held in LDS
 constexpr int FIRST_WORDS = FIRST_CHUNK / 32;  // touched-column bitmap of a chunk
-constexpr int FIRST_ENTRIES = 2048;  // member entries of one row staged in LDS
-constexpr int HASH_SLOTS = 4096;     // hashed sums of one CSR row (load factor at most 1/2)
+constexpr int FIRST_ENTRIES = 1024;  // member entries of one row staged in LDS
 constexpr int ROW_WORDS = 2048;      // touched-column bitmap of a whole row (rows up to 65536 columns)
-struct HashTab {
-  int key[HASH_SLOTS];  // column, or -1
-  float val[HASH_SLOTS];
+struct RankTab {
+  int base[ROW_WORDS];         // touched columns before each bitmap word
+  float val[FIRST_ENTRIES];    // sums of the touched columns, in column order
 };
 struct FirstShared {
   PropShared p;
   union {
     float row[FIRST_CHUNK];  // chunked path: sums; valid only where the bitmap is set
-    HashTab ht;              // hashed path
+    RankTab rk;              // ranked path
   };
   uint32_t bits[ROW_WORDS];  // touched columns (of the chunk, or of the whole row)
   int col[FIRST_ENTRIES];
@@ -558,73 +563,37 @@ __device__ __forceinline__ void sparse_add(FirstShared& sh, int m, float c, floa
   sh.row[m] = __builtin_fmaf(c, v, (old & bit) ? sh.row[m] : 0.0f);
 }
 
-// CSR rows whose staged entries fit the hash table skip the column chunks:
-// sums live in an LDS hash table keyed by column (first touch starts from 0,
-// then one FMA per entry in member order, exactly as in the chunks) and a
-// bitmap of the whole row marks the touched columns, which gives the
-// ascending column order for the output and the dense store's per-thread
-// order for the squared norm (thread t owns float4 columns t, t + 256, ...).
-__device__ __forceinline__ uint32_t hash_col(int c) { return ((uint32_t)c * 2654435761u) >> 20; }
-
-__device__ __forceinline__ float hash_get(const FirstShared& sh, int c) {
-  uint32_t h = hash_col(c);
-  while (sh.ht.key[h] != c) h = (h + 1) & (HASH_SLOTS - 1);
-  return sh.ht.val[h];
+// CSR rows whose staged entries fit skip the column chunks. A bitmap of the
+// whole row marks every column the members touch; a prefix count over its
+// words gives each touched column its rank (its position in column order),
+// and the sums live in an LDS array indexed by rank, starting from 0 and
+// taking one FMA per entry in member order, exactly as in the chunks. The
+// ranks give the ascending column order of the output directly, and the
+// bitmap gives the dense store's per-thread order for the squared norm
+// (thread t owns float4 columns t, t + 256, ...).
+__device__ __forceinline__ int col_rank(const FirstShared& sh, int c) {
+  const uint32_t wd = sh.bits[c >> 5];
+  return sh.rk.base[c >> 5] + __builtin_popcount(wd & ((1u << (c & 31)) - 1u));
 }
 
 // Returns the end of the written entries; *ss receives the squared norm.
-__device__ __forceinline__ int hashed_row(FirstShared& sh, int k2, int64_t ld, const SlRows& out, int pos,
+__device__ __forceinline__ int ranked_row(FirstShared& sh, int k2, int64_t ld, const SlRows& out, int pos,
                                           float* ss) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int words = (int)(ld >> 5);
+  const int total_e = sh.start[k2];
   for (int k = tid; k < words; k += 256) sh.bits[k] = 0u;
-  for (int k = tid; k < HASH_SLOTS; k += 256) sh.ht.key[k] = -1;
   __syncthreads();
-  for (int r = 0; r < k2; r++) {
-    const float c = sh.p.cf[r];
-    for (int s = sh.start[r] + tid; s < sh.start[r + 1]; s += 256) {  // distinct columns within a member
-      const int col = sh.col[s];
-      const float v = sh.val[s];
-      uint32_t h = hash_col(col);
-      while (true) {
-        const int old = atomicCAS(&sh.ht.key[h], -1, col);
-        if (old == -1) {
-          sh.ht.val[h] = __builtin_fmaf(c, v, 0.0f);
-          atomicOr(&sh.bits[col >> 5], 1u << (col & 31));
-          break;
-        }
-        if (old == col) {
-          sh.ht.val[h] = __builtin_fmaf(c, v, sh.ht.val[h]);
-          break;
-        }
-        h = (h + 1) & (HASH_SLOTS - 1);
-      }
-    }
-    __syncthreads();
+  for (int s = tid; s < total_e; s += 256) {
+    const int c = sh.col[s];
+    atomicOr(&sh.bits[c >> 5], 1u << (c & 31));
   }
-  float acc = 0.f;
-  for (int f = tid; f < (int)(ld >> 2); f += 256) {
-    const uint32_t nib = (sh.bits[f >> 3] >> ((f & 7) * 4)) & 0xFu;
-    if (nib)
-      for (int e = 0; e < 4; e++)
-        if (nib & (1u << e)) {
-          const float v = hash_get(sh, 4 * f + e);
-          acc = __builtin_fmaf(v, v, acc);
-        }
-  }
-  *ss = acc;
-  // thread t emits a contiguous run of bitmap words: counts, block scan, writes
+  __syncthreads();
+  // ranks: thread t owns a contiguous run of words
   const int per = (words + 255) / 256;
   const int w0 = min(words, tid * per), w1 = min(words, w0 + per);
   int mine = 0;
-  for (int x = w0; x < w1; x++) {
-    uint32_t wd = sh.bits[x];
-    while (wd) {
-      const int b = __builtin_ctz(wd);
-      wd &= wd - 1u;
-      mine += hash_get(sh, 32 * x + b) != 0.f;
-    }
-  }
+  for (int x = w0; x < w1; x++) mine += __builtin_popcount(sh.bits[x]);
   int incl = mine;
   for (int o = 1; o < 64; o <<= 1) {
     const int t = __shfl_up(incl, o, kWave);
@@ -632,17 +601,64 @@ __device__ __forceinline__ int hashed_row(FirstShared& sh, int k2, int64_t ld, c
   }
   if (lane == 63) sh.wsum[w] = incl;
   __syncthreads();
-  int at = pos + incl - mine, total = 0;
+  int run = incl - mine;
+  for (int x = 0; x < w; x++) run += sh.wsum[x];
+  const int touched = sh.wsum[0] + sh.wsum[1] + sh.wsum[2] + sh.wsum[3];
+  for (int x = w0; x < w1; x++) {
+    sh.rk.base[x] = run;
+    run += __builtin_popcount(sh.bits[x]);
+  }
+  for (int k = tid; k < touched; k += 256) sh.rk.val[k] = 0.f;
+  __syncthreads();
+  for (int r = 0; r < k2; r++) {
+    const float c = sh.p.cf[r];
+    for (int s = sh.start[r] + tid; s < sh.start[r + 1]; s += 256) {  // distinct columns within a member
+      const int k = col_rank(sh, sh.col[s]);
+      sh.rk.val[k] = __builtin_fmaf(c, sh.val[s], sh.rk.val[k]);
+    }
+    __syncthreads();
+  }
+  float acc = 0.f;
+  const int nf = (int)(ld >> 2);
+  for (int f = tid; f < nf; f += 256) {
+    const uint32_t nib = (sh.bits[f >> 3] >> ((f & 7) * 4)) & 0xFu;
+    if (nib) {
+      const int k0 = col_rank(sh, 4 * f);  // rank of the first column of this float4
+      int k = k0;
+      for (int e = 0; e < 4; e++)
+        if (nib & (1u << e)) {
+          const float v = sh.rk.val[k++];
+          acc = __builtin_fmaf(v, v, acc);
+        }
+    }
+  }
+  *ss = acc;
+  // output: the same contiguous word runs, exact zeros (cancelled sums) dropped
+  int keep = 0;
+  for (int x = w0; x < w1; x++) {
+    const int b0 = sh.rk.base[x], nb = __builtin_popcount(sh.bits[x]);
+    for (int k = b0; k < b0 + nb; k++) keep += sh.rk.val[k] != 0.f;
+  }
+  incl = keep;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  __syncthreads();  // everyone has read wsum above
+  if (lane == 63) sh.wsum[w] = incl;
+  __syncthreads();
+  int at = pos + incl - keep, total = 0;
   for (int x = 0; x < 4; x++) {
     at += (x < w) ? sh.wsum[x] : 0;
     total += sh.wsum[x];
   }
   for (int x = w0; x < w1; x++) {
     uint32_t wd = sh.bits[x];
+    int k = sh.rk.base[x];
     while (wd) {
       const int b = __builtin_ctz(wd);
       wd &= wd - 1u;
-      const float v = hash_get(sh, 32 * x + b);
+      const float v = sh.rk.val[k++];
       if (v != 0.f) {
         out.col[at] = 32 * x + b;
         out.val[at] = v;
@@ -663,12 +679,17 @@ __device__ __forceinline__ int hashed_row(FirstShared& sh, int k2, int64_t ld, c
 // per-thread order (thread t owns float4 columns t, t + 256, ... of a chunk),
 // so sigma is identical either way.
 template <class Src>
-__device__ __forceinline__ void sparse_row_core(const Src& src, int k2, int64_t ld, float* __restrict__ hout,
-                                                uint16_t* __restrict__ hi, uint16_t* __restrict__ lo,
-                                                float* __restrict__ sout, const SlOut* sl, int i, FirstShared& sh) {
+__device__ __forceinline__ void sparse_row_core(const Src& src, const float* __restrict__ sin,
+                                                const int32_t* __restrict__ knn, const float* __restrict__ kv,
+                                                int k1, int k2, int alpha, int agg, int64_t ld,
+                                                float* __restrict__ hout, uint16_t* __restrict__ hi,
+                                                uint16_t* __restrict__ lo, float* __restrict__ sout,
+                                                const SlOut* sl, int i, FirstShared& sh) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid < k2) {
-    const int j = sh.p.nb[tid];
+  int pos = 0;
+  const bool csr = sl_begin(sl, i, &pos);  // issued first: independent of the members
+  if (tid < k2) {  // coefficients and entry counts in one round of loads
+    const int j = coef_member(sin, knn, kv, k1, k2, alpha, agg, i, tid, sh.p);
     sh.mcnt[tid] = src.count(j);
     sh.mbase[tid] = src.base(j);
   }
@@ -702,12 +723,10 @@ __device__ __forceinline__ void sparse_row_core(const Src& src, int k2, int64_t 
     }
   }
   __syncthreads();
-  int pos = 0;
-  const bool csr = sl_begin(sl, i, &pos);
   const int pos0 = pos;
   float ss = 0.f;
   if (csr && staged && (ld >> 5) <= ROW_WORDS) {
-    const int end = hashed_row(sh, k2, ld, sl->rows, pos, &ss);
+    const int end = ranked_row(sh, k2, ld, sl->rows, pos, &ss);
     if (tid == 0) {
       sl->rows.so[i] = pos0;
       sl->rows.cnt[i] = end - pos0;
@@ -810,9 +829,8 @@ __device__ __forceinline__ void first_layer_row(const int32_t* __restrict__ knn,
                                                 float* __restrict__ sout, uint16_t* __restrict__ hi,
                                                 uint16_t* __restrict__ lo, int i, FirstShared& sh,
                                                 const SlOut* sl = nullptr) {
-  load_coefs(nullptr, knn, kv, k1, k2, alpha, agg, i, sh.p);
   const FirstSrc src{knn, mflag, off, inl, k1, sym};
-  sparse_row_core(src, k2, ld, hout, hi, lo, sout, sl, i, sh);
+  sparse_row_core(src, nullptr, knn, kv, k1, k2, alpha, agg, ld, hout, hi, lo, sout, sl, i, sh);
 }
 
 // Layer l >= 2 of the sparse layers from the CSR rows of layer l - 1
@@ -822,9 +840,8 @@ __device__ __forceinline__ void sparse_prop_row(const SlRows& in, const float* _
                                                 int k1, int k2, int alpha, int agg, int64_t ld,
                                                 float* __restrict__ hout, float* __restrict__ sout, const SlOut* sl,
                                                 int i, FirstShared& sh) {
-  load_coefs(sin, knn, kv, k1, k2, alpha, agg, i, sh.p);
   const CsrSrc src{in};
-  sparse_row_core(src, k2, ld, hout, nullptr, nullptr, sout, sl, i, sh);
+  sparse_row_core(src, sin, knn, kv, k1, k2, alpha, agg, ld, hout, nullptr, nullptr, sout, sl, i, sh);
 }
 
 }  // namespace rr
