@@ -28,7 +28,9 @@ constexpr int TSTRIDE = BM + 1;            // transposed-tile LDS row stride (fl
 static_assert(BN * TSTRIDE * 4 <= GEMM_LDS_BYTES, "transpose staging must fit the GEMM LDS");
 
 enum { MODE_F32 = 0, MODE_BF16 = 1, MODE_FP8 = 2 };
-enum { EPI_SIM = 0, EPI_DIST = 1, EPI_SIM_SYM = 2 };
+// EPI_SIM_SYM16: EPI_SIM_SYM storing S as IEEE binary16 (the low-precision
+// paths, whose S only ranks candidates that are then re-scored in FP32).
+enum { EPI_SIM = 0, EPI_DIST = 1, EPI_SIM_SYM = 2, EPI_SIM_SYM16 = 3 };
 
 template <int MODE>
 __device__ __forceinline__ void mfma_stage(f32x16 (&acc)[2][2], const u32x4 (&a)[2][4], const u32x4 (&b)[2][4]) {
@@ -89,8 +91,8 @@ struct GemmArgs {
 // thread of the workgroup must call it with the same tile. NBUF = 1 keeps one
 // LDS stage and prefetches the next into registers (more workgroups per CU;
 // measured faster than NBUF = 2 double buffering on the 19281-row problem).
-// EPI_SIM_SYM (A == B, tm <= tn): also stores the mirrored tile C^T, so only
-// the upper triangle of tiles is computed.
+// EPI_SIM_SYM / EPI_SIM_SYM16 (A == B, tm <= tn): also stores the mirrored
+// tile C^T, so only the upper triangle of tiles is computed.
 template <int MODE, int EPI, int NBUF = 1>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uint8_t* lds) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -181,7 +183,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
 
   // 32x32 accumulator layout: register r of lane l holds
   // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of its block.
-  const bool mirror = (EPI == EPI_SIM_SYM) && (tm != tn);
+  const bool mirror = (EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16) && (tm != tn);
+  _Float16* out16 = (_Float16*)g.out;  // EPI_SIM_SYM16: ldo counts halves
   float* tr = (float*)lds;  // transposed staging, valid after the loop's last barrier
 #pragma unroll
   for (int sm = 0; sm < 2; sm++)
@@ -199,7 +202,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
           if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = 1.0f - g.sa[row] * scol * v;
         } else {
           const float s = (row < g.M && col < g.Nn) ? v * g.sa[row] * scol + 0.0f : 0.f;
-          if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = s;
+          if (row < g.M && col < g.Nn) {
+            if (EPI == EPI_SIM_SYM16)
+              out16[(int64_t)row * g.ldo + col] = (_Float16)s;
+            else
+              g.out[(int64_t)row * g.ldo + col] = s;
+          }
           if (mirror) tr[lc * TSTRIDE + lr] = s;
         }
       }
@@ -210,7 +218,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
     const int c = tid & 127;
     for (int rr = tid >> 7; rr < BN; rr += 2) {
       const int row = n0 + rr, col = m0 + c;
-      if (row < g.Nn && col < g.M) g.out[(int64_t)row * g.ldo + col] = tr[rr * TSTRIDE + c];
+      if (row < g.Nn && col < g.M) {
+        if (EPI == EPI_SIM_SYM16)
+          out16[(int64_t)row * g.ldo + col] = (_Float16)tr[rr * TSTRIDE + c];
+        else
+          g.out[(int64_t)row * g.ldo + col] = tr[rr * TSTRIDE + c];
+      }
     }
   }
   __syncthreads();  // LDS is reused by the next tile of a persistent workgroup

@@ -24,10 +24,11 @@ __device__ __forceinline__ TileMap grouped_order(int pid, int tiles_m, int tiles
 
 template <int MODE, int EPI>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g, int tiles_m, int tiles_n) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[EPI == EPI_SIM_SYM ? GEMM_LDS_BYTES : GEMM_LDS_1BUF];
+  constexpr bool SYM = EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[SYM ? GEMM_LDS_BYTES : GEMM_LDS_1BUF];
   const int pid = xcd_linear(blockIdx.x, gridDim.x);
   int tm, tn;
-  if (EPI == EPI_SIM_SYM) {
+  if (SYM) {
     upper_tile(pid, tiles_m, tm, tn);
   } else {
     const TileMap t = grouped_order(pid, tiles_m, tiles_n);
@@ -41,7 +42,7 @@ template <int MODE, int EPI>
 static hipError_t launch_gemm_t(const void* a, int M, int64_t lda, const void* b, int Nn, int64_t ldb, int64_t kbytes,
                                 const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s) {
   const int tm = (M + BM - 1) / BM, tn = (Nn + BN - 1) / BN;
-  const int64_t nwg = (EPI == EPI_SIM_SYM) ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tm * tn;
+  const int64_t nwg = (EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16) ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tm * tn;
   if (nwg <= 0 || nwg > 0x7FFFFFFF || kbytes % BKB || kbytes <= 0) return hipErrorInvalidValue;
   GemmArgs g{(const uint8_t*)a, (const uint8_t*)b, M, Nn, lda, ldb, (int)(kbytes / BKB), sa, sb, out, ldo};
   hipLaunchKernelGGL((gemm_nt_kernel<MODE, EPI>), dim3((unsigned)nwg), dim3(256), 0, s, g, tm, tn);
@@ -49,14 +50,20 @@ static hipError_t launch_gemm_t(const void* a, int M, int64_t lda, const void* b
 }
 
 hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes, const float* sa,
-                           float* out, int64_t ldo, hipStream_t s) {
+                           void* out, int64_t ldo, bool half_out, hipStream_t s) {
+  float* o = (float*)out;
+  if (half_out && prec == SimPrec::F32) return hipErrorInvalidValue;  // the FP32 path keeps S exact
   switch (prec) {
     case SimPrec::F32:
-      return launch_gemm_t<MODE_F32, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, out, ldo, s);
+      return launch_gemm_t<MODE_F32, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, o, ldo, s);
     case SimPrec::BF16:
-      return launch_gemm_t<MODE_BF16, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, out, ldo, s);
+      return half_out
+                 ? launch_gemm_t<MODE_BF16, EPI_SIM_SYM16>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, o, ldo, s)
+                 : launch_gemm_t<MODE_BF16, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, o, ldo, s);
     case SimPrec::FP8:
-      return launch_gemm_t<MODE_FP8, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, out, ldo, s);
+      return half_out
+                 ? launch_gemm_t<MODE_FP8, EPI_SIM_SYM16>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, o, ldo, s)
+                 : launch_gemm_t<MODE_FP8, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, o, ldo, s);
   }
   return hipErrorInvalidValue;
 }

@@ -52,18 +52,19 @@ __global__ __launch_bounds__(256) void g_sim(const BatchTable* __restrict__ t) {
     const int T = (D.n + BM - 1) / BM;
     int tm, tn;
     upper_tile(item - t->start[GS_SIM][p], T, tm, tn);
-    gemm_tile<MODE, EPI_SIM_SYM>(g, tm, tn, lds);
+    gemm_tile<MODE, MODE == MODE_F32 ? EPI_SIM_SYM : EPI_SIM_SYM16>(g, tm, tn, lds);  // as the direct path
   }
 }
 
-template <int R>
+template <int R, typename T>
 __global__ __launch_bounds__(256) void g_topk(const BatchTable* __restrict__ t) {
   __shared__ uint64_t ring_all[4][128];
   FOR_ITEMS(GS_TOPK) {
     const int p = find_prob(t, GS_TOPK, item);
     const ProbDesc& D = t->p[p];
     const int i = (item - t->start[GS_TOPK][p]) * 4 + (threadIdx.x >> 6);
-    if (i < D.n) topk_row<R>(D.A, D.ldN, D.n, i, D.kc, D.ci, D.cv, D.kc, ring_all[threadIdx.x >> 6]);
+    if (i < D.n)
+      topk_row<R, false, T>((const T*)D.A, D.ldN, D.n, i, D.kc, D.ci, D.cv, D.kc, ring_all[threadIdx.x >> 6]);
   }
 }
 
@@ -228,17 +229,18 @@ hipError_t enqueue_grouped(const BatchKey& key, const BatchTable* d_tab, hipStre
       GTRY(go(g_sim<MODE_FP8>, kGroupedGemmWGs, s, d_tab));
       break;
   }
+  const bool half = prec != SimPrec::F32;  // S in binary16, as the direct path
   switch (key.r) {
     case 1:
-      GTRY(go(g_topk<1>, kGroupedRowWGs, s, d_tab));
+      GTRY(half ? go(g_topk<1, _Float16>, kGroupedRowWGs, s, d_tab) : go(g_topk<1, float>, kGroupedRowWGs, s, d_tab));
       GTRY(go(g_rescore<1>, kGroupedRowWGs, s, d_tab));
       break;
     case 2:
-      GTRY(go(g_topk<2>, kGroupedRowWGs, s, d_tab));
+      GTRY(half ? go(g_topk<2, _Float16>, kGroupedRowWGs, s, d_tab) : go(g_topk<2, float>, kGroupedRowWGs, s, d_tab));
       GTRY(go(g_rescore<2>, kGroupedRowWGs, s, d_tab));
       break;
     default:
-      GTRY(go(g_topk<4>, kGroupedRowWGs, s, d_tab));
+      GTRY(half ? go(g_topk<4, _Float16>, kGroupedRowWGs, s, d_tab) : go(g_topk<4, float>, kGroupedRowWGs, s, d_tab));
       GTRY(go(g_rescore<4>, kGroupedRowWGs, s, d_tab));
       break;
   }

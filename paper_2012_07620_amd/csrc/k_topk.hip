@@ -4,26 +4,35 @@
 
 namespace rr {
 
-template <int R>
-__global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ S, int64_t ldS, int N, int rows, int K,
+template <int R, typename T>
+__global__ __launch_bounds__(256) void topk_kernel(const T* __restrict__ S, int64_t ldS, int N, int rows, int K,
                                                    int32_t* __restrict__ oidx, float* __restrict__ oval, int ldo) {
   __shared__ uint64_t ring_all[4][128];
   const int w = threadIdx.x >> 6;
   const int i = blockIdx.x * 4 + w;
   if (i >= rows) return;  // no block-level barriers in the body: waves are independent
-  topk_row<R>(S, ldS, N, i, K, oidx, oval, ldo, ring_all[w]);
+  topk_row<R, false, T>(S, ldS, N, i, K, oidx, oval, ldo, ring_all[w]);
 }
 
-hipError_t launch_topk(const float* S, int64_t ldS, int N, int rows, int K, int32_t* idx, float* val, int ldo,
-                       hipStream_t s) {
-  if (K < 1 || K > 256 || K > N || (ldS & 3)) return hipErrorInvalidValue;
+template <typename T>
+static void launch_topk_t(const T* S, int64_t ldS, int N, int rows, int K, int32_t* idx, float* val, int ldo,
+                          hipStream_t s) {
   dim3 grid((rows + 3) / 4), block(256);
   if (K <= 64)
-    hipLaunchKernelGGL(topk_kernel<1>, grid, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
+    hipLaunchKernelGGL((topk_kernel<1, T>), grid, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
   else if (K <= 128)
-    hipLaunchKernelGGL(topk_kernel<2>, grid, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
+    hipLaunchKernelGGL((topk_kernel<2, T>), grid, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
   else
-    hipLaunchKernelGGL(topk_kernel<4>, grid, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
+    hipLaunchKernelGGL((topk_kernel<4, T>), grid, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
+}
+
+hipError_t launch_topk(const void* S, bool half, int64_t ldS, int N, int rows, int K, int32_t* idx, float* val,
+                       int ldo, hipStream_t s) {
+  if (K < 1 || K > 256 || K > N || (ldS & 3)) return hipErrorInvalidValue;
+  if (half)
+    launch_topk_t((const _Float16*)S, ldS, N, rows, K, idx, val, ldo, s);
+  else
+    launch_topk_t((const float*)S, ldS, N, rows, K, idx, val, ldo, s);
   return hipGetLastError();
 }
 

@@ -60,9 +60,13 @@ hipError_t launch_prep(const void* x, int in_bf16, int n, int d, float* xp, int6
 
 // a2 / a7: C = A * B^T on matrix cores. A: M rows, B: Nn rows, K-major,
 // row strides in bytes (multiples of 128), kbytes = K extent in bytes.
-// Similarity epilogue: out[i][j] = acc * sa[i] * sb[j] (-0 -> +0), ldo floats.
+// Similarity epilogue: out[i][j] = acc * sa[i] * sb[j] (-0 -> +0), ldo
+// elements: FP32, or binary16 (round to nearest even) with half_out, which
+// the low-precision paths use (their S only ranks candidates that are then
+// re-scored in FP32; binary16 rounding, at most 2^-11 relative, is below the
+// error of the BF16 / FP8 product itself) to halve S's bytes.
 hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes,
-                           const float* sa, float* out, int64_t ldo, hipStream_t s);
+                           const float* sa, void* out, int64_t ldo, bool half_out, hipStream_t s);
 // Final epilogue: out[q][g] = 1 - sa[q] * sb[g] * acc, ldo floats.
 hipError_t launch_gemm_dist(const float* a, int M, const float* b, int Nn, int64_t ld_elems, int64_t kelems,
                             const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s);
@@ -70,9 +74,10 @@ hipError_t launch_gemm_dist_bf16x3(const uint16_t* a_hi, const uint16_t* a_lo, i
                                    const uint16_t* b_lo, int Nn, int64_t ld_elems, int64_t kelems,
                                    const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s);
 
-// a3: per-row top-K (K <= 256) of rows [0, rows) of S (row stride ldS,
-// N valid columns) under (value desc, column asc), the row's own column first.
-hipError_t launch_topk(const float* S, int64_t ldS, int N, int rows, int K, int32_t* idx, float* val,
+// a3: per-row top-K (K <= 256) of rows [0, rows) of S (FP32, or binary16
+// with half; row stride ldS elements, N valid columns) under (value desc,
+// column asc), the row's own column first.
+hipError_t launch_topk(const void* S, bool half, int64_t ldS, int N, int rows, int K, int32_t* idx, float* val,
                        int ldo, hipStream_t s);
 
 // Cluster order of rows [0, rows) of `lists` (row width w, entries < n):

@@ -94,12 +94,12 @@ hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipS
   RR_STAGE(RERANK_STAGE_PREP, 1);
   RR_STAGE(RERANK_STAGE_SIMILARITY, 0);
   if (P.prec == SimPrec::F32)
-    RR_TRY(launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, S, P.ldN, s));
+    RR_TRY(launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, S, P.ldN, false, s));
   else
-    RR_TRY(launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, S, P.ldN, s));
+    RR_TRY(launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, S, P.ldN, true, s));
   RR_STAGE(RERANK_STAGE_SIMILARITY, 1);
   RR_STAGE(RERANK_STAGE_TOPK, 0);
-  RR_TRY(launch_topk(S, P.ldN, P.n, P.n, P.kc, ci, cv, P.kc, s));
+  RR_TRY(launch_topk(S, P.prec != SimPrec::F32, P.ldN, P.n, P.n, P.kc, ci, cv, P.kc, s));
   RR_STAGE(RERANK_STAGE_TOPK, 1);
   RR_STAGE(RERANK_STAGE_RESCORE, 0);
   if (P.rescore)

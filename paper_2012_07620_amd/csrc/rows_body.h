@@ -99,12 +99,13 @@ __device__ __forceinline__ void prep_row(const void* __restrict__ x, int i, int 
 // The row's own column gets the largest key, so it is always member 0.
 // ASC (the ranking list of Algorithm 1): the K smallest values of the row,
 // ties to the lower column, no forced self member; oval may be null.
-template <int R, bool ASC = false>
-__device__ __forceinline__ void topk_row(const float* __restrict__ S, int64_t ldS, int N, int i, int K,
+template <int R, bool ASC = false, typename T = float>
+__device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, int N, int i, int K,
                                          int32_t* __restrict__ oidx, float* __restrict__ oval, int ldo,
                                          uint64_t* ring) {
+  static_assert(!ASC || sizeof(T) == 4, "distance rows are FP32");
   const int lane = threadIdx.x & 63;
-  const float* srow = S + (int64_t)i * ldS;
+  const T* srow = S + (int64_t)i * ldS;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
 
   uint64_t best[R];
@@ -120,8 +121,12 @@ __device__ __forceinline__ void topk_row(const float* __restrict__ S, int64_t ld
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int col = c0 + u * 256 + lane * 4;
-      if (!ASC) {  // S rows: 256-byte aligned, padded to a multiple of 64 columns
+      if (!ASC && sizeof(T) == 4) {  // S rows: 256-byte aligned, padded to a multiple of 64 columns
         v[u] = (col < N) ? *(const f32x4*)(srow + col) : f32x4{0.f, 0.f, 0.f, 0.f};
+      } else if (!ASC) {  // binary16 S rows, same padding
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        const h4 hv = (col < N) ? *(const h4*)(srow + col) : h4{0, 0, 0, 0};
+        v[u] = f32x4{(float)hv.x, (float)hv.y, (float)hv.z, (float)hv.w};
       } else {  // caller's distance rows: any stride, no padding
 #pragma unroll
         for (int e = 0; e < 4; e++) v[u][e] = (col + e < N) ? srow[col + e] : 0.f;
