@@ -157,15 +157,16 @@ hipError_t launch_propagate_gated(const float* hin, const float* sin, int n, int
 // Ranking list: per row of D (q rows, stride g), the r smallest positions in
 // ascending order, ties to the lower position (r <= 256).
 hipError_t launch_rank(const float* D, int q, int g, int r, int32_t* out, hipStream_t s);
-// a7, sparse form: D[q][g] = 1 - sq[q] * sg[g] * <h_q, h_{Q+g}> from the
-// non-zeros of H (n rows, row stride ld, columns < ld). `pool` (pool_bytes,
-// must not overlap H) holds the compacted rows; `ints` holds
-// sparse_final_ints(n, ld) int32 of counters. When the non-zeros exceed
-// pool_bytes / 16 the FP32 matrix-core product computes D instead (decided on
-// the device). D is q x (n - q), row stride n - q.
-// With `lay` (the gate and rows of the last sparse layer, H then being that
-// layer's buffer): when the gate is sparse the CSR rows are used as they are
-// and only the column layout goes into `pool`.
+// a7, sparse form: D[q][g] = 1 - sq[q] * <h_q, sg[g] h_{Q+g}> from the
+// non-zeros of H (n rows, row stride ld, columns < ld; sigma = sq then sg).
+// `pool` (pool_bytes, must not overlap H) holds the compacted rows and the
+// gallery's column layout; `ints` holds sparse_final_ints(n, ld) int32 of
+// counters, offsets and the queries' cluster order (from knn, n x k1). When
+// the compacted rows exceed pool_bytes / 16 the FP32 matrix-core product
+// computes D instead (decided on the device). D is q x (n - q), row stride
+// n - q. With `lay` (the gate and rows of the last sparse layer, H then being
+// that layer's buffer): when the gate is sparse the CSR rows are used as they
+// are and only the column layout goes into `pool`.
 constexpr int kSparseChunk = 16384;  // gallery accumulators per pass of the sparse product
 inline int64_t sparse_chunks(int64_t n) { return (n + kSparseChunk - 1) / kSparseChunk; }
 // column buckets: (gallery chunk, quarter of the chunk, column)
@@ -177,7 +178,6 @@ inline int64_t sparse_final_head(int64_t n, int64_t ld) {
 inline int64_t sparse_final_ints(int64_t n, int64_t ld) {
   return sparse_final_head(n, ld) + cluster_order_ints(n, n) + n;  // + the queries' cluster order
 }
-// knn (n x k1, the kNN lists) orders the queries by cluster.
 hipError_t launch_sparse_final(const float* H, int n, int q, int64_t ld, const float* sigma, float* dist, void* pool,
                                int64_t pool_bytes, int32_t* ints, const SlGate* lay_gate, const SlRows* lay,
                                const int32_t* knn, int k1, hipStream_t s);
