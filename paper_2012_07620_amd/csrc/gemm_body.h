@@ -24,13 +24,11 @@ namespace rr {
 constexpr int BM = 128, BN = 128, BKB = 128, LDSR = BKB + 16, TILEB = BM * LDSR;
 constexpr int GEMM_LDS_BYTES = 4 * TILEB;  // 73728: two stage buffers, or one + the mirror-tile staging
 constexpr int GEMM_LDS_1BUF = 2 * TILEB;   // 36864: one stage buffer (EPI_DIST)
-constexpr int TSTRIDE = BM + 1;            // transposed-tile LDS row stride (floats)
-static_assert(BN * TSTRIDE * 4 <= GEMM_LDS_BYTES, "transpose staging must fit the GEMM LDS");
 
 enum { MODE_F32 = 0, MODE_BF16 = 1, MODE_FP8 = 2 };
 // EPI_SIM_SYM16: EPI_SIM_SYM storing S as IEEE binary16 (the low-precision
 // paths, whose S only ranks candidates that are then re-scored in FP32).
-enum { EPI_SIM = 0, EPI_DIST = 1, EPI_SIM_SYM = 2, EPI_SIM_SYM16 = 3 };
+enum { EPI_DIST = 1, EPI_SIM_SYM = 2, EPI_SIM_SYM16 = 3 };
 
 template <int MODE>
 __device__ __forceinline__ void mfma_stage(f32x16 (&acc)[2][2], const u32x4 (&a)[2][4], const u32x4 (&b)[2][4]) {
@@ -183,50 +181,95 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
 
   // 32x32 accumulator layout: register r of lane l holds
   // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of its block.
-  const bool mirror = (EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16) && (tm != tn);
-  _Float16* out16 = (_Float16*)g.out;  // EPI_SIM_SYM16: ldo counts halves
-  float* tr = (float*)lds;  // transposed staging, valid after the loop's last barrier
+  if constexpr (EPI == EPI_DIST) {
 #pragma unroll
-  for (int sm = 0; sm < 2; sm++)
+    for (int sm = 0; sm < 2; sm++)
 #pragma unroll
-    for (int sn = 0; sn < 2; sn++) {
-      const int lc = wn * 64 + sn * 32 + (lane & 31);
-      const int col = n0 + lc;
-      const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
+      for (int sn = 0; sn < 2; sn++) {
+        const int col = n0 + wn * 64 + sn * 32 + (lane & 31);
+        const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
 #pragma unroll
-      for (int r = 0; r < 16; r++) {
-        const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        const int row = m0 + lr;
-        const float v = acc[sm][sn][r];
-        if (EPI == EPI_DIST) {
-          if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = 1.0f - g.sa[row] * scol * v;
-        } else {
-          const float s = (row < g.M && col < g.Nn) ? v * g.sa[row] * scol + 0.0f : 0.f;
-          if (row < g.M && col < g.Nn) {
-            if (EPI == EPI_SIM_SYM16)
-              out16[(int64_t)row * g.ldo + col] = (_Float16)s;
-            else
-              g.out[(int64_t)row * g.ldo + col] = s;
-          }
-          if (mirror) tr[lc * TSTRIDE + lr] = s;
+        for (int r = 0; r < 16; r++) {
+          const int row = m0 + wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+          if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = 1.0f - g.sa[row] * scol * acc[sm][sn][r];
         }
       }
-    }
-  if (mirror) {
-    __syncthreads();
-    // rows n0.. of C^T: thread t writes columns t%128 of rows t/128, +2, ...
-    const int c = tid & 127;
-    for (int rr = tid >> 7; rr < BN; rr += 2) {
-      const int row = n0 + rr, col = m0 + c;
-      if (row < g.Nn && col < g.M) {
-        if (EPI == EPI_SIM_SYM16)
-          out16[(int64_t)row * g.ldo + col] = (_Float16)tr[rr * TSTRIDE + c];
-        else
-          g.out[(int64_t)row * g.ldo + col] = tr[rr * TSTRIDE + c];
+    __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
+  } else {
+    // Similarity: the scaled tile is staged row-major in LDS (free after the
+    // loop's last barrier), then written with 16-byte stores per lane: rows
+    // of the tile at (tm, tn) and, off the diagonal, rows of its transpose at
+    // (tn, tm) (lanes along the tile's columns, each gathering one 16-byte run
+    // of a transposed row). Zeros stand in outside M x Nn and are not stored.
+    constexpr bool H16 = (EPI == EPI_SIM_SYM16);
+    constexpr int TS = BN + 4;  // staged row stride (floats; 16-byte aligned rows)
+    static_assert(BM * TS * 4 <= GEMM_LDS_BYTES, "staged tile must fit the similarity LDS");
+    float* T = (float*)lds;
+#pragma unroll
+    for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+      for (int sn = 0; sn < 2; sn++) {
+        const int lc = wn * 64 + sn * 32 + (lane & 31);
+        const int col = n0 + lc;
+        const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+          const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+          const int row = m0 + lr;
+          T[lr * TS + lc] = (row < g.M && col < g.Nn) ? acc[sm][sn][r] * g.sa[row] * scol + 0.0f : 0.f;
+        }
       }
+    __syncthreads();
+    constexpr int V = H16 ? 8 : 4;        // elements per 16-byte store
+    constexpr int CPR = BN / V;           // 16-byte chunks per tile row
+    constexpr int RPP = 256 / CPR;        // tile rows per pass
+    _Float16* out16 = (_Float16*)g.out;   // EPI_SIM_SYM16: ldo counts halves
+    const bool vec = (((uintptr_t)g.out & 15) == 0) && (g.ldo % V == 0);
+    auto put = [&](int64_t row, int col0, int lim, const float* v) {  // V values at (row, col0..), cols < lim
+      if (vec && col0 + V <= lim) {
+        if constexpr (H16) {
+          typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+          h8 hv;
+#pragma unroll
+          for (int e = 0; e < 8; e++) hv[e] = (_Float16)v[e];
+          *(h8*)(out16 + row * g.ldo + col0) = hv;
+        } else {
+          *(f32x4*)(g.out + row * g.ldo + col0) = f32x4{v[0], v[1], v[2], v[3]};
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < V; e++)
+          if (col0 + e < lim) {
+            if constexpr (H16)
+              out16[row * g.ldo + col0 + e] = (_Float16)v[e];
+            else
+              g.out[row * g.ldo + col0 + e] = v[e];
+          }
+      }
+    };
+    // the tile: lanes along a row
+    for (int lr = tid / CPR; lr < BM; lr += RPP) {
+      const int row = m0 + lr;
+      if (row >= g.M) continue;
+      const int ch = tid % CPR;
+      float v[V];
+#pragma unroll
+      for (int e = 0; e < V; e++) v[e] = T[lr * TS + ch * V + e];
+      put(row, n0 + ch * V, g.Nn, v);
     }
+    if (tm != tn) {  // the transpose: lane = tile column, one V-run of tile rows each
+      const int lc = tid & 127;
+      const int row = n0 + lc;
+      if (row < g.Nn)
+        for (int ch = tid >> 7; ch < BM / V; ch += 2) {
+          float v[V];
+#pragma unroll
+          for (int e = 0; e < V; e++) v[e] = T[(ch * V + e) * TS + lc];
+          put(row, m0 + ch * V, g.M, v);
+        }
+    }
+    __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
   }
-  __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
 }
 
 // ---------------------------------------------------------------- bf16x3
