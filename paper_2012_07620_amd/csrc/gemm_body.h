@@ -28,7 +28,9 @@ constexpr int GEMM_LDS_1BUF = 2 * TILEB;   // 36864: one stage buffer (EPI_DIST)
 enum { MODE_F32 = 0, MODE_BF16 = 1, MODE_FP8 = 2 };
 // EPI_SIM_SYM16: EPI_SIM_SYM storing S as IEEE binary16 (the low-precision
 // paths, whose S only ranks candidates that are then re-scored in FP32).
-enum { EPI_DIST = 1, EPI_SIM_SYM = 2, EPI_SIM_SYM16 = 3 };
+// EPI_PART: no epilogue; the raw accumulators of a K range go to a 128 x 128
+// partial tile (g.out, tile-local layout) for a later fixed-order sum.
+enum { EPI_DIST = 1, EPI_SIM_SYM = 2, EPI_SIM_SYM16 = 3, EPI_PART = 4 };
 
 template <int MODE>
 __device__ __forceinline__ void mfma_stage(f32x16 (&acc)[2][2], const u32x4 (&a)[2][4], const u32x4 (&b)[2][4]) {
@@ -92,7 +94,9 @@ struct GemmArgs {
 // EPI_SIM_SYM / EPI_SIM_SYM16 (A == B, tm <= tn): also stores the mirrored
 // tile C^T, so only the upper triangle of tiles is computed.
 template <int MODE, int EPI, int NBUF = 1>
-__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uint8_t* lds) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uint8_t* lds, int st0 = 0,
+                                          int st1 = -1) {
+  if (st1 < 0) st1 = g.nst;  // K stages [st0, st1)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = tm * BM, n0 = tn * BN;
@@ -136,12 +140,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
   const int fb = (wn * 64 + (lane & 31)) * LDSR + (lane >> 5) * 64;
 
   if (NBUF == 2) {
-    gload(0);
+    gload(st0);
     lstore(0);
     __syncthreads();
-    for (int st = 0; st < g.nst; st++) {
-      const int buf = st & 1;
-      if (st + 1 < g.nst) gload(st + 1);
+    for (int st = st0; st < st1; st++) {
+      const int buf = (st - st0) & 1;
+      if (st + 1 < st1) gload(st + 1);
       const uint8_t* la = lds + buf * 2 * TILEB;
       const uint8_t* lb = la + TILEB;
       u32x4 a[2][4], b[2][4];
@@ -153,17 +157,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
           b[s][c] = *(const u32x4*)(lb + fb + s * 32 * LDSR + c * 16);
         }
       mfma_stage<MODE>(acc, a, b);
-      if (st + 1 < g.nst) lstore(buf ^ 1);
+      if (st + 1 < st1) lstore(buf ^ 1);
       __syncthreads();
     }
   } else {
     // one stage buffer, next stage prefetched into registers
-    gload(0);
-    for (int st = 0; st < g.nst; st++) {
-      if (st) __syncthreads();
+    gload(st0);
+    for (int st = st0; st < st1; st++) {
+      if (st > st0) __syncthreads();
       lstore(0);
       __syncthreads();
-      if (st + 1 < g.nst) gload(st + 1);
+      if (st + 1 < st1) gload(st + 1);
       const uint8_t* la = lds;
       const uint8_t* lb = la + TILEB;
       u32x4 a[2][4], b[2][4];
@@ -181,7 +185,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
 
   // 32x32 accumulator layout: register r of lane l holds
   // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of its block.
-  if constexpr (EPI == EPI_DIST) {
+  if constexpr (EPI == EPI_PART) {
+#pragma unroll
+    for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+      for (int sn = 0; sn < 2; sn++)
+#pragma unroll
+        for (int r = 0; r < 16; r++) g.out[((sm * 2 + sn) * 16 + r) * 256 + tid] = acc[sm][sn][r];
+    __syncthreads();
+  } else if constexpr (EPI == EPI_DIST) {
 #pragma unroll
     for (int sm = 0; sm < 2; sm++)
 #pragma unroll
@@ -270,6 +282,30 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
     }
     __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
   }
+}
+
+// Tail tile (tm, tn) of EPI_DIST computed as `parts` K ranges: sum the EPI_PART
+// partial tiles in range order, then the EPI_DIST epilogue.
+__device__ __forceinline__ void gemm_fix_tile(const GemmArgs& g, int tm, int tn, const float* __restrict__ part,
+                                              int parts) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = tm * BM, n0 = tn * BN;
+#pragma unroll
+  for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+    for (int sn = 0; sn < 2; sn++) {
+      const int col = n0 + wn * 64 + sn * 32 + (lane & 31);
+      const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
+#pragma unroll 4
+      for (int r = 0; r < 16; r++) {
+        const int at = ((sm * 2 + sn) * 16 + r) * 256 + tid;
+        float v = part[at];
+        for (int k = 1; k < parts; k++) v += part[(int64_t)k * BM * BN + at];
+        const int row = m0 + wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = 1.0f - g.sa[row] * scol * v;
+      }
+    }
 }
 
 // ---------------------------------------------------------------- bf16x3

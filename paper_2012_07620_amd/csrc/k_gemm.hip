@@ -68,9 +68,79 @@ hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes
   return hipErrorInvalidValue;
 }
 
+// Tail of the FP32 final product split along K. Tiles run in rounds of
+// `slots` resident workgroups; when the last round is partly empty, its tiles
+// (logical tiles first..tiles-1) are computed as `parts` K ranges each
+// (gemm_part_kernel, partial tiles in `ws`) and summed in range order by
+// gemm_fix_kernel, which applies the epilogue. Fixed ranges and order: the
+// result is deterministic.
+__global__ __launch_bounds__(256) void gemm_part_kernel(GemmArgs g, int tiles_m, int tiles_n, int first, int parts,
+                                                        float* __restrict__ ws) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[GEMM_LDS_1BUF];
+  const int w = xcd_linear(blockIdx.x, gridDim.x);
+  const int k = w % parts;
+  const TileMap t = grouped_order(first + w / parts, tiles_m, tiles_n);
+  GemmArgs gp = g;
+  gp.out = ws + (int64_t)((w / parts) * parts + k) * BM * BN;
+  gemm_tile<MODE_F32, EPI_PART>(gp, t.tm, t.tn, lds, (int)((int64_t)k * g.nst / parts),
+                                (int)((int64_t)(k + 1) * g.nst / parts));
+}
+
+__global__ __launch_bounds__(256) void gemm_fix_kernel(GemmArgs g, int tiles_m, int tiles_n, int first, int parts,
+                                                       const float* __restrict__ ws) {
+  const int w = blockIdx.x;
+  const TileMap t = grouped_order(first + w, tiles_m, tiles_n);
+  gemm_fix_tile(g, t.tm, t.tn, ws + (int64_t)w * parts * BM * BN, parts);
+}
+
+// Resident workgroups of the FP32 final product (queried once per process,
+// on the device current at the first call; thread-safe initialisation).
+static int dist_slots() {
+  static const int slots = [] {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)gemm_nt_kernel<MODE_F32, EPI_DIST>, 256,
+                                                     0) != hipSuccess)
+      return 0;
+    return cus * per;
+  }();
+  return slots;
+}
+
 hipError_t launch_gemm_dist(const float* a, int M, const float* b, int Nn, int64_t ld_elems, int64_t kelems,
-                            const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s) {
-  return launch_gemm_t<MODE_F32, EPI_DIST>(a, M, ld_elems * 4, b, Nn, ld_elems * 4, kelems * 4, sa, sb, out, ldo, s);
+                            const float* sa, const float* sb, float* out, int64_t ldo, float* ws, int64_t ws_bytes,
+                            hipStream_t s) {
+  const int tm = (M + BM - 1) / BM, tn = (Nn + BN - 1) / BN;
+  const int64_t tiles = (int64_t)tm * tn;
+  const int slots = ws ? dist_slots() : 0;
+  const int nst = (int)(kelems * 4 / BKB);
+  int parts = 1;
+  int64_t rem = 0;
+  if (slots > 0 && tiles > slots && kelems * 4 % BKB == 0) {
+    rem = tiles % slots;
+    // K ranges per tail tile: the fewest partial rounds per tile, needing a
+    // saving of at least a fifth of a round
+    double best = 1.0;
+    for (int p = 2; p <= 8; p++) {
+      const double cost = (double)((rem * p + slots - 1) / slots) / p;
+      if (cost < best - 1e-9 && nst >= 8 * p && rem * p * BM * BN * 4 <= ws_bytes) {
+        best = cost;
+        parts = p;
+      }
+    }
+    if (best > 0.8) parts = 1;
+  }
+  if (parts == 1 || rem == 0)
+    return launch_gemm_t<MODE_F32, EPI_DIST>(a, M, ld_elems * 4, b, Nn, ld_elems * 4, kelems * 4, sa, sb, out, ldo, s);
+  if (tiles > 0x7FFFFFFF || rem * parts > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const int64_t first = tiles - rem;
+  GemmArgs g{(const uint8_t*)a, (const uint8_t*)b, M, Nn, ld_elems * 4, ld_elems * 4, nst, sa, sb, out, ldo};
+  hipLaunchKernelGGL((gemm_nt_kernel<MODE_F32, EPI_DIST>), dim3((unsigned)first), dim3(256), 0, s, g, tm, tn);
+  hipLaunchKernelGGL(gemm_part_kernel, dim3((unsigned)(rem * parts)), dim3(256), 0, s, g, tm, tn, (int)first, parts, ws);
+  hipLaunchKernelGGL(gemm_fix_kernel, dim3((unsigned)rem), dim3(256), 0, s, g, tm, tn, (int)first, parts,
+                     (const float*)ws);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void gemm_x3_kernel(GemmX3Args g, int tiles_m, int tiles_n) {

@@ -68,8 +68,11 @@ hipError_t launch_prep(const void* x, int in_bf16, int n, int d, float* xp, int6
 hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes,
                            const float* sa, void* out, int64_t ldo, bool half_out, hipStream_t s);
 // Final epilogue: out[q][g] = 1 - sa[q] * sb[g] * acc, ldo floats.
+// Final product, D = 1 - sa[i] * sb[j] * acc. ws (ws_bytes, may be null):
+// scratch for splitting the last, partly filled round of tiles along K.
 hipError_t launch_gemm_dist(const float* a, int M, const float* b, int Nn, int64_t ld_elems, int64_t kelems,
-                            const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s);
+                            const float* sa, const float* sb, float* out, int64_t ldo, float* ws, int64_t ws_bytes,
+                            hipStream_t s);
 hipError_t launch_gemm_dist_bf16x3(const uint16_t* a_hi, const uint16_t* a_lo, int M, const uint16_t* b_hi,
                                    const uint16_t* b_lo, int Nn, int64_t ld_elems, int64_t kelems,
                                    const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s);

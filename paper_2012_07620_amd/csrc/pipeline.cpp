@@ -221,7 +221,12 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
   const float* hq = cur;
   const float* hg = cur + (size_t)P.q * P.ldH;
   if (P.fprec == FinalPrec::F32) {
-    RR_TRY(launch_gemm_dist(hq, P.q, hg, P.g, P.ldH, P.ldH, csig, csig + P.q, dist, P.g, s));
+    // scratch for the tail split: whichever N x N buffer does not hold the last layer
+    float* spare = (cur != A) ? A : B;
+    const int64_t spare_bytes = !spare ? 0
+                                : (spare == A) ? (int64_t)P.n * (P.ldN > P.ldH ? P.ldN : P.ldH) * 4
+                                               : (int64_t)P.n * P.ldH * 4;
+    RR_TRY(launch_gemm_dist(hq, P.q, hg, P.g, P.ldH, P.ldH, csig, csig + P.q, dist, P.g, spare, spare_bytes, s));
   } else if (P.fprec == FinalPrec::SPARSE) {  // adjacency features: cur is A or B, the other one is free
     float* pool = (cur == A) ? B : A;
     if (P.sparse_layers) {
