@@ -416,19 +416,32 @@ __device__ __forceinline__ void gemm_tile_x3(const GemmX3Args& g, int tm, int tn
   __syncthreads();
 }
 
-// Upper-triangle tile t (0 <= t < T(T+1)/2) of a T x T tile grid, row-major
-// over tm: (0,0),(0,1)..(0,T-1),(1,1),...
+// Upper-triangle tile t (0 <= t < T(T+1)/2) of a T x T tile grid. Tile rows
+// are taken in bands of 8; a band's tiles are listed column by column
+// (tn ascending, the band's rows with tm <= tn inside a column), so the
+// workgroups resident on one XCD at a time cover a few columns of one band and
+// share its 8 row blocks and their column blocks in that XCD's L2.
 __device__ __forceinline__ void upper_tile(int t, int T, int& tm, int& tn) {
-  // rows before tm hold tm*T - tm*(tm-1)/2 tiles; invert with a float guess, then fix up
-  float b = 2.f * T + 1.f;
-  int m = (int)((b - __builtin_sqrtf(b * b - 8.f * (float)t)) * 0.5f);
-  if (m < 0) m = 0;
-  if (m > T - 1) m = T - 1;
-  auto first = [&](int mm) { return mm * T - mm * (mm - 1) / 2; };
-  while (m > 0 && first(m) > t) m--;
-  while (m + 1 < T && first(m + 1) <= t) m++;
-  tm = m;
-  tn = m + (t - first(m));
+  constexpr int G = 8;
+  for (int r0 = 0;; r0 += G) {
+    const int gs = min(G, T - r0), r1 = r0 + gs;
+    const int head = gs * (gs + 1) / 2;  // columns r0..r1-1: the band's own triangle
+    const int cnt = head + gs * (T - r1);
+    if (t < cnt || r1 >= T) {
+      if (t < head) {
+        int j = 0;
+        while ((j + 1) * (j + 2) / 2 <= t) j++;
+        tm = r0 + (t - j * (j + 1) / 2);
+        tn = r0 + j;
+      } else {
+        const int u = t - head;
+        tn = r1 + u / gs;
+        tm = r0 + u % gs;
+      }
+      return;
+    }
+    t -= cnt;
+  }
 }
 
 }  // namespace rr
