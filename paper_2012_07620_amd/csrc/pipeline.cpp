@@ -221,8 +221,9 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
   const float* hq = cur;
   const float* hg = cur + (size_t)P.q * P.ldH;
   if (P.fprec == FinalPrec::F32) {
-    // scratch for the tail split: whichever N x N buffer does not hold the last layer
-    float* spare = (cur != A) ? A : B;
+    // scratch for the tail split: whichever N x N buffer does not hold the last
+    // layer; none (no split) for problems the serving path batches
+    float* spare = P.n <= kGroupedMaxN ? nullptr : (cur != A) ? A : B;
     const int64_t spare_bytes = !spare ? 0
                                 : (spare == A) ? (int64_t)P.n * (P.ldN > P.ldH ? P.ldN : P.ldH) * 4
                                                : (int64_t)P.n * P.ldH * 4;

@@ -13,6 +13,10 @@ namespace rr {
 constexpr int kMaxCand = 256;   // k1 + extra candidates held by one wavefront
 constexpr int kMaxLayers = 256; // Table 2 goes up to 256 layers
 constexpr int kMaxAlpha = 8;
+// Problems up to this size are batched by the serving path's grouped launches;
+// the direct path computes them with the same tile work (no split tail), so a
+// request's result does not depend on which path ran it.
+constexpr int kGroupedMaxN = 8192;
 
 struct Plan {
   int n = 0, q = 0, g = 0, d = 0, k1 = 0, k2 = 0, layers = 0, alpha = 0, kc = 0;

@@ -7,7 +7,7 @@
 // context budget, so requests that arrive while others run start as slots
 // and memory free up, and their kernels overlap on the device.
 //
-// Small problems (N <= kSmallN) are gathered into batches of up to kMaxBatch
+// Small problems (N <= kGroupedMaxN) are gathered into batches of up to kMaxBatch
 // requests with the same batch key and run as one persistent grouped launch
 // per stage. Each slot captures that launch sequence (table copy from pinned
 // host memory + one launch per stage) into a hipGraph per key once, and a
@@ -33,7 +33,6 @@
 namespace rr {
 
 constexpr int kSlots = 4;
-constexpr int kSmallN = 8192;
 
 using Clock = std::chrono::steady_clock;
 
@@ -192,7 +191,7 @@ class Server {
     r->in_bf16 = in_bf16;
     r->dist = dist;
     r->ws_bytes = r->plan.total;
-    r->small = p->n <= kSmallN && r->plan.rescore && r->plan.fprec == FinalPrec::F32;
+    r->small = p->n <= kGroupedMaxN && r->plan.rescore && r->plan.fprec == FinalPrec::F32;
     r->key = BatchKey{(int)r->plan.prec, r->plan.kc <= 64 ? 1 : (r->plan.kc <= 128 ? 2 : 4), p->layers, p->node,
                       p->aggregator};
     r->t_submit = Clock::now();
