@@ -86,45 +86,56 @@ struct GemmArgs {
   int64_t ldo;  // floats
 };
 
-// One 128 x 128 output tile (tm, tn). Uses `lds` (GEMM_LDS_1BUF bytes for
-// NBUF = 1 with EPI_DIST, else GEMM_LDS_BYTES) and block barriers: every
-// thread of the workgroup must call it with the same tile. NBUF = 1 keeps one
-// LDS stage and prefetches the next into registers (more workgroups per CU;
-// measured faster than NBUF = 2 double buffering on the 19281-row problem).
-// EPI_SIM_SYM / EPI_SIM_SYM16 (A == B, tm <= tn): also stores the mirrored
-// tile C^T, so only the upper triangle of tiles is computed.
-template <int MODE, int EPI, int NBUF = 1>
+// LDS bytes of one stage buffer pair (A and B) holding KS 128-byte K slices.
+__host__ __device__ constexpr int gemm_stage_lds(int ks) { return 2 * BM * (ks * BKB + 16); }
+
+// One 128 x 128 output tile (tm, tn). Uses `lds` (gemm_stage_lds(KS) bytes for
+// NBUF = 1 with EPI_DIST / EPI_PART, else GEMM_LDS_BYTES) and block barriers:
+// every thread of the workgroup must call it with the same tile. NBUF = 1
+// keeps one LDS stage and prefetches the next into registers (more workgroups
+// per CU; measured faster than NBUF = 2 double buffering on the 19281-row
+// problem). KS 128-byte K slices share one LDS stage (one barrier pair per
+// KS slices; the similarity's mirror staging fits in the same LDS); the K
+// range [st0, st1), counted in slices, must then be whole stages. EPI_SIM_SYM / EPI_SIM_SYM16 (A == B, tm <= tn): also stores the
+// mirrored tile C^T, so only the upper triangle of tiles is computed.
+template <int MODE, int EPI, int NBUF = 1, int KS = 1>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uint8_t* lds, int st0 = 0,
                                           int st1 = -1) {
-  if (st1 < 0) st1 = g.nst;  // K stages [st0, st1)
+  static_assert(KS == 1 || (NBUF == 1 && gemm_stage_lds(KS) <= GEMM_LDS_BYTES), "wide stages: one buffer");
+  constexpr int SB = KS * BKB;      // bytes per row per LDS stage
+  constexpr int LR = SB + 16;       // padded LDS row
+  constexpr int TB = BM * LR;       // one operand's stage
+  constexpr int CH = SB / 16;       // 16-byte chunks per row per stage
+  constexpr int NL = BM * CH / 256; // 16-byte loads per thread per operand
+  if (st1 < 0) st1 = g.nst;  // K slices [st0, st1)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = tm * BM, n0 = tn * BN;
 
-  const uint8_t* pa[4];
-  const uint8_t* pb[4];
-  int ls[4];
+  const uint8_t* pa[NL];
+  const uint8_t* pb[NL];
+  int ls[NL];
 #pragma unroll
-  for (int u = 0; u < 4; u++) {
-    const int f = u * 256 + tid, row = f >> 3, c = f & 7;
+  for (int u = 0; u < NL; u++) {
+    const int f = u * 256 + tid, row = f / CH, c = f % CH;
     pa[u] = g.A + (int64_t)min(m0 + row, g.M - 1) * g.lda + c * 16;
     pb[u] = g.B + (int64_t)min(n0 + row, g.Nn - 1) * g.ldb + c * 16;
-    ls[u] = row * LDSR + c * 16;
+    ls[u] = row * LR + c * 16;
   }
-  u32x4 ra[4], rb[4];
+  u32x4 ra[NL], rb[NL];
   auto gload = [&](int st) {
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
+    for (int u = 0; u < NL; u++) {
       ra[u] = *(const u32x4*)(pa[u] + (int64_t)st * BKB);
       rb[u] = *(const u32x4*)(pb[u] + (int64_t)st * BKB);
     }
   };
   auto lstore = [&](int buf) {
-    uint8_t* base = lds + buf * 2 * TILEB;
+    uint8_t* base = lds + buf * 2 * TB;
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
+    for (int u = 0; u < NL; u++) {
       *(u32x4*)(base + ls[u]) = ra[u];
-      *(u32x4*)(base + TILEB + ls[u]) = rb[u];
+      *(u32x4*)(base + TB + ls[u]) = rb[u];
     }
   };
 
@@ -136,8 +147,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[sm][sn][r] = 0.f;
 
-  const int fa = (wm * 64 + (lane & 31)) * LDSR + (lane >> 5) * 64;
-  const int fb = (wn * 64 + (lane & 31)) * LDSR + (lane >> 5) * 64;
+  const int fa = (wm * 64 + (lane & 31)) * LR + (lane >> 5) * 64;
+  const int fb = (wn * 64 + (lane & 31)) * LR + (lane >> 5) * 64;
 
   if (NBUF == 2) {
     gload(st0);
@@ -146,15 +157,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
     for (int st = st0; st < st1; st++) {
       const int buf = (st - st0) & 1;
       if (st + 1 < st1) gload(st + 1);
-      const uint8_t* la = lds + buf * 2 * TILEB;
-      const uint8_t* lb = la + TILEB;
+      const uint8_t* la = lds + buf * 2 * TB;
+      const uint8_t* lb = la + TB;
       u32x4 a[2][4], b[2][4];
 #pragma unroll
       for (int s = 0; s < 2; s++)
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-          a[s][c] = *(const u32x4*)(la + fa + s * 32 * LDSR + c * 16);
-          b[s][c] = *(const u32x4*)(lb + fb + s * 32 * LDSR + c * 16);
+          a[s][c] = *(const u32x4*)(la + fa + s * 32 * LR + c * 16);
+          b[s][c] = *(const u32x4*)(lb + fb + s * 32 * LR + c * 16);
         }
       mfma_stage<MODE>(acc, a, b);
       if (st + 1 < st1) lstore(buf ^ 1);
@@ -163,22 +174,25 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
   } else {
     // one stage buffer, next stage prefetched into registers
     gload(st0);
-    for (int st = st0; st < st1; st++) {
+    for (int st = st0; st < st1; st += KS) {
       if (st > st0) __syncthreads();
       lstore(0);
       __syncthreads();
-      if (st + 1 < st1) gload(st + 1);
+      if (st + KS < st1) gload(st + KS);
       const uint8_t* la = lds;
-      const uint8_t* lb = la + TILEB;
-      u32x4 a[2][4], b[2][4];
+      const uint8_t* lb = la + TB;
 #pragma unroll
-      for (int s = 0; s < 2; s++)
+      for (int q = 0; q < KS; q++) {
+        u32x4 a[2][4], b[2][4];
 #pragma unroll
-        for (int c = 0; c < 4; c++) {
-          a[s][c] = *(const u32x4*)(la + fa + s * 32 * LDSR + c * 16);
-          b[s][c] = *(const u32x4*)(lb + fb + s * 32 * LDSR + c * 16);
-        }
-      mfma_stage<MODE>(acc, a, b);
+        for (int s = 0; s < 2; s++)
+#pragma unroll
+          for (int c = 0; c < 4; c++) {
+            a[s][c] = *(const u32x4*)(la + fa + s * 32 * LR + q * BKB + c * 16);
+            b[s][c] = *(const u32x4*)(lb + fb + s * 32 * LR + q * BKB + c * 16);
+          }
+        mfma_stage<MODE>(acc, a, b);
+      }
     }
     __syncthreads();
   }

@@ -22,10 +22,18 @@ __device__ __forceinline__ TileMap grouped_order(int pid, int tiles_m, int tiles
   return TileMap{first_m + in % gsz, in / gsz};
 }
 
+// 128-byte K slices per LDS stage. The final product's K (the padded N x N
+// row stride) is whole 256-byte stages: two slices halve its barrier pairs
+// (15.6 -> 15.2 ms at N = 19281). The similarity keeps one (two measured no
+// faster: its 2048-element K leaves few stages per tile).
+constexpr int DIST_KS = 2;
+constexpr int SIM_KS = 1;
+
 template <int MODE, int EPI>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   constexpr bool SYM = EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16;
-  __shared__ __attribute__((aligned(16))) uint8_t lds[SYM ? GEMM_LDS_BYTES : GEMM_LDS_1BUF];
+  constexpr int KS = EPI == EPI_DIST ? DIST_KS : SYM ? SIM_KS : 1;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[SYM ? GEMM_LDS_BYTES : gemm_stage_lds(KS)];
   const int pid = xcd_linear(blockIdx.x, gridDim.x);
   int tm, tn;
   if (SYM) {
@@ -35,7 +43,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g, int tiles_m, i
     tm = t.tm;
     tn = t.tn;
   }
-  gemm_tile<MODE, EPI>(g, tm, tn, lds);
+  gemm_tile<MODE, EPI, 1, KS>(g, tm, tn, lds);
 }
 
 template <int MODE, int EPI>
@@ -43,7 +51,8 @@ static hipError_t launch_gemm_t(const void* a, int M, int64_t lda, const void* b
                                 const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s) {
   const int tm = (M + BM - 1) / BM, tn = (Nn + BN - 1) / BN;
   const int64_t nwg = (EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16) ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tm * tn;
-  if (nwg <= 0 || nwg > 0x7FFFFFFF || kbytes % BKB || kbytes <= 0) return hipErrorInvalidValue;
+  constexpr int KS = EPI == EPI_DIST ? DIST_KS : (EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16) ? SIM_KS : 1;
+  if (nwg <= 0 || nwg > 0x7FFFFFFF || kbytes % (BKB * KS) || kbytes <= 0) return hipErrorInvalidValue;
   GemmArgs g{(const uint8_t*)a, (const uint8_t*)b, M, Nn, lda, ldb, (int)(kbytes / BKB), sa, sb, out, ldo};
   hipLaunchKernelGGL((gemm_nt_kernel<MODE, EPI>), dim3((unsigned)nwg), dim3(256), 0, s, g, tm, tn);
   return hipGetLastError();
@@ -76,14 +85,15 @@ hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes
 // result is deterministic.
 __global__ __launch_bounds__(256) void gemm_part_kernel(GemmArgs g, int tiles_m, int tiles_n, int first, int parts,
                                                         float* __restrict__ ws) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[GEMM_LDS_1BUF];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[gemm_stage_lds(DIST_KS)];
   const int w = xcd_linear(blockIdx.x, gridDim.x);
   const int k = w % parts;
   const TileMap t = grouped_order(first + w / parts, tiles_m, tiles_n);
   GemmArgs gp = g;
   gp.out = ws + (int64_t)((w / parts) * parts + k) * BM * BN;
-  gemm_tile<MODE_F32, EPI_PART>(gp, t.tm, t.tn, lds, (int)((int64_t)k * g.nst / parts),
-                                (int)((int64_t)(k + 1) * g.nst / parts));
+  const int64_t nsk = g.nst / DIST_KS;  // whole LDS stages
+  gemm_tile<MODE_F32, EPI_PART, 1, DIST_KS>(gp, t.tm, t.tn, lds, (int)(k * nsk / parts * DIST_KS),
+                                            (int)((k + 1) * nsk / parts * DIST_KS));
 }
 
 __global__ __launch_bounds__(256) void gemm_fix_kernel(GemmArgs g, int tiles_m, int tiles_n, int first, int parts,
@@ -115,6 +125,7 @@ hipError_t launch_gemm_dist(const float* a, int M, const float* b, int Nn, int64
   const int64_t tiles = (int64_t)tm * tn;
   const int slots = ws ? dist_slots() : 0;
   const int nst = (int)(kelems * 4 / BKB);
+  if (nst % DIST_KS) return hipErrorInvalidValue;  // K is padded to whole LDS stages
   int parts = 1;
   int64_t rem = 0;
   if (slots > 0 && tiles > slots && kelems * 4 % BKB == 0) {

@@ -42,7 +42,7 @@ struct SlOut {
 inline int64_t scan_parts(int64_t n) { return (n + 1023) / 1024 + 1; }
 
 // Row stride (elements) of the padded K-major copies the GEMMs read: every
-// row is a whole number of 128-byte stages.
+// row is a whole number of 128-byte K slices.
 inline int64_t pad_k_elems(int64_t d, int bytes_per_elem) {
   const int64_t per = 128 / bytes_per_elem;
   return (d + per - 1) / per * per;
