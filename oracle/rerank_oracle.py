@@ -43,6 +43,22 @@ Readings taken where the paper is silent (each is also the GPU library's):
       messages e_ij^alpha h_j; the residual h_i is added in every case.
   R12 the ranking list L of Algorithm 1: per query, gallery rows by
       ascending distance, ties to the lower gallery index.
+
+Retrieval metrics (Section 4.1, Evaluation Metrics), applied to synthetic
+identity labels: the true matches of a query are the gallery rows carrying
+its label.
+  R13 AP is the area under the query's precision-recall curve taken over the
+      ranking list R12 with the trapezoid rule: the curve starts at recall 0,
+      precision 1, and every list position adds a point (recall, precision)
+      of the list's prefix up to it. With P true matches, the i-th (0-based)
+      at list position r_i contributes (1/P) * (p_before + p_at) / 2, where
+      p_at = (i+1)/(r_i+1) and p_before = i/r_i (1 when r_i = 0); positions
+      that are not true matches add no area. mAP is the mean AP over the
+      queries with at least one true match.
+  R14 Recall@K is 1 for a query whose first true match is among the first K
+      positions of its list, else 0; averaged over the queries with at least
+      one true match. No junk or same-camera filtering (the synthetic data
+      has neither).
 """
 from __future__ import annotations
 
@@ -57,6 +73,7 @@ __all__ = [
     "unit_rows", "similarity_rows", "knn_of_row", "knn_lists", "adjacency",
     "symmetric_adjacency", "edge_weights", "initial_features", "propagate",
     "row_norms", "distances", "rerank", "ranking", "Graph", "OracleResult",
+    "average_precision", "evaluate",
 ]
 
 
@@ -272,3 +289,43 @@ def rerank(x: np.ndarray, n_query: int, k1: int, k2: int, layers: int,
     w = edge_weights(g.idx, g.val, k2, alpha)
     h = propagate(h0, w, layers, aggregator=aggregator)
     return OracleResult(g, h, distances(h, n_query, q_rows, g_rows))
+
+
+def average_precision(dist_row: np.ndarray, match: np.ndarray):
+    """AP of one query (reading R13) and the list position of its first true
+    match (-1 without matches). ``match`` flags the true matches among the
+    gallery positions of ``dist_row``."""
+    order = np.argsort(np.asarray(dist_row, dtype=np.float64), kind="stable")
+    hits = np.asarray(match, dtype=bool)[order]
+    p = int(hits.sum())
+    if p == 0:
+        return 0.0, -1
+    ap = 0.0
+    i = 0  # true matches before the current position
+    for r in np.flatnonzero(hits):
+        p_before = 1.0 if r == 0 else i / r
+        p_at = (i + 1) / (r + 1)
+        ap += (1.0 / p) * (p_before + p_at) / 2.0
+        i += 1
+    return ap, int(np.flatnonzero(hits)[0])
+
+
+def evaluate(dist: np.ndarray, q_labels, g_labels, ks: Iterable[int] = (1, 5, 10)) -> dict:
+    """mAP and Recall@K of a query x gallery distance matrix (Section 4.1,
+    readings R13-R14). Returns per-query ``ap`` and ``first`` (list position
+    of the first true match, -1 without one) and the means over the queries
+    that have a true match."""
+    dist = np.asarray(dist)
+    q_labels = np.asarray(q_labels)
+    g_labels = np.asarray(g_labels)
+    ks = [int(k) for k in ks]
+    ap = np.zeros(dist.shape[0])
+    first = np.full(dist.shape[0], -1, dtype=np.int64)
+    for q in range(dist.shape[0]):
+        ap[q], first[q] = average_precision(dist[q], g_labels == q_labels[q])
+    valid = first >= 0
+    nv = int(valid.sum())
+    out = {"ap": ap, "first": first, "queries": nv,
+           "map": float(ap[valid].mean()) if nv else 0.0,
+           "recall": {k: (float((first[valid] < k).mean()) if nv else 0.0) for k in ks}}
+    return out

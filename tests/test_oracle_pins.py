@@ -344,3 +344,115 @@ def test_mean_is_sum_with_scaled_messages():
     a = orc.propagate(h0, w, 2, aggregator="mean").toarray()
     b = orc.propagate(h0, (w / 4.0).tocsr(), 2, aggregator="sum").toarray()
     np.testing.assert_allclose(a, b, atol=1e-14)
+
+
+# ---- retrieval metrics (Section 4.1, Evaluation Metrics; readings R13-R14)
+
+def test_ap_of_one_true_match_at_each_position():
+    # closed form: one true match at list position r has precision 1/(r+1)
+    # there and 0 just before it (1 before the first position), so the
+    # trapezoid over its recall step 0 -> 1 is 1 for r = 0, else 1/(2(r+1))
+    g = 9
+    dist = np.arange(g, dtype=np.float64)[::-1].copy()  # list order: positions g-1, ..., 0
+    for r in range(g):
+        match = np.zeros(g, dtype=bool)
+        match[g - 1 - r] = True
+        ap, first = orc.average_precision(dist, match)
+        assert first == r
+        assert ap == pytest.approx(1.0 if r == 0 else 1.0 / (2 * (r + 1)), abs=1e-15)
+
+
+def test_ap_of_two_true_matches_closed_form():
+    # matches at list positions r0 < r1: (1/2) * [(p_before0 + 1/(r0+1))/2 + (1/r1 + 2/(r1+1))/2]
+    for r0, r1 in [(0, 1), (0, 4), (2, 3), (1, 6)]:
+        d = np.arange(8.0)
+        m = np.zeros(8, dtype=bool)
+        m[[r0, r1]] = True
+        pb0 = 1.0 if r0 == 0 else 0.0
+        expect = 0.5 * ((pb0 + 1 / (r0 + 1)) / 2 + (1 / r1 + 2 / (r1 + 1)) / 2)
+        assert orc.average_precision(d, m)[0] == pytest.approx(expect, abs=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ap_is_the_area_under_the_whole_precision_recall_polyline(seed):
+    # a second formulation: precision and recall after every list position,
+    # the polyline from (0, 1) through all of them, integrated by np.trapezoid
+    rng = np.random.default_rng(seed)
+    for _ in range(40):
+        g = int(rng.integers(1, 60))
+        dist = rng.integers(0, 6, g).astype(np.float32)  # many ties
+        match = rng.random(g) < rng.random()
+        ap, first = orc.average_precision(dist, match)
+        if not match.any():
+            assert (ap, first) == (0.0, -1)
+            continue
+        hits = match[np.lexsort((np.arange(g), dist))]
+        tp = np.cumsum(hits)
+        prec = tp / np.arange(1, g + 1)
+        rec = tp / hits.sum()
+        area = np.trapezoid(np.r_[1.0, prec], np.r_[0.0, rec])
+        assert ap == pytest.approx(area, abs=1e-12)
+        assert first == int(np.argmax(hits))
+
+
+def test_recall_at_k_and_map_against_brute_force():
+    rng = np.random.default_rng(7)
+    q, g = 30, 50
+    dist = rng.integers(0, 10, (q, g)).astype(np.float32)
+    ql = rng.integers(0, 6, q)
+    gl = rng.integers(0, 8, g)  # labels 6, 7 only in the gallery; some queries may have no match
+    gl[:3] = 99
+    ql[:2] = 123                # two queries without a true match
+    res = orc.evaluate(dist, ql, gl, ks=(1, 3, 10, 50))
+    valid = [i for i in range(q) if (gl == ql[i]).any()]
+    assert res["queries"] == len(valid) and res["first"][0] == -1 and res["ap"][1] == 0.0
+    for k in (1, 3, 10, 50):
+        hits = [any(gl[j] == ql[i] for j in sorted(range(g), key=lambda j: (dist[i, j], j))[:k]) for i in valid]
+        assert res["recall"][k] == pytest.approx(np.mean(hits), abs=1e-15)
+    assert res["map"] == pytest.approx(np.mean([res["ap"][i] for i in valid]), abs=1e-15)
+    assert res["recall"][50] == 1.0
+
+
+def test_metric_ties_go_to_the_lower_gallery_position():
+    # equal distances: the lower gallery position is listed first (reading R12)
+    assert orc.average_precision(np.array([0.2, 0.2]), np.array([False, True])) == (0.25, 1)
+    assert orc.average_precision(np.array([0.2, 0.2]), np.array([True, False])) == (1.0, 0)
+    assert orc.average_precision(np.array([-0.0, 0.0]), np.array([False, True])) == (0.25, 1)
+
+
+def test_perfect_ranking_gives_map_one():
+    q, g = 5, 12
+    gl = np.arange(g) % 4
+    ql = np.arange(q) % 4
+    dist = np.where(gl[None, :] == ql[:, None], 0.1, 0.9) + 1e-3 * np.arange(g)[None, :]
+    res = orc.evaluate(dist, ql, gl, ks=(1,))
+    assert res["map"] == 1.0 and res["recall"][1] == 1.0
+
+
+def test_planted_ap_mistakes_fail_the_polyline_pin():
+    # plausible slips in the AP definition, each written beside the oracle's
+    # own loop: all of them must disagree with the integrated polyline
+    def ap_variant(dist, match, kind):
+        hits = np.asarray(match)[np.argsort(dist, kind="stable")]
+        pos = np.flatnonzero(hits)
+        p, ap, prev = len(pos), 0.0, 1.0
+        for i, r in enumerate(pos):
+            p_at = (i + 1) / (r + 1)
+            if kind == "non_interpolated":
+                ap += p_at / p
+            elif kind == "before_at_previous_match":
+                ap += (prev + p_at) / 2 / p
+            elif kind == "off_by_one":
+                ap += ((1.0 if r == 0 else i / r) + (i + 1) / max(r, 1)) / 2 / p
+            prev = p_at
+        return ap
+
+    rng = np.random.default_rng(3)
+    dist = rng.random(25)
+    match = rng.random(25) < 0.3
+    hits = match[np.argsort(dist, kind="stable")]
+    tp = np.cumsum(hits)
+    area = np.trapezoid(np.r_[1.0, tp / np.arange(1, 26)], np.r_[0.0, tp / hits.sum()])
+    assert orc.average_precision(dist, match)[0] == pytest.approx(area, abs=1e-12)
+    for kind in ("non_interpolated", "before_at_previous_match", "off_by_one"):
+        assert abs(ap_variant(dist, match, kind) - area) > 1e-3, kind
