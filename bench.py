@@ -174,6 +174,28 @@ def serving_bench(binding, torch, synth, count, warmup):
     return res
 
 
+def quality_check(binding, torch, synth, spec, dev):
+    """Retrieval quality (mAP, Recall@K of Section 4.1, computed on the GPU by
+    rerank_evaluate) of plain cosine ranking and of the re-ranked distances,
+    on a noisier draw of the benchmark's shape: sigma = 2 (d/128)^(1/4) puts
+    the same-identity cosine ~1/(1+sigma^2) near the cross-identity spread
+    ~1/sqrt(d), where cosine ranking alone is far from perfect."""
+    import dataclasses
+    sigma = 2.0 * (spec.dim / 128.0) ** 0.25
+    qs = dataclasses.replace(spec, sigma=sigma, seed=spec.seed + 1)
+    x, lab = synth.make_features_device(qs, dev, return_labels=True)
+    ql, gl = lab[:qs.n_query].contiguous(), lab[qs.n_query:].contiguous()
+    out = {"sigma": sigma, "seed": qs.seed}
+    for name, layers, node in (("cosine", 0, "raw"), ("reranked", qs.layers, "adj")):
+        d = binding.run(x, qs.n_query, qs.k1, qs.k2, layers, node=node)
+        ev = binding.evaluate(d, ql, gl, (1, 5, 10))
+        out[name] = {"map": ev["map"], "recall_at": {str(k): v for k, v in ev["recall"].items()},
+                     "queries": ev["queries"]}
+        del d
+    torch.cuda.synchronize()
+    return out
+
+
 def cpu_baseline(x32, spec):
     """The FP64 oracle (as it stands) on the same problem, on this host."""
     from oracle import rerank_oracle as orc
@@ -200,6 +222,7 @@ def main() -> int:
     ap.add_argument("--no-lowp", action="store_true", help="skip every variant line")
     ap.add_argument("--variants", default="", help="comma-separated variant names to time (default: all)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-quality", action="store_true", help="skip the mAP / Recall@K check")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy a 1 GiB float32 tensor once (reference kernel for HBM counters)")
@@ -265,6 +288,11 @@ def main() -> int:
                                            "traffic": tr["bytes"] if tr else None, "traffic_detail": tr}
             lowp[name] = entry
 
+    quality = None
+    if not args.no_quality:
+        log("retrieval quality (cosine vs re-ranked)")
+        quality = quality_check(binding, torch, synth, spec, dev)
+
     if args.calibrate_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -317,6 +345,7 @@ def main() -> int:
         "variants": lowp,
         "parity": parity,
         "serving": serving,
+        "quality": quality,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -169,6 +169,32 @@ rerank_status rerank_similarity(rerank_ctx* ctx, const rerank_params* p, const v
 rerank_status rerank_rank(rerank_ctx* ctx, const float* d_dist, int32_t q, int32_t g, int32_t r, int32_t* d_rank,
                           void* hip_stream);
 
+/* Retrieval quality of a distance matrix under identity labels, the
+ * evaluation metrics of Section 4.1 (mean average precision and Recall@K).
+ * Each query's ranking list is its gallery positions by ascending distance,
+ * ties to the lower position (as rerank_rank); its true matches are the
+ * gallery positions whose label equals the query's.
+ *   d_dist      q rows of g float32 distances, row stride ld_dist >= g
+ *               (rerank_run writes ld_dist = g); finite values
+ *   d_q_labels  q int32 labels; d_g_labels  g int32 labels
+ *   ks, n_ks    HOST array of 1 <= n_ks <= 16 cut-offs, each K >= 1
+ *   d_ap        out: q float64, the query's average precision = the
+ *               trapezoid area under its precision-recall curve (from
+ *               recall 0 at precision 1, one point per list position); 0
+ *               for a query without a true match
+ *   d_first     out: q int32, list position of the first true match, -1
+ *               without one
+ *   d_summary   out: n_ks + 2 float64: [mAP, Recall@ks[0], ...,
+ *               Recall@ks[n_ks-1], number of queries with a true match];
+ *               the means are over the queries with a true match (0 if none)
+ * All d_ pointers are device memory owned by the caller (d_ap, d_summary
+ * 8-byte aligned, the rest 4-byte aligned). Stream-ordered on hip_stream;
+ * the host does not wait. RERANK_E_INVALID for NULL or misaligned pointers
+ * or sizes out of range. */
+rerank_status rerank_evaluate(rerank_ctx* ctx, const float* d_dist, int32_t q, int32_t g, int64_t ld_dist,
+                              const int32_t* d_q_labels, const int32_t* d_g_labels, const int32_t* ks, int32_t n_ks,
+                              double* d_ap, int32_t* d_first, double* d_summary, void* hip_stream);
+
 /* ---- serving: asynchronous requests with admission and continuous batching
  * A submitted request is admitted once its working set (rerank_workspace_bytes)
  * fits in the free part of the context budget; admitted requests run

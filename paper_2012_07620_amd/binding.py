@@ -26,7 +26,7 @@ EXPORTS = (
     "rerank_default_params", "rerank_validate", "rerank_workspace_bytes", "rerank_create", "rerank_destroy",
     "rerank_run", "rerank_knn", "rerank_similarity", "rerank_submit", "rerank_poll", "rerank_wait",
     "rerank_cancel", "rerank_status_str", "rerank_last_error", "rerank_stage_times", "rerank_stage_name",
-    "rerank_rank",
+    "rerank_rank", "rerank_evaluate",
 )
 CTX_STAGE_TIMING = 1
 CTX_DENSE_LAYERS = 2
@@ -80,6 +80,8 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
             "rerank_stage_times": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double)]),
             "rerank_stage_name": (ctypes.c_char_p, [i32]),
             "rerank_rank": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp]),
+            "rerank_evaluate": (ctypes.c_int, [vp, vp, i32, i32, ctypes.c_int64, vp, vp,
+                                               ctypes.POINTER(i32), i32, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -227,6 +229,31 @@ def rank(dist, r: int, ctx: Optional[Context] = None):
     _check(library().rerank_rank(ctx.handle, dist.data_ptr(), q, g, r, out.data_ptr(),
                                  _stream_ptr(torch, dist.device)))
     return out
+
+
+def evaluate(dist, q_labels, g_labels, ks=(1, 5, 10), ctx: Optional[Context] = None) -> dict:
+    """mAP and Recall@K of the distance rows ``dist`` (Q x G float32 device
+    tensor, row stride >= G) under int32 device label vectors. Returns
+    ``{"map", "recall": {K: value}, "queries", "ap", "first"}`` with the
+    per-query tensors on the device; waits for the result."""
+    import torch
+    if not dist.is_cuda or dist.dim() != 2 or dist.dtype != torch.float32 or dist.stride(1) != 1:
+        raise ValueError("dist must be a 2-D float32 device tensor with unit column stride")
+    q, g = dist.shape
+    for t, n in ((q_labels, q), (g_labels, g)):
+        if not t.is_cuda or t.dtype != torch.int32 or t.dim() != 1 or t.numel() != n or not t.is_contiguous():
+            raise ValueError("labels must be contiguous int32 device vectors of Q and G entries")
+    ks = [int(k) for k in ks]
+    ctx = ctx or default_context(dist.device.index or 0)
+    ap = torch.empty(q, dtype=torch.float64, device=dist.device)
+    first = torch.empty(q, dtype=torch.int32, device=dist.device)
+    summary = torch.empty(len(ks) + 2, dtype=torch.float64, device=dist.device)
+    karr = (ctypes.c_int32 * len(ks))(*ks)
+    _check(library().rerank_evaluate(ctx.handle, dist.data_ptr(), q, g, dist.stride(0), q_labels.data_ptr(),
+                                     g_labels.data_ptr(), karr, len(ks), ap.data_ptr(), first.data_ptr(),
+                                     summary.data_ptr(), _stream_ptr(torch, dist.device)))
+    s = summary.cpu().tolist()
+    return {"map": s[0], "recall": dict(zip(ks, s[1:1 + len(ks)])), "queries": int(s[-1]), "ap": ap, "first": first}
 
 
 def submit(ctx: Context, x, out, n_query: int, k1: int, k2: int, layers: int = 1, alpha: int = 2,

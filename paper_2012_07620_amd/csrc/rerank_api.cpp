@@ -6,6 +6,7 @@
 #include <string>
 
 #include "ctx.h"
+#include "eval.h"
 #include "pipeline.h"
 #include "serve.h"
 
@@ -315,6 +316,32 @@ rerank_status rerank_rank(rerank_ctx* ctx, const float* d_dist, int32_t q, int32
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   e = launch_rank(d_dist, q, g, r, d_rank, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "launch_rank");
+  return RERANK_OK;
+}
+
+rerank_status rerank_evaluate(rerank_ctx* ctx, const float* d_dist, int32_t q, int32_t g, int64_t ld_dist,
+                              const int32_t* d_q_labels, const int32_t* d_g_labels, const int32_t* ks, int32_t n_ks,
+                              double* d_ap, int32_t* d_first, double* d_summary, void* hip_stream) {
+  if (!ctx || !d_dist || !d_q_labels || !d_g_labels || !ks || !d_ap || !d_first || !d_summary ||
+      ((uintptr_t)d_dist & 3) || ((uintptr_t)d_q_labels & 3) || ((uintptr_t)d_g_labels & 3) ||
+      ((uintptr_t)d_first & 3) || ((uintptr_t)d_ap & 7) || ((uintptr_t)d_summary & 7)) {
+    set_error("a pointer is NULL or misaligned");
+    return RERANK_E_INVALID;
+  }
+  if (q < 1 || g < 1 || ld_dist < g || n_ks < 1 || n_ks > kEvalMaxK) {
+    set_error("need q >= 1, g >= 1, ld_dist >= g, 1 <= n_ks <= 16");
+    return RERANK_E_INVALID;
+  }
+  for (int j = 0; j < n_ks; j++)
+    if (ks[j] < 1) {
+      set_error("every cut-off K must be >= 1");
+      return RERANK_E_INVALID;
+    }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  e = launch_evaluate(d_dist, q, g, ld_dist, d_q_labels, d_g_labels, ks, n_ks, d_ap, d_first, d_summary,
+                      (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "launch_evaluate");
   return RERANK_OK;
 }
 

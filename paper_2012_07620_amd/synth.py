@@ -174,10 +174,12 @@ def request_specs(stream: StreamSpec, count: int, qps: float):
     return out
 
 
-def make_features_device(spec: ProblemSpec, device, seed: Optional[int] = None):
+def make_features_device(spec: ProblemSpec, device, seed: Optional[int] = None, return_labels: bool = False):
     """Same recipe as :func:`make_problem`, drawn with torch's generator on
     ``device`` (fast; used for the many requests of a serving stream). Returns
-    the features as a contiguous (N, d) tensor in the spec's storage dtype."""
+    the features as a contiguous (N, d) tensor in the spec's storage dtype,
+    and with ``return_labels`` also the (N,) int32 identity labels
+    (distractors get unique labels >= n_ids)."""
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(int(spec.seed if seed is None else seed))
@@ -194,7 +196,13 @@ def make_features_device(spec: ProblemSpec, device, seed: Optional[int] = None):
     q_lab = q_lab[torch.randperm(spec.n_query, generator=g, device=device)]
     g_lab = g_lab[torch.randperm(n_gal_ids, generator=g, device=device)]
     dis = unit(torch.randn(n_dis, d, generator=g, device=device)) if n_dis else torch.zeros(0, d, device=device)
-    gal = torch.cat([centres[g_lab], dis])[torch.randperm(spec.n_gallery, generator=g, device=device)]
+    perm = torch.randperm(spec.n_gallery, generator=g, device=device)
+    gal = torch.cat([centres[g_lab], dis])[perm]
     base = torch.cat([centres[q_lab], gal])
     x = unit(base + torch.randn(base.shape, generator=g, device=device) * (spec.sigma / d ** 0.5))
-    return (x.to(torch.bfloat16) if spec.dtype == "bf16" else x.float()).contiguous()
+    x = (x.to(torch.bfloat16) if spec.dtype == "bf16" else x.float()).contiguous()
+    if not return_labels:
+        return x
+    dis_lab = spec.n_ids + torch.arange(n_dis, device=device)
+    labels = torch.cat([q_lab, torch.cat([g_lab, dis_lab])[perm]]).to(torch.int32).contiguous()
+    return x, labels

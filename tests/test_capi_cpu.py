@@ -124,3 +124,19 @@ def test_context_flags_checked_before_any_device_call():
     assert binding.CTX_STAGE_TIMING == 1 and binding.CTX_DENSE_LAYERS == 2
     hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "rerank.h")).read()
     assert "#define RERANK_CTX_STAGE_TIMING 1u" in hdr and "#define RERANK_CTX_DENSE_LAYERS 2u" in hdr
+
+
+def test_evaluate_rejects_bad_arguments_before_any_device_call():
+    lib = binding.library()
+    buf = (ctypes.c_double * 8)()
+    p = ctypes.addressof(buf)  # 8-byte aligned stand-in, never dereferenced on these paths
+    ks = (ctypes.c_int32 * 2)(1, 5)
+    bad_k = (ctypes.c_int32 * 2)(1, 0)
+    assert lib.rerank_evaluate(None, p, 2, 3, 3, p, p, ks, 2, p, p, p, None) == binding.E_INVALID
+    assert lib.rerank_evaluate(p, None, 2, 3, 3, p, p, ks, 2, p, p, p, None) == binding.E_INVALID
+    assert lib.rerank_evaluate(p, p, 2, 3, 3, p, p, ks, 2, p + 4, p, p, None) == binding.E_INVALID  # ap misaligned
+    assert lib.rerank_evaluate(p, p, 0, 3, 3, p, p, ks, 2, p, p, p, None) == binding.E_INVALID
+    assert lib.rerank_evaluate(p, p, 2, 3, 2, p, p, ks, 2, p, p, p, None) == binding.E_INVALID  # ld < g
+    assert lib.rerank_evaluate(p, p, 2, 3, 3, p, p, ks, 0, p, p, p, None) == binding.E_INVALID
+    assert lib.rerank_evaluate(p, p, 2, 3, 3, p, p, ks, 17, p, p, p, None) == binding.E_INVALID
+    assert lib.rerank_evaluate(p, p, 2, 3, 3, p, p, bad_k, 2, p, p, p, None) == binding.E_INVALID
