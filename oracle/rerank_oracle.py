@@ -22,7 +22,8 @@ the definition written out in float64, taken from the exact input values:
   Final      ranking by cosine similarity of the refined features; the
              oracle returns the query x gallery distance 1 - cos.
 
-Readings taken where the paper is silent (each is also the GPU library's):
+Readings taken where the paper is silent (each is also the GPU library's;
+R11 and R12 concern arguments and test tolerances, not arithmetic):
   R1  cos is a true cosine: rows are divided by their norm.
   R2  row i itself is always member 0 of N(i, k) with similarity exactly 1,
       so every row has exactly k1 neighbours including itself.
@@ -37,25 +38,25 @@ Readings taken where the paper is silent (each is also the GPU library's):
   R9  output D_qg = 1 - cos(h_q, h_g) for q < Q <= g < N.
   R10 node mode "raw" uses h^(0)_i = x_i (the Table 1 ablation column with
       original features); with zero layers it gives the initial ranking.
-      Node mode "adj_raw" uses h^(0)_i = row i of A (Table 1, A_i column).
-  R11 aggregators (Eq. 13): "sum" (the paper's choice), "mean" = the sum of
+  R13 aggregators (Eq. 13): "sum" (the paper's choice), "mean" = the sum of
       the k2 messages divided by k2, "max" = element-wise maximum of the k2
       messages e_ij^alpha h_j; the residual h_i is added in every case.
-  R12 the ranking list L of Algorithm 1: per query, gallery rows by
+  R14 node mode "adj_raw" uses h^(0)_i = row i of A (Table 1, A_i column).
+  R15 the ranking list L of Algorithm 1: per query, gallery rows by
       ascending distance, ties to the lower gallery index.
 
 Retrieval metrics (Section 4.1, Evaluation Metrics), applied to synthetic
 identity labels: the true matches of a query are the gallery rows carrying
 its label.
-  R13 AP is the area under the query's precision-recall curve taken over the
-      ranking list R12 with the trapezoid rule: the curve starts at recall 0,
+  R16 AP is the area under the query's precision-recall curve taken over the
+      ranking list R15 with the trapezoid rule: the curve starts at recall 0,
       precision 1, and every list position adds a point (recall, precision)
       of the list's prefix up to it. With P true matches, the i-th (0-based)
       at list position r_i contributes (1/P) * (p_before + p_at) / 2, where
       p_at = (i+1)/(r_i+1) and p_before = i/r_i (1 when r_i = 0); positions
       that are not true matches add no area. mAP is the mean AP over the
       queries with at least one true match.
-  R14 Recall@K is 1 for a query whose first true match is among the first K
+  R17 Recall@K is 1 for a query whose first true match is among the first K
       positions of its list, else 0; averaged over the queries with at least
       one true match. No junk or same-camera filtering (the synthetic data
       has neither).
@@ -221,7 +222,7 @@ def _aggregate_max(h, w: sp.csr_matrix):
 def propagate(h0, w: sp.csr_matrix, layers: int, keep_all: bool = False, aggregator: str = "sum"):
     """Eq. 13/14: h <- h + aggregate(e_ij^alpha h_j, j in N(i,k2)), ``layers``
     times, each followed by the row L2 normalisation. Aggregators per reading
-    R11. ``keep_all`` also returns every intermediate h."""
+    R13. ``keep_all`` also returns every intermediate h."""
     h = h0
     hist = [h0]
     k2 = np.diff(w.indptr)
@@ -268,7 +269,7 @@ class OracleResult:
 
 def ranking(dist: np.ndarray, r: int) -> np.ndarray:
     """The first ``r`` entries of the ranking list L (Algorithm 1, reading
-    R12): per query row of ``dist``, gallery positions by ascending distance,
+    R15): per query row of ``dist``, gallery positions by ascending distance,
     ties to the lower position (a stable sort)."""
     return np.argsort(dist, axis=1, kind="stable")[:, :r]
 
@@ -292,7 +293,7 @@ def rerank(x: np.ndarray, n_query: int, k1: int, k2: int, layers: int,
 
 
 def average_precision(dist_row: np.ndarray, match: np.ndarray):
-    """AP of one query (reading R13) and the list position of its first true
+    """AP of one query (reading R16) and the list position of its first true
     match (-1 without matches). ``match`` flags the true matches among the
     gallery positions of ``dist_row``."""
     order = np.argsort(np.asarray(dist_row, dtype=np.float64), kind="stable")
@@ -312,7 +313,7 @@ def average_precision(dist_row: np.ndarray, match: np.ndarray):
 
 def evaluate(dist: np.ndarray, q_labels, g_labels, ks: Iterable[int] = (1, 5, 10)) -> dict:
     """mAP and Recall@K of a query x gallery distance matrix (Section 4.1,
-    readings R13-R14). Returns per-query ``ap`` and ``first`` (list position
+    readings R16-R17). Returns per-query ``ap`` and ``first`` (list position
     of the first true match, -1 without one) and the means over the queries
     that have a true match."""
     dist = np.asarray(dist)

@@ -346,7 +346,7 @@ def test_mean_is_sum_with_scaled_messages():
     np.testing.assert_allclose(a, b, atol=1e-14)
 
 
-# ---- retrieval metrics (Section 4.1, Evaluation Metrics; readings R13-R14)
+# ---- retrieval metrics (Section 4.1, Evaluation Metrics; readings R16-R17)
 
 def test_ap_of_one_true_match_at_each_position():
     # closed form: one true match at list position r has precision 1/(r+1)
@@ -414,7 +414,7 @@ def test_recall_at_k_and_map_against_brute_force():
 
 
 def test_metric_ties_go_to_the_lower_gallery_position():
-    # equal distances: the lower gallery position is listed first (reading R12)
+    # equal distances: the lower gallery position is listed first (reading R15)
     assert orc.average_precision(np.array([0.2, 0.2]), np.array([False, True])) == (0.25, 1)
     assert orc.average_precision(np.array([0.2, 0.2]), np.array([True, False])) == (1.0, 0)
     assert orc.average_precision(np.array([-0.0, 0.0]), np.array([False, True])) == (0.25, 1)
