@@ -103,6 +103,27 @@ __global__ __launch_bounds__(256) void gemm_fix_kernel(GemmArgs g, int tiles_m, 
   gemm_fix_tile(g, t.tm, t.tn, ws + (int64_t)w * parts * BM * BN, parts);
 }
 
+// K ranges per tile of a partly filled last round of `tiles` tiles on
+// `slots` resident workgroups: the fewest partial rounds per tile, needing a
+// saving of at least a fifth of a round, at least 8 K stages per range and
+// room for the partial tiles in ws_bytes; 1 = no split. *rem receives the
+// number of tail tiles.
+static int tail_parts(int64_t tiles, int slots, int nst, int64_t ws_bytes, int64_t* rem) {
+  *rem = 0;
+  if (slots <= 0 || tiles <= slots) return 1;
+  *rem = tiles % slots;
+  int parts = 1;
+  double best = 1.0;
+  for (int p = 2; p <= 8; p++) {
+    const double cost = (double)((*rem * p + slots - 1) / slots) / p;
+    if (cost < best - 1e-9 && nst >= 8 * p && *rem * p * BM * BN * 4 <= ws_bytes) {
+      best = cost;
+      parts = p;
+    }
+  }
+  return (best > 0.8 || *rem == 0) ? 1 : parts;
+}
+
 // Resident workgroups of the FP32 final product (queried once per process,
 // on the device current at the first call; thread-safe initialisation).
 static int dist_slots() {
@@ -126,23 +147,9 @@ hipError_t launch_gemm_dist(const float* a, int M, const float* b, int Nn, int64
   const int slots = ws ? dist_slots() : 0;
   const int nst = (int)(kelems * 4 / BKB);
   if (nst % DIST_KS) return hipErrorInvalidValue;  // K is padded to whole LDS stages
-  int parts = 1;
   int64_t rem = 0;
-  if (slots > 0 && tiles > slots && kelems * 4 % BKB == 0) {
-    rem = tiles % slots;
-    // K ranges per tail tile: the fewest partial rounds per tile, needing a
-    // saving of at least a fifth of a round
-    double best = 1.0;
-    for (int p = 2; p <= 8; p++) {
-      const double cost = (double)((rem * p + slots - 1) / slots) / p;
-      if (cost < best - 1e-9 && nst >= 8 * p && rem * p * BM * BN * 4 <= ws_bytes) {
-        best = cost;
-        parts = p;
-      }
-    }
-    if (best > 0.8) parts = 1;
-  }
-  if (parts == 1 || rem == 0)
+  const int parts = (kelems * 4 % BKB == 0) ? tail_parts(tiles, slots, nst, ws_bytes, &rem) : 1;
+  if (parts == 1)
     return launch_gemm_t<MODE_F32, EPI_DIST>(a, M, ld_elems * 4, b, Nn, ld_elems * 4, kelems * 4, sa, sb, out, ldo, s);
   if (tiles > 0x7FFFFFFF || rem * parts > 0x7FFFFFFF) return hipErrorInvalidValue;
   const int64_t first = tiles - rem;
@@ -160,16 +167,19 @@ __global__ __launch_bounds__(256) void gemm_x3_kernel(GemmX3Args g, int tiles_m,
   gemm_tile_x3(g, t.tm, t.tn, lds_x3);
 }
 
+// Raises the dynamic-LDS limit of gemm_x3_kernel once per process
+// (thread-safe initialisation); the status of that call.
+static hipError_t x3_attr() {
+  static const hipError_t e = hipFuncSetAttribute((const void*)gemm_x3_kernel,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, X3_LDS_BYTES);
+  return e;
+}
+
 hipError_t launch_gemm_dist_bf16x3(const uint16_t* a_hi, const uint16_t* a_lo, int M, const uint16_t* b_hi,
                                    const uint16_t* b_lo, int Nn, int64_t ld_elems, int64_t kelems, const float* sa,
                                    const float* sb, float* out, int64_t ldo, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)gemm_x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       X3_LDS_BYTES);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  const hipError_t e = x3_attr();
+  if (e != hipSuccess) return e;
   const int tm = (M + BM - 1) / BM, tn = (Nn + BN - 1) / BN;
   const int64_t nwg = (int64_t)tm * tn;
   if (nwg <= 0 || nwg > 0x7FFFFFFF || kelems % 64 || kelems <= 0 || ld_elems % 64) return hipErrorInvalidValue;

@@ -164,6 +164,7 @@ def test_low_precision_similarity_error(gpu_lib, prec):
     (333, 33, 96, 20, 6, 2, "raw"),
     (333, 33, 96, 20, 6, 0, "raw"),
     (130, 30, 64, 9, 4, 3, "adj"),
+    (12000, 5000, 64, 20, 6, 1, "adj"),  # 40 x 55 tiles: the partly filled last round is split along K
 ])
 def test_final_bf16x3_matches_fp64(gpu_lib, n, q, d, k1, k2, layers, node):
     # the split-bf16 final product must meet the FP32 path's tolerance
