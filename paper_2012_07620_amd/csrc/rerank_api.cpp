@@ -94,9 +94,11 @@ static rerank_status with_ws(rerank_ctx* ctx, const Plan& P, void* hip_stream, F
     if (e != hipSuccess) return hip_fail(e, "stage clock");
   }
   e = body(s, &where);
+  // recorded after a failure too: whatever was enqueued still uses the working
+  // set, and later calls (any stream) and its reallocation wait for this event
+  const hipError_t er = hipEventRecord(ctx->ws_free, s);
   if (e != hipSuccess) return hip_fail(e, where);
-  e = hipEventRecord(ctx->ws_free, s);
-  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if (er != hipSuccess) return hip_fail(er, "hipEventRecord");
   return RERANK_OK;
 }
 

@@ -393,8 +393,13 @@ class Server {
     }
     if (e != hipSuccess) {
       const std::string msg = std::string(where) + ": " + hipGetErrorString(e);
+      // work enqueued before the failure may still run on the slot's stream:
+      // let it drain before the working sets can go to other requests
+      (void)hipStreamSynchronize(s.stream);
+      (void)hipGetLastError();
       for (auto& r : s.reqs) {
         pool_.release(r->ws);
+        r->ws = nullptr;
         finish(r, RERANK_E_HIP, msg);
       }
       s.reqs.clear();
@@ -519,6 +524,12 @@ void server_stop(Server* s) {
   delete s;
 }
 
+// The context's server if one was started (read under the lock that creates it).
+static Server* server_of(rerank_ctx* ctx) {
+  std::lock_guard<std::mutex> lk(ctx->server_mu);
+  return ctx->server;
+}
+
 static rerank_status get_server(rerank_ctx* ctx, Server** out) {
   std::lock_guard<std::mutex> lk(ctx->server_mu);
   if (!ctx->server) {
@@ -568,27 +579,30 @@ rerank_status rerank_submit(rerank_ctx* ctx, const rerank_params* p, const void*
 }
 
 rerank_status rerank_poll(rerank_ctx* ctx, uint64_t ticket, int* done) {
-  if (!ctx || !done || !ctx->server) {
+  Server* srv = ctx ? server_of(ctx) : nullptr;
+  if (!done || !srv) {
     set_error("ctx/done NULL or nothing submitted");
     return RERANK_E_INVALID;
   }
-  return ctx->server->poll(ticket, done);
+  return srv->poll(ticket, done);
 }
 
 rerank_status rerank_wait(rerank_ctx* ctx, uint64_t ticket, int64_t timeout_us, double* latency_ms) {
-  if (!ctx || !ctx->server) {
+  Server* srv = ctx ? server_of(ctx) : nullptr;
+  if (!srv) {
     set_error("ctx NULL or nothing submitted");
     return RERANK_E_INVALID;
   }
-  return ctx->server->wait(ticket, timeout_us, latency_ms);
+  return srv->wait(ticket, timeout_us, latency_ms);
 }
 
 rerank_status rerank_cancel(rerank_ctx* ctx, uint64_t ticket) {
-  if (!ctx || !ctx->server) {
+  Server* srv = ctx ? server_of(ctx) : nullptr;
+  if (!srv) {
     set_error("ctx NULL or nothing submitted");
     return RERANK_E_INVALID;
   }
-  return ctx->server->cancel(ticket);
+  return srv->cancel(ticket);
 }
 
 }  // extern "C"
