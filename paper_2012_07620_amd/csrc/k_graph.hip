@@ -139,17 +139,20 @@ __global__ __launch_bounds__(256) void propagate_kernel(const float* __restrict_
                                                         int64_t ld, int64_t cols, const int32_t* __restrict__ knn,
                                                         const float* __restrict__ kv, int k1, int k2, int alpha,
                                                         int agg, float* __restrict__ hout, float* __restrict__ sout,
-                                                        uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+                                                        uint16_t* __restrict__ hi, uint16_t* __restrict__ lo,
+                                                        const int32_t* __restrict__ order) {
   __shared__ PropShared sh;
-  propagate_row(hin, sin, ld, cols, knn, kv, k1, k2, alpha, agg, hout, sout, hi, lo, blockIdx.x, sh);
+  const int i = order ? order[xcd_linear(blockIdx.x, gridDim.x)] : (int)blockIdx.x;
+  propagate_row(hin, sin, ld, cols, knn, kv, k1, k2, alpha, agg, hout, sout, hi, lo, i, sh);
 }
 
 hipError_t launch_propagate(const float* hin, const float* sin, int n, int64_t ld, int64_t cols,
                             const int32_t* knn_idx, const float* knn_val, int k1, int k2, int alpha, int agg,
-                            float* hout, float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s) {
+                            float* hout, float* sout, uint16_t* hi, uint16_t* lo, const int32_t* order,
+                            hipStream_t s) {
   if (k2 < 1 || k2 > 256 || (cols & 3) || (ld & 3)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(propagate_kernel, dim3(n), dim3(256), 0, s, hin, sin, ld, cols, knn_idx, knn_val, k1, k2, alpha,
-                     agg, hout, sout, hi, lo);
+                     agg, hout, sout, hi, lo, order);
   return hipGetLastError();
 }
 

@@ -115,10 +115,13 @@ hipError_t launch_astar_sigma(const int32_t* cnt, int n, int k1, float* sigma, b
 // w_i0 = 1 for the row itself, w_ir = val_ir^alpha; sout_i = 1/|hout_i|.
 // sin == nullptr means all ones. When hi/lo are non-null the row is written
 // as bf16 high/low parts (final bf16x3 product) instead of FP32.
-// agg: rerank_aggregator of Eq. 13.
+// agg: rerank_aggregator of Eq. 13. order (n rows, or nullptr for index
+// order): rows are computed in this order, consecutive ones on one XCD, so
+// the neighbour rows a cluster shares are read from that XCD's L2.
 hipError_t launch_propagate(const float* hin, const float* sin, int n, int64_t ld, int64_t cols,
                             const int32_t* knn_idx, const float* knn_val, int k1, int k2, int alpha, int agg,
-                            float* hout, float* sout, uint16_t* hi, uint16_t* lo, hipStream_t s);
+                            float* hout, float* sout, uint16_t* hi, uint16_t* lo, const int32_t* order,
+                            hipStream_t s);
 // Sparse first layer (A* never stored densely when layers >= 1):
 // mutual flags of every (i, r) pair and non-mutual in-degree counts ...
 hipError_t launch_mutual(const int32_t* knn_idx, int n, int k1, uint8_t* mflag, int32_t* innm, hipStream_t s);

@@ -195,6 +195,13 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
     RR_STAGE(RERANK_STAGE_ADJACENCY, 1);
     RR_STAGE(RERANK_STAGE_PROPAGATE, 0);
   }
+  const int32_t* order = nullptr;  // dense layers walk rows in cluster order
+  if (first < P.layers && !P.sparse_layers) {
+    int32_t* oscr = at<int32_t>(ws, P.o_ord);
+    int32_t* ord = oscr + cluster_order_ints(P.n, P.n);
+    RR_TRY(launch_cluster_order(ki, P.n, P.k1, P.n, oscr, ord, s));
+    order = ord;
+  }
   for (int l = first; l < P.layers; l++) {
     float* out = (cur == A) ? B : A;
     float* osig = (csig == sa) ? sb : sa;
@@ -211,7 +218,7 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
                                     s));
     } else {
       RR_TRY(launch_propagate(cur, csig, P.n, P.ldH, P.ldH, ki, kv, P.k1, P.k2, P.alpha, P.agg, out, osig,
-                              last ? hi : nullptr, last ? lo : nullptr, s));
+                              last ? hi : nullptr, last ? lo : nullptr, order, s));
     }
     cur = out;
     csig = osig;

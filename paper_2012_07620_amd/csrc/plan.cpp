@@ -86,6 +86,8 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o, bool dense_layers
     P.o_sb = take(n * 4);
     P.o_cnt = take(n * 8);  // in-degree and mutual counts (or in-degree and cursor), 2n int32
     P.o_part = take((size_t)scan_parts(P.n) * 4);  // block sums of the prefix sums over rows
+    // cluster order of the rows for the dense layers (+ its scratch)
+    if (P.layers > 0) P.o_ord = take((size_t)(cluster_order_ints(P.n, P.n) + P.n) * 4);
     P.sparse_first = (P.node != RERANK_NODE_RAW && P.layers > 0 && P.agg != RERANK_AGG_MAX);
     if (P.sparse_first && P.node == RERANK_NODE_ADJ_SYM) {
       P.o_mflag = take(n * P.k1);

@@ -33,7 +33,8 @@ struct Plan {
   // byte offsets into the working set
   size_t o_xp = 0, o_xl = 0, o_rn = 0, o_sl = 0, o_a = 0, o_b = 0, o_ci = 0, o_cv = 0, o_ki = 0, o_kv = 0,
          o_sa = 0, o_sb = 0, o_cnt = 0, o_hi = 0, o_lo = 0, o_mflag = 0, o_off = 0, o_inl = 0, o_sp = 0,
-         o_slg = 0, o_slr = 0, o_part = 0;
+         o_slg = 0, o_slr = 0, o_part = 0,
+         o_ord = 0;
   bool sparse_first = false;   // layer 1 built from the sparse A* / A rows (layers >= 1, sum or mean)
   bool sparse_layers = false;  // layers kept as CSR rows for the sparse final product
   size_t total = 0;
