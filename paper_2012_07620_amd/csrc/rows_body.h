@@ -581,9 +581,10 @@ __device__ __forceinline__ int col_rank(const FirstShared& sh, int c) {
   return sh.rk.base[c >> 5] + __builtin_popcount(wd & ((1u << (c & 31)) - 1u));
 }
 
-// Returns the end of the written entries; *ss receives the squared norm.
-__device__ __forceinline__ int ranked_row(FirstShared& sh, int k2, int64_t ld, const SlRows& out, int pos,
-                                          float* ss) {
+// Sums of a staged row by column rank: whole-row bitmap of the touched
+// columns, rank table, then the members' terms added member by member (the
+// dense layer's order). Leaves bits, rk and wsum set for the caller.
+__device__ __forceinline__ void ranked_sums(FirstShared& sh, int k2, int64_t ld) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int words = (int)(ld >> 5);
   const int total_e = sh.start[k2];
@@ -623,6 +624,17 @@ __device__ __forceinline__ int ranked_row(FirstShared& sh, int k2, int64_t ld, c
     }
     __syncthreads();
   }
+}
+
+// CSR output of a staged row. Returns the end of the written entries; *ss
+// receives the squared norm.
+__device__ __forceinline__ int ranked_row(FirstShared& sh, int k2, int64_t ld, const SlRows& out, int pos,
+                                          float* ss) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int words = (int)(ld >> 5);
+  ranked_sums(sh, k2, ld);
+  const int per = (words + 255) / 256;
+  const int w0 = min(words, tid * per), w1 = min(words, w0 + per);
   float acc = 0.f;
   const int nf = (int)(ld >> 2);
   for (int f = tid; f < nf; f += 256) {
@@ -644,7 +656,7 @@ __device__ __forceinline__ int ranked_row(FirstShared& sh, int k2, int64_t ld, c
     const int b0 = sh.rk.base[x], nb = __builtin_popcount(sh.bits[x]);
     for (int k = b0; k < b0 + nb; k++) keep += sh.rk.val[k] != 0.f;
   }
-  incl = keep;
+  int incl = keep;
   for (int o = 1; o < 64; o <<= 1) {
     const int t = __shfl_up(incl, o, kWave);
     if (lane >= o) incl += t;
@@ -673,6 +685,35 @@ __device__ __forceinline__ int ranked_row(FirstShared& sh, int k2, int64_t ld, c
   }
   __syncthreads();  // wsum, bits and the table are reused by the caller
   return pos + total;
+}
+
+// Dense output of a staged row (row i of hout, or of the hi / lo planes): one
+// pass over the row, zeros where no column was touched; *ss receives the
+// squared norm, accumulated per thread over float4 f = tid, tid + 256, ...
+// like the chunked writer, so both give the same bits.
+__device__ __forceinline__ void ranked_dense_row(FirstShared& sh, int k2, int64_t ld, float* __restrict__ hout,
+                                                 uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int i,
+                                                 float* ss) {
+  const int tid = threadIdx.x;
+  ranked_sums(sh, k2, ld);
+  float acc = 0.f;
+  const int nf = (int)(ld >> 2);
+  for (int f = tid; f < nf; f += 256) {
+    const uint32_t nib = (sh.bits[f >> 3] >> ((f & 7) * 4)) & 0xFu;
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (nib) {
+      int k = col_rank(sh, 4 * f);  // rank of the first touched column of this float4
+      for (int e = 0; e < 4; e++)
+        if (nib & (1u << e)) v[e] = sh.rk.val[k++];
+    }
+    if (hi)
+      split_store4(hi, lo, (int64_t)i * ld + 4 * f, v);
+    else
+      ((f32x4*)(hout + (int64_t)i * ld))[f] = v;
+    acc = sq_acc4(acc, v);
+  }
+  *ss = acc;
+  __syncthreads();  // bits and the table are reused by the caller
 }
 
 // u_i = sum_r cf_r h_{j_r} over the k2 members (coefficients already in sh.p)
@@ -730,11 +771,15 @@ __device__ __forceinline__ void sparse_row_core(const Src& src, const float* __r
   __syncthreads();
   const int pos0 = pos;
   float ss = 0.f;
-  if (csr && staged && (ld >> 5) <= ROW_WORDS) {
-    const int end = ranked_row(sh, k2, ld, sl->rows, pos, &ss);
-    if (tid == 0) {
-      sl->rows.so[i] = pos0;
-      sl->rows.cnt[i] = end - pos0;
+  if (staged && (ld >> 5) <= ROW_WORDS) {  // whole row at once, no column chunks
+    if (csr) {
+      const int end = ranked_row(sh, k2, ld, sl->rows, pos, &ss);
+      if (tid == 0) {
+        sl->rows.so[i] = pos0;
+        sl->rows.cnt[i] = end - pos0;
+      }
+    } else {
+      ranked_dense_row(sh, k2, ld, hout, hi, lo, i, &ss);
     }
     finish_norm(ss, sout, i, sh.p);
     return;
