@@ -495,7 +495,7 @@ __device__ __forceinline__ void csr_pair(const int32_t* __restrict__ knn, int n,
 
 // Rows built from sparse member rows (the first layer from A* / A, and the
 // sparse layers from CSR rows), one LDS column chunk at a time.
-constexpr int FIRST_CHUNK = 8192;    // floats of the output row held in LDS
+constexpr int FIRST_CHUNK = 3072;    // floats of the output row held in LDS (fallback path; 12 KB like the rank table)
 constexpr int FIRST_WORDS = FIRST_CHUNK / 32;  // touched-column bitmap of a chunk
 constexpr int FIRST_ENTRIES = 1024;  // member entries of one row staged in LDS
 constexpr int ROW_WORDS = 2048;      // touched-column bitmap of a whole row (rows up to 65536 columns)
