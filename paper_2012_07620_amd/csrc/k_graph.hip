@@ -51,17 +51,19 @@ hipError_t launch_cluster_order(const int32_t* lists, int rows, int w, int n, in
 template <int R>
 __global__ __launch_bounds__(256) void rescore_kernel(const float* __restrict__ xp, int64_t ldp,
                                                       const float* __restrict__ rn, int n,
-                                                      const int32_t* __restrict__ cand, int Kc, int k1,
+                                                      const int32_t* __restrict__ cand,
+                                                      const float* __restrict__ cval, int Kc, int k1, float skip2,
                                                       int32_t* __restrict__ kidx, float* __restrict__ kval,
                                                       const int32_t* __restrict__ order) {
   const int p = (order ? xcd_linear(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (p >= n) return;
   const int i = order ? order[p] : p;
-  rescore_row<R>(xp, ldp, rn, i, cand, Kc, k1, kidx, kval);
+  rescore_row<R>(xp, ldp, rn, i, cand, cval, Kc, k1, skip2, kidx, kval);
 }
 
-hipError_t launch_rescore(const float* xp, int64_t ldp, int d, const float* rn, int n, const int32_t* cand, int Kc,
-                          int k1, int32_t* knn_idx, float* knn_val, int32_t* scratch, hipStream_t s) {
+hipError_t launch_rescore(const float* xp, int64_t ldp, int d, const float* rn, int n, const int32_t* cand,
+                          const float* cval, int Kc, int k1, float skip2, int32_t* knn_idx, float* knn_val,
+                          int32_t* scratch, hipStream_t s) {
   (void)d;
   if (Kc < k1 || Kc > 256 || (ldp & 3)) return hipErrorInvalidValue;
   const int32_t* order = nullptr;
@@ -73,11 +75,14 @@ hipError_t launch_rescore(const float* xp, int64_t ldp, int d, const float* rn, 
   }
   dim3 grid((n + 3) / 4), block(256);
   if (Kc <= 64)
-    hipLaunchKernelGGL(rescore_kernel<1>, grid, block, 0, s, xp, ldp, rn, n, cand, Kc, k1, knn_idx, knn_val, order);
+    hipLaunchKernelGGL(rescore_kernel<1>, grid, block, 0, s, xp, ldp, rn, n, cand, cval, Kc, k1, skip2, knn_idx, knn_val,
+                       order);
   else if (Kc <= 128)
-    hipLaunchKernelGGL(rescore_kernel<2>, grid, block, 0, s, xp, ldp, rn, n, cand, Kc, k1, knn_idx, knn_val, order);
+    hipLaunchKernelGGL(rescore_kernel<2>, grid, block, 0, s, xp, ldp, rn, n, cand, cval, Kc, k1, skip2, knn_idx, knn_val,
+                       order);
   else
-    hipLaunchKernelGGL(rescore_kernel<4>, grid, block, 0, s, xp, ldp, rn, n, cand, Kc, k1, knn_idx, knn_val, order);
+    hipLaunchKernelGGL(rescore_kernel<4>, grid, block, 0, s, xp, ldp, rn, n, cand, cval, Kc, k1, skip2, knn_idx, knn_val,
+                       order);
   return hipGetLastError();
 }
 

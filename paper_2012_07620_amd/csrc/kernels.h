@@ -90,12 +90,26 @@ hipError_t launch_topk(const void* S, bool half, int64_t ldS, int N, int rows, i
 inline int64_t cluster_order_ints(int64_t rows, int64_t n) { return (3 * n + rows + 1 + scan_parts(n) + 3) / 4 * 4; }
 hipError_t launch_cluster_order(const int32_t* lists, int rows, int w, int n, int32_t* scratch, int32_t* order,
                                 hipStream_t s);
+// 2 delta for the candidate skip of the FP32 re-score: delta bounds the
+// error of the FP32 similarity product over K padded terms, scaled by the two
+// inverse norms (|error| <= (K + 8) u / (1 - (K + 8) u) of |x_i| |x_j| by
+// Cauchy-Schwarz, u = 2^-24), here doubled for margin. The low-precision
+// products have no such tight bound: -1 (re-score every candidate).
+__host__ __device__ inline float rescore_skip2(bool f32_product, int64_t K) {
+  if (!f32_product) return -1.f;
+  const double ku = (double)(K + 8) * 0x1p-24;
+  return (float)(2.0 * 2.0 * ku / (1.0 - ku));
+}
+
 // a3b: FP32 compensated re-score of Kc candidates per row, then the k1 cut.
-// scratch (cluster_order_ints(n, n) + n int32, 16-byte aligned) or nullptr: rows are re-scored in
-// an order that keeps rows with shared candidates on one XCD (the results do
-// not depend on the order).
+// cval: the candidates' product values (sorted descending, as top-k writes
+// them); skip2 = rescore_skip2(...) skips candidates that cannot reach the
+// top k1 (-1: re-score all). scratch (cluster_order_ints(n, n) + n int32,
+// 16-byte aligned) or nullptr: rows are re-scored in an order that keeps rows
+// with shared candidates on one XCD (the results do not depend on the order).
 hipError_t launch_rescore(const float* xp, int64_t ldp, int d, const float* rn, int n, const int32_t* cand,
-                          int Kc, int k1, int32_t* knn_idx, float* knn_val, int32_t* scratch, hipStream_t s);
+                          const float* cval, int Kc, int k1, float skip2, int32_t* knn_idx, float* knn_val,
+                          int32_t* scratch, hipStream_t s);
 // Copy the first k1 of Kc candidates (no re-score).
 hipError_t launch_take_prefix(const int32_t* cand_idx, const float* cand_val, int n, int Kc, int k1,
                               int32_t* knn_idx, float* knn_val, hipStream_t s);

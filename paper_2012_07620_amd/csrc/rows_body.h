@@ -200,18 +200,33 @@ __device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, i
 // candidates at a time.
 template <int R>
 __device__ __forceinline__ void rescore_row(const float* __restrict__ xp, int64_t ldp, const float* __restrict__ rn,
-                                            int i, const int32_t* __restrict__ cand, int Kc, int k1,
-                                            int32_t* __restrict__ kidx, float* __restrict__ kval) {
+                                            int i, const int32_t* __restrict__ cand, const float* __restrict__ cval,
+                                            int Kc, int k1, float skip2, int32_t* __restrict__ kidx,
+                                            float* __restrict__ kval) {
   const int lane = threadIdx.x & 63;
   const int sub = lane >> 4, sl = lane & 15;
   const float* xi = xp + (int64_t)i * ldp;
   const float rni = rn[i];
+  // Candidates arrive sorted by their product values g. With skip2 = 2 delta
+  // >= 0 (delta bounds |g - exact|), a candidate past position k1 can enter
+  // the exact top-k1 only if g >= g[k1 - 1] - skip2: those form a prefix,
+  // and only that prefix is re-scored (same lists and values as all of it).
+  int cnt = Kc;
+  if (skip2 >= 0.f) {
+    const float thr = cval[(int64_t)i * Kc + (k1 - 1)] - skip2;
+    int last = k1 - 1;
+    for (int c = k1 + lane; c < Kc; c += 64)
+      if (cval[(int64_t)i * Kc + c] >= thr) last = max(last, c);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) last = max(last, __shfl_xor(last, m, kWave));
+    cnt = last + 1;
+  }
   uint64_t keys[R];
 #pragma unroll
   for (int r = 0; r < R; r++) keys[r] = 0;
-  for (int c0 = 0; c0 < Kc; c0 += 4) {
+  for (int c0 = 0; c0 < cnt; c0 += 4) {
     const int c = c0 + sub;
-    const int j = (c < Kc) ? cand[(int64_t)i * Kc + c] : i;
+    const int j = (c < cnt) ? cand[(int64_t)i * Kc + c] : i;
     DF acc{0.f, 0.f};
     if (j != i) {
       const float* xj = xp + (int64_t)j * ldp;
@@ -236,7 +251,7 @@ __device__ __forceinline__ void rescore_row(const float* __restrict__ xp, int64_
     for (int s = 0; s < 4; s++) {
       const uint64_t ks = shfl_u64(key, s * 16);
       const int cs = c0 + s;
-      if (cs < Kc) {
+      if (cs < cnt) {
 #pragma unroll
         for (int r = 0; r < R; r++)
           if ((cs >> 6) == r && lane == (cs & 63)) keys[r] = ks;
