@@ -17,6 +17,8 @@
 // 64 bf16 (32x32x16 bf16, 4 steps) or 128 OCP e4m3 (32x32x64 f8f6f4, unit
 // block scales, 2 steps). Accumulation is FP32 in every mode.
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 
 namespace rr {
@@ -31,6 +33,11 @@ enum { MODE_F32 = 0, MODE_BF16 = 1, MODE_FP8 = 2 };
 // EPI_PART: no epilogue; the raw accumulators of a K range go to a 128 x 128
 // partial tile (g.out, tile-local layout) for a later fixed-order sum.
 enum { EPI_DIST = 1, EPI_SIM_SYM = 2, EPI_SIM_SYM16 = 3, EPI_PART = 4 };
+// LDS of a similarity tile (one stage buffer, reused for staging the output
+// tile): FP32 S needs 128 x 132 floats, binary16 S fits in the stage buffer.
+__host__ __device__ constexpr int sim_lds_bytes(int epi) {
+  return epi == EPI_SIM_SYM16 ? GEMM_LDS_1BUF : GEMM_LDS_BYTES;
+}
 
 template <int MODE>
 __device__ __forceinline__ void mfma_stage(f32x16 (&acc)[2][2], const u32x4 (&a)[2][4], const u32x4 (&b)[2][4]) {
@@ -223,14 +230,19 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
     __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
   } else {
     // Similarity: the scaled tile is staged row-major in LDS (free after the
-    // loop's last barrier), then written with 16-byte stores per lane: rows
-    // of the tile at (tm, tn) and, off the diagonal, rows of its transpose at
-    // (tn, tm) (lanes along the tile's columns, each gathering one 16-byte run
-    // of a transposed row). Zeros stand in outside M x Nn and are not stored.
+    // loop's last barrier) in the output type (binary16 values are rounded
+    // here, once, as a direct store would), then written with 16-byte stores
+    // per lane: rows of the tile at (tm, tn) and, off the diagonal, rows of
+    // its transpose at (tn, tm) (lanes along the tile's columns, each
+    // gathering one 16-byte run of a transposed row). Zeros stand in outside
+    // M x Nn and are not stored.
     constexpr bool H16 = (EPI == EPI_SIM_SYM16);
-    constexpr int TS = BN + 4;  // staged row stride (floats; 16-byte aligned rows)
-    static_assert(BM * TS * 4 <= GEMM_LDS_BYTES, "staged tile must fit the similarity LDS");
-    float* T = (float*)lds;
+    using OT = typename std::conditional<H16, _Float16, float>::type;
+    constexpr int V = 16 / (int)sizeof(OT);  // elements per 16-byte store
+    constexpr int TS = BN + V;               // staged row stride (16-byte aligned rows)
+    static_assert(BM * TS * (int)sizeof(OT) <= sim_lds_bytes(EPI), "staged tile must fit the similarity LDS");
+    typedef OT ov __attribute__((ext_vector_type(V)));
+    OT* T = (OT*)lds;
 #pragma unroll
     for (int sm = 0; sm < 2; sm++)
 #pragma unroll
@@ -242,35 +254,21 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
         for (int r = 0; r < 16; r++) {
           const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
           const int row = m0 + lr;
-          T[lr * TS + lc] = (row < g.M && col < g.Nn) ? acc[sm][sn][r] * g.sa[row] * scol + 0.0f : 0.f;
+          T[lr * TS + lc] = (OT)((row < g.M && col < g.Nn) ? acc[sm][sn][r] * g.sa[row] * scol + 0.0f : 0.f);
         }
       }
     __syncthreads();
-    constexpr int V = H16 ? 8 : 4;        // elements per 16-byte store
     constexpr int CPR = BN / V;           // 16-byte chunks per tile row
     constexpr int RPP = 256 / CPR;        // tile rows per pass
-    _Float16* out16 = (_Float16*)g.out;   // EPI_SIM_SYM16: ldo counts halves
+    OT* out = (OT*)g.out;                 // ldo counts elements of the output type
     const bool vec = (((uintptr_t)g.out & 15) == 0) && (g.ldo % V == 0);
-    auto put = [&](int64_t row, int col0, int lim, const float* v) {  // V values at (row, col0..), cols < lim
+    auto put = [&](int64_t row, int col0, int lim, const ov& v) {  // V values at (row, col0..), cols < lim
       if (vec && col0 + V <= lim) {
-        if constexpr (H16) {
-          typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-          h8 hv;
-#pragma unroll
-          for (int e = 0; e < 8; e++) hv[e] = (_Float16)v[e];
-          *(h8*)(out16 + row * g.ldo + col0) = hv;
-        } else {
-          *(f32x4*)(g.out + row * g.ldo + col0) = f32x4{v[0], v[1], v[2], v[3]};
-        }
+        *(ov*)(out + row * g.ldo + col0) = v;
       } else {
 #pragma unroll
         for (int e = 0; e < V; e++)
-          if (col0 + e < lim) {
-            if constexpr (H16)
-              out16[row * g.ldo + col0 + e] = (_Float16)v[e];
-            else
-              g.out[row * g.ldo + col0 + e] = v[e];
-          }
+          if (col0 + e < lim) out[row * g.ldo + col0 + e] = v[e];
       }
     };
     // the tile: lanes along a row
@@ -278,17 +276,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
       const int row = m0 + lr;
       if (row >= g.M) continue;
       const int ch = tid % CPR;
-      float v[V];
-#pragma unroll
-      for (int e = 0; e < V; e++) v[e] = T[lr * TS + ch * V + e];
-      put(row, n0 + ch * V, g.Nn, v);
+      put(row, n0 + ch * V, g.Nn, *(const ov*)(T + lr * TS + ch * V));
     }
     if (tm != tn) {  // the transpose: lane = tile column, one V-run of tile rows each
       const int lc = tid & 127;
       const int row = n0 + lc;
       if (row < g.Nn)
         for (int ch = tid >> 7; ch < BM / V; ch += 2) {
-          float v[V];
+          ov v;
 #pragma unroll
           for (int e = 0; e < V; e++) v[e] = T[(ch * V + e) * TS + lc];
           put(row, m0 + ch * V, g.M, v);
