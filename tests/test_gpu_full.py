@@ -117,3 +117,25 @@ def test_large_sampled(gpu_lib):
             err = np.abs(d[q_rows] - dref)
             print(f"large {prec}: rows with identical k1 sets {same:.6f}, D max err {err.max():.2e}")
             assert same >= 0.995 and err.max() <= D_TOL[prec]
+
+
+def test_mid_similarity_error_within_the_rescore_bound(gpu_lib, mid):
+    # The FP32 re-score skips candidates whose product value lies more than
+    # 2 delta below the k1-th one, delta = (K + 8) u / (1 - (K + 8) u) (the
+    # product's error bound, doubled again in the library). Check that the
+    # measured error of the FP32 similarity product is far inside delta.
+    import torch
+    from paper_2012_07620_amd import binding
+    p, _ = mid
+    s = binding.similarity(torch.from_numpy(p.x32).cuda())
+    rows = np.random.default_rng(1).choice(p.spec.n, 48, replace=False)
+    got = s[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+    del s
+    torch.cuda.synchronize()
+    ref = orc.similarity_rows(orc.unit_rows(p.x32), rows)
+    k = (p.spec.dim + 63) // 64 * 64
+    ku = (k + 8) * 2.0 ** -24
+    delta = ku / (1 - ku)
+    err = np.abs(got - ref).max()
+    print(f"FP32 similarity: max |S - S64| = {err:.2e}, delta = {delta:.2e}")
+    assert err <= delta / 16
