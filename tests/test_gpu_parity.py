@@ -243,3 +243,14 @@ def test_ranking_of_a_rerank(gpu_lib):
             prev = dref[qi, oref[qi, pos - 1]] if pos else -np.inf
             if b - a > 1e-5 and a - prev > 1e-5:
                 assert rk[qi, pos] == oref[qi, pos]
+
+
+@pytest.mark.parametrize("layers", [64, 256])
+@pytest.mark.parametrize("final_prec", ["f32", "sparse"])
+def test_many_layers(gpu_lib, layers, final_prec):
+    # Table 2 runs up to 256 layers: rows are renormalised after every layer,
+    # so rounding does not grow with depth; the sparse layers turn dense once
+    # their supports outgrow the slots, on the device
+    x = synth.random_features(300, 32, seed=layers, n_ids=6)
+    mx, mean, excused = _check_full(gpu_lib, x, 60, 12, 5, layers, final_prec=final_prec)
+    print(f"L={layers} {final_prec}: max err {mx:.2e} mean {mean:.2e} excused {excused}")
