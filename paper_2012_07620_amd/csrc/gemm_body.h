@@ -93,6 +93,76 @@ struct GemmArgs {
   int64_t ldo;  // floats
 };
 
+// Similarity epilogue of tile (tm, tn) from its accumulators (EPI_SIM_SYM or
+// EPI_SIM_SYM16); uses `lds` (sim_lds_bytes(EPI)) and block barriers.
+template <int EPI>
+__device__ __forceinline__ void sim_epilogue(const GemmArgs& g, int tm, int tn, const f32x16 (&acc)[2][2],
+                                             uint8_t* lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = tm * BM, n0 = tn * BN;
+  // Similarity: the scaled tile is staged row-major in LDS (free after the
+  // loop's last barrier) in the output type (binary16 values are rounded
+  // here, once, as a direct store would), then written with 16-byte stores
+  // per lane: rows of the tile at (tm, tn) and, off the diagonal, rows of
+  // its transpose at (tn, tm) (lanes along the tile's columns, each
+  // gathering one 16-byte run of a transposed row). Zeros stand in outside
+  // M x Nn and are not stored.
+  constexpr bool H16 = (EPI == EPI_SIM_SYM16);
+  using OT = typename std::conditional<H16, _Float16, float>::type;
+  constexpr int V = 16 / (int)sizeof(OT);  // elements per 16-byte store
+  constexpr int TS = BN + V;               // staged row stride (16-byte aligned rows)
+  static_assert(BM * TS * (int)sizeof(OT) <= sim_lds_bytes(EPI), "staged tile must fit the similarity LDS");
+  typedef OT ov __attribute__((ext_vector_type(V)));
+  OT* T = (OT*)lds;
+#pragma unroll
+  for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+    for (int sn = 0; sn < 2; sn++) {
+      const int lc = wn * 64 + sn * 32 + (lane & 31);
+      const int col = n0 + lc;
+      const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int row = m0 + lr;
+        T[lr * TS + lc] = (OT)((row < g.M && col < g.Nn) ? acc[sm][sn][r] * g.sa[row] * scol + 0.0f : 0.f);
+      }
+    }
+  __syncthreads();
+  constexpr int CPR = BN / V;           // 16-byte chunks per tile row
+  constexpr int RPP = 256 / CPR;        // tile rows per pass
+  OT* out = (OT*)g.out;                 // ldo counts elements of the output type
+  const bool vec = (((uintptr_t)g.out & 15) == 0) && (g.ldo % V == 0);
+  auto put = [&](int64_t row, int col0, int lim, const ov& v) {  // V values at (row, col0..), cols < lim
+    if (vec && col0 + V <= lim) {
+      *(ov*)(out + row * g.ldo + col0) = v;
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; e++)
+        if (col0 + e < lim) out[row * g.ldo + col0 + e] = v[e];
+    }
+  };
+  // the tile: lanes along a row
+  for (int lr = tid / CPR; lr < BM; lr += RPP) {
+    const int row = m0 + lr;
+    if (row >= g.M) continue;
+    const int ch = tid % CPR;
+    put(row, n0 + ch * V, g.Nn, *(const ov*)(T + lr * TS + ch * V));
+  }
+  if (tm != tn) {  // the transpose: lane = tile column, one V-run of tile rows each
+    const int lc = tid & 127;
+    const int row = n0 + lc;
+    if (row < g.Nn)
+      for (int ch = tid >> 7; ch < BM / V; ch += 2) {
+        ov v;
+#pragma unroll
+        for (int e = 0; e < V; e++) v[e] = T[(ch * V + e) * TS + lc];
+        put(row, m0 + ch * V, g.M, v);
+      }
+  }
+}
+
 // LDS bytes of one stage buffer pair (A and B) holding KS 128-byte K slices.
 __host__ __device__ constexpr int gemm_stage_lds(int ks) { return 2 * BM * (ks * BKB + 16); }
 
@@ -229,66 +299,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
       }
     __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
   } else {
-    // Similarity: the scaled tile is staged row-major in LDS (free after the
-    // loop's last barrier) in the output type (binary16 values are rounded
-    // here, once, as a direct store would), then written with 16-byte stores
-    // per lane: rows of the tile at (tm, tn) and, off the diagonal, rows of
-    // its transpose at (tn, tm) (lanes along the tile's columns, each
-    // gathering one 16-byte run of a transposed row). Zeros stand in outside
-    // M x Nn and are not stored.
-    constexpr bool H16 = (EPI == EPI_SIM_SYM16);
-    using OT = typename std::conditional<H16, _Float16, float>::type;
-    constexpr int V = 16 / (int)sizeof(OT);  // elements per 16-byte store
-    constexpr int TS = BN + V;               // staged row stride (16-byte aligned rows)
-    static_assert(BM * TS * (int)sizeof(OT) <= sim_lds_bytes(EPI), "staged tile must fit the similarity LDS");
-    typedef OT ov __attribute__((ext_vector_type(V)));
-    OT* T = (OT*)lds;
-#pragma unroll
-    for (int sm = 0; sm < 2; sm++)
-#pragma unroll
-      for (int sn = 0; sn < 2; sn++) {
-        const int lc = wn * 64 + sn * 32 + (lane & 31);
-        const int col = n0 + lc;
-        const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
-#pragma unroll
-        for (int r = 0; r < 16; r++) {
-          const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-          const int row = m0 + lr;
-          T[lr * TS + lc] = (OT)((row < g.M && col < g.Nn) ? acc[sm][sn][r] * g.sa[row] * scol + 0.0f : 0.f);
-        }
-      }
-    __syncthreads();
-    constexpr int CPR = BN / V;           // 16-byte chunks per tile row
-    constexpr int RPP = 256 / CPR;        // tile rows per pass
-    OT* out = (OT*)g.out;                 // ldo counts elements of the output type
-    const bool vec = (((uintptr_t)g.out & 15) == 0) && (g.ldo % V == 0);
-    auto put = [&](int64_t row, int col0, int lim, const ov& v) {  // V values at (row, col0..), cols < lim
-      if (vec && col0 + V <= lim) {
-        *(ov*)(out + row * g.ldo + col0) = v;
-      } else {
-#pragma unroll
-        for (int e = 0; e < V; e++)
-          if (col0 + e < lim) out[row * g.ldo + col0 + e] = v[e];
-      }
-    };
-    // the tile: lanes along a row
-    for (int lr = tid / CPR; lr < BM; lr += RPP) {
-      const int row = m0 + lr;
-      if (row >= g.M) continue;
-      const int ch = tid % CPR;
-      put(row, n0 + ch * V, g.Nn, *(const ov*)(T + lr * TS + ch * V));
-    }
-    if (tm != tn) {  // the transpose: lane = tile column, one V-run of tile rows each
-      const int lc = tid & 127;
-      const int row = n0 + lc;
-      if (row < g.Nn)
-        for (int ch = tid >> 7; ch < BM / V; ch += 2) {
-          ov v;
-#pragma unroll
-          for (int e = 0; e < V; e++) v[e] = T[(ch * V + e) * TS + lc];
-          put(row, m0 + ch * V, g.M, v);
-        }
-    }
+    sim_epilogue<EPI>(g, tm, tn, acc, lds);
     __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
   }
 }
@@ -315,6 +326,27 @@ __device__ __forceinline__ void gemm_fix_tile(const GemmArgs& g, int tm, int tn,
         if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = 1.0f - g.sa[row] * scol * v;
       }
     }
+}
+
+// Tail tile (tm, tn) of a similarity product computed as `parts` K ranges:
+// the partial tiles summed in range order, then the similarity epilogue.
+template <int EPI>
+__device__ __forceinline__ void gemm_sim_fix_tile(const GemmArgs& g, int tm, int tn, const float* __restrict__ part,
+                                                  int parts, uint8_t* lds) {
+  const int tid = threadIdx.x;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+    for (int sn = 0; sn < 2; sn++)
+#pragma unroll 4
+      for (int r = 0; r < 16; r++) {
+        const int at = ((sm * 2 + sn) * 16 + r) * 256 + tid;
+        float v = part[at];
+        for (int k = 1; k < parts; k++) v += part[(int64_t)k * BM * BN + at];
+        acc[sm][sn][r] = v;
+      }
+  sim_epilogue<EPI>(g, tm, tn, acc, lds);
 }
 
 // ---------------------------------------------------------------- bf16x3

@@ -50,6 +50,28 @@ void gemm_nt_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   gemm_tile<MODE, EPI, 1, KS>(g, tm, tn, lds);
 }
 
+// K ranges per tile (at most max_parts) of a partly filled last round of
+// `tiles` tiles on `slots` resident workgroups: the fewest partial rounds per
+// tile, needing a saving of at least a fifth of a round, at least 8 K stages
+// per range and room for the partial tiles in ws_bytes; 1 = no split. *rem
+// receives the number of tail tiles.
+static int tail_parts(int64_t tiles, int slots, int nst, int64_t tile_bytes, int64_t ws_bytes, int max_parts,
+                      int64_t* rem) {
+  *rem = 0;
+  if (slots <= 0 || tiles <= slots) return 1;
+  *rem = tiles % slots;
+  int parts = 1;
+  double best = 1.0;
+  for (int p = 2; p <= max_parts; p++) {
+    const double cost = (double)((*rem * p + slots - 1) / slots) / p;
+    if (cost < best - 1e-9 && nst >= 8 * p && *rem * p * tile_bytes <= ws_bytes) {
+      best = cost;
+      parts = p;
+    }
+  }
+  return (best > 0.8 || *rem == 0) ? 1 : parts;
+}
+
 template <int MODE, int EPI>
 static hipError_t launch_gemm_t(const void* a, int M, int64_t lda, const void* b, int Nn, int64_t ldb, int64_t kbytes,
                                 const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s) {
@@ -62,21 +84,87 @@ static hipError_t launch_gemm_t(const void* a, int M, int64_t lda, const void* b
   return hipGetLastError();
 }
 
+// Tail of a similarity product split along K, as for the final product:
+// partial tiles of the last round's upper-triangle tiles (logical tiles
+// first..), summed in range order by sim_fix_kernel, which applies the
+// similarity epilogue (tile and mirror).
+template <int MODE>
+__global__ __launch_bounds__(256) void sim_part_kernel(GemmArgs g, int tiles, int first, int parts,
+                                                       float* __restrict__ ws) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[gemm_stage_lds(SIM_KS)];
+  const int w = xcd_linear(blockIdx.x, gridDim.x);
+  const int k = w % parts;
+  int tm, tn;
+  upper_tile(first + w / parts, tiles, tm, tn);
+  GemmArgs gp = g;
+  gp.out = ws + (int64_t)w * BM * BN;
+  const int64_t nsk = g.nst / SIM_KS;
+  gemm_tile<MODE, EPI_PART, 1, SIM_KS>(gp, tm, tn, lds, (int)(k * nsk / parts * SIM_KS),
+                                       (int)((k + 1) * nsk / parts * SIM_KS));
+}
+
+template <int EPI>
+__global__ __launch_bounds__(256) void sim_fix_kernel(GemmArgs g, int tiles, int first, int parts,
+                                                      const float* __restrict__ ws) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[sim_lds_bytes(EPI)];
+  int tm, tn;
+  upper_tile(first + (int)blockIdx.x, tiles, tm, tn);
+  gemm_sim_fix_tile<EPI>(g, tm, tn, ws + (int64_t)blockIdx.x * parts * BM * BN, parts, lds);
+}
+
+// Resident workgroups of a similarity kernel (per instantiation, queried once
+// per process on the current device; thread-safe initialisation).
+template <int MODE, int EPI>
+static int sim_slots() {
+  static const int slots = [] {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)gemm_nt_kernel<MODE, EPI>, 256, 0) !=
+            hipSuccess)
+      return 0;
+    return cus * per;
+  }();
+  return slots;
+}
+
+template <int MODE, int EPI>
+static hipError_t launch_sim_t(const void* a, int M, int64_t lda, int64_t kbytes, const float* sa, float* out,
+                               int64_t ldo, float* ws, int64_t ws_bytes, hipStream_t s) {
+  const int T = (M + BM - 1) / BM;
+  const int64_t nwg = (int64_t)T * (T + 1) / 2;
+  if (nwg <= 0 || nwg > 0x7FFFFFFF || kbytes % (BKB * SIM_KS) || kbytes <= 0) return hipErrorInvalidValue;
+  const int nst = (int)(kbytes / BKB);
+  int64_t rem = 0;
+  // at most two ranges: a similarity tile is short, so summing more partials
+  // in the fix-up costs more than the finer split saves
+  const int parts =
+      ws ? tail_parts(nwg, sim_slots<MODE, EPI>(), nst / SIM_KS, (int64_t)BM * BN * 4, ws_bytes, 2, &rem) : 1;
+  if (parts == 1)
+    return launch_gemm_t<MODE, EPI>(a, M, lda, a, M, lda, kbytes, sa, sa, out, ldo, s);
+  const int64_t first = nwg - rem;
+  GemmArgs g{(const uint8_t*)a, (const uint8_t*)a, M, M, lda, lda, nst, sa, sa, out, ldo};
+  hipLaunchKernelGGL((gemm_nt_kernel<MODE, EPI>), dim3((unsigned)first), dim3(256), 0, s, g, T, T);
+  hipLaunchKernelGGL((sim_part_kernel<MODE>), dim3((unsigned)(rem * parts)), dim3(256), 0, s, g, T, (int)first, parts,
+                     ws);
+  hipLaunchKernelGGL((sim_fix_kernel<EPI>), dim3((unsigned)rem), dim3(256), 0, s, g, T, (int)first, parts,
+                     (const float*)ws);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes, const float* sa,
-                           void* out, int64_t ldo, bool half_out, hipStream_t s) {
+                           void* out, int64_t ldo, bool half_out, float* ws, int64_t ws_bytes, hipStream_t s) {
   float* o = (float*)out;
   if (half_out && prec == SimPrec::F32) return hipErrorInvalidValue;  // the FP32 path keeps S exact
   switch (prec) {
     case SimPrec::F32:
-      return launch_gemm_t<MODE_F32, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, o, ldo, s);
+      return launch_sim_t<MODE_F32, EPI_SIM_SYM>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s);
     case SimPrec::BF16:
-      return half_out
-                 ? launch_gemm_t<MODE_BF16, EPI_SIM_SYM16>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, o, ldo, s)
-                 : launch_gemm_t<MODE_BF16, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, o, ldo, s);
+      return half_out ? launch_sim_t<MODE_BF16, EPI_SIM_SYM16>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s)
+                      : launch_sim_t<MODE_BF16, EPI_SIM_SYM>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s);
     case SimPrec::FP8:
-      return half_out
-                 ? launch_gemm_t<MODE_FP8, EPI_SIM_SYM16>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, o, ldo, s)
-                 : launch_gemm_t<MODE_FP8, EPI_SIM_SYM>(a, M, lda_bytes, a, M, lda_bytes, kbytes, sa, sa, o, ldo, s);
+      return half_out ? launch_sim_t<MODE_FP8, EPI_SIM_SYM16>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s)
+                      : launch_sim_t<MODE_FP8, EPI_SIM_SYM>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s);
   }
   return hipErrorInvalidValue;
 }
@@ -107,26 +195,6 @@ __global__ __launch_bounds__(256) void gemm_fix_kernel(GemmArgs g, int tiles_m, 
   gemm_fix_tile(g, t.tm, t.tn, ws + (int64_t)w * parts * BM * BN, parts);
 }
 
-// K ranges per tile of a partly filled last round of `tiles` tiles on
-// `slots` resident workgroups: the fewest partial rounds per tile, needing a
-// saving of at least a fifth of a round, at least 8 K stages per range and
-// room for the partial tiles in ws_bytes; 1 = no split. *rem receives the
-// number of tail tiles.
-static int tail_parts(int64_t tiles, int slots, int nst, int64_t ws_bytes, int64_t* rem) {
-  *rem = 0;
-  if (slots <= 0 || tiles <= slots) return 1;
-  *rem = tiles % slots;
-  int parts = 1;
-  double best = 1.0;
-  for (int p = 2; p <= 8; p++) {
-    const double cost = (double)((*rem * p + slots - 1) / slots) / p;
-    if (cost < best - 1e-9 && nst >= 8 * p && *rem * p * BM * BN * 4 <= ws_bytes) {
-      best = cost;
-      parts = p;
-    }
-  }
-  return (best > 0.8 || *rem == 0) ? 1 : parts;
-}
 
 // Resident workgroups of the FP32 final product (queried once per process,
 // on the device current at the first call; thread-safe initialisation).
@@ -152,7 +220,8 @@ hipError_t launch_gemm_dist(const float* a, int M, const float* b, int Nn, int64
   const int nst = (int)(kelems * 4 / BKB);
   if (nst % DIST_KS) return hipErrorInvalidValue;  // K is padded to whole LDS stages
   int64_t rem = 0;
-  const int parts = (kelems * 4 % BKB == 0) ? tail_parts(tiles, slots, nst, ws_bytes, &rem) : 1;
+  const int parts =
+      (kelems * 4 % BKB == 0) ? tail_parts(tiles, slots, nst, (int64_t)BM * BN * 4, ws_bytes, 8, &rem) : 1;
   if (parts == 1)
     return launch_gemm_t<MODE_F32, EPI_DIST>(a, M, ld_elems * 4, b, Nn, ld_elems * 4, kelems * 4, sa, sb, out, ldo, s);
   if (tiles > 0x7FFFFFFF || rem * parts > 0x7FFFFFFF) return hipErrorInvalidValue;

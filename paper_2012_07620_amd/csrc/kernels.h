@@ -64,9 +64,12 @@ hipError_t launch_prep(const void* x, int in_bf16, int n, int d, float* xp, int6
 // elements: FP32, or binary16 (round to nearest even) with half_out, which
 // the low-precision paths use (their S only ranks candidates that are then
 // re-scored in FP32; binary16 rounding, at most 2^-11 relative, is below the
-// error of the BF16 / FP8 product itself) to halve S's bytes.
+// error of the BF16 / FP8 product itself) to halve S's bytes. ws (ws_bytes,
+// may be null): scratch for splitting the last, partly filled round of tiles
+// along K (fixed ranges summed in order: deterministic).
 hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes,
-                           const float* sa, void* out, int64_t ldo, bool half_out, hipStream_t s);
+                           const float* sa, void* out, int64_t ldo, bool half_out, float* ws, int64_t ws_bytes,
+                           hipStream_t s);
 // Final epilogue: out[q][g] = 1 - sa[q] * sb[g] * acc, ldo floats.
 // Final product, D = 1 - sa[i] * sb[j] * acc. ws (ws_bytes, may be null):
 // scratch for splitting the last, partly filled round of tiles along K.

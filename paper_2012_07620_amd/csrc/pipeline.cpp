@@ -93,10 +93,15 @@ hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipS
   RR_TRY(launch_prep(x, in_bf16, P.n, P.d, xp, P.ldp, rn, P.prec, xl, P.ldl, sl, s));
   RR_STAGE(RERANK_STAGE_PREP, 1);
   RR_STAGE(RERANK_STAGE_SIMILARITY, 0);
+  // the feature buffer B (not yet in use) holds the partial tiles of a K-split
+  // last round; none for problems the serving path batches (as for the final)
+  float* sws = (P.o_b && P.n > kGroupedMaxN) ? at<float>(ws, P.o_b) : nullptr;
+  const int64_t sws_bytes = sws ? (int64_t)P.n * P.ldH * 4 : 0;
   if (P.prec == SimPrec::F32)
-    RR_TRY(launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, S, P.ldN, false, s));
+    RR_TRY(launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, S, P.ldN, false, sws, sws_bytes, s));
   else
-    RR_TRY(launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, S, P.ldN, true, s));
+    RR_TRY(launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, S, P.ldN, true, sws, sws_bytes,
+                           s));
   RR_STAGE(RERANK_STAGE_SIMILARITY, 1);
   RR_STAGE(RERANK_STAGE_TOPK, 0);
   RR_TRY(launch_topk(S, P.prec != SimPrec::F32, P.ldN, P.n, P.n, P.kc, ci, cv, P.kc, s));

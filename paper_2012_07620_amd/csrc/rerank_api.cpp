@@ -292,9 +292,9 @@ rerank_status rerank_similarity(rerank_ctx* ctx, const rerank_params* p, const v
       return e;
     }
     if (P.prec == SimPrec::F32)
-      e = launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, d_s, ld_s, false, s);
+      e = launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, d_s, ld_s, false, nullptr, 0, s);
     else
-      e = launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, d_s, ld_s, false, s);
+      e = launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, d_s, ld_s, false, nullptr, 0, s);
     if (e != hipSuccess) *where = "launch_gemm_sim";
     return e;
   });
