@@ -262,7 +262,8 @@ def main() -> int:
         for name, prec, fprec in (("bf16", "bf16", "f32"), ("fp8", "fp8", "f32"),
                                   ("f32_final_bf16x3", "f32", "bf16x3"), ("bf16_final_bf16x3", "bf16", "bf16x3"),
                                   ("f32_final_sparse", "f32", "sparse"), ("bf16_final_sparse", "bf16", "sparse"),
-                                  ("fp8_final_sparse", "fp8", "sparse")):
+                                  ("fp8_final_sparse", "fp8", "sparse"), ("bf16_final_bf16", "bf16", "bf16"),
+                                  ("fp8_final_bf16", "fp8", "bf16")):
             if args.variants and name not in args.variants.split(","):
                 continue
             log(f"timing {name} path")
@@ -278,6 +279,10 @@ def main() -> int:
                 entry["final_roofline"] = {"bound": "mfma", "achieved": fl, "peak": PEAK["bf16_mfma_tflops"] / 3,
                                            "unit": "TFLOP/s (FP32-equivalent; 3 bf16 products per FP32 product)",
                                            "frac": fl / (PEAK["bf16_mfma_tflops"] / 3)}
+            if fprec == "bf16":
+                fl = wl["final"][1] / (st_l["final"] * 1e-3) / 1e12
+                entry["final_roofline"] = {"bound": "mfma", "achieved": fl, "peak": PEAK["bf16_mfma_tflops"],
+                                           "unit": "TFLOP/s", "frac": fl / PEAK["bf16_mfma_tflops"]}
             if fprec == "sparse":
                 # the rows reach the product as CSR (a few hundred bytes each), so the floor is writing D once
                 nbytes = 4.0 * spec.n_query * spec.n_gallery

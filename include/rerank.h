@@ -74,7 +74,10 @@ typedef enum { RERANK_NODE_ADJ_SYM = 0, RERANK_NODE_RAW = 1, RERANK_NODE_ADJ = 2
 typedef enum { RERANK_AGG_SUM = 0, RERANK_AGG_MEAN = 1, RERANK_AGG_MAX = 2 } rerank_aggregator;
 
 /* Arithmetic of the final query x gallery product. F32 is plain FP32 matrix
- * cores; BF16X3 splits each FP32 operand into a high and a low bfloat16 part
+ * cores; BF16 rounds the refined features to bfloat16 (nearest even) and
+ * multiplies them on bfloat16 matrix cores with FP32 accumulation, scaled by
+ * the FP32 inverse norms (cosine error below 2^-7: a low-precision mode, for
+ * the low-precision similarity paths); BF16X3 splits each FP32 operand into a high and a low bfloat16 part
  * and sums the three leading partial products on bfloat16 matrix cores with
  * FP32 accumulation (relative error of each product about 2^-16). SPARSE
  * multiplies only the non-zeros of the refined features: A* rows hold O(k1)
@@ -89,7 +92,12 @@ typedef enum { RERANK_AGG_SUM = 0, RERANK_AGG_MEAN = 1, RERANK_AGG_MAX = 2 } rer
  * before the product; when the compacted rows would exceed the spare N x N
  * buffer (average row density above 1/4) the FP32 matrix-core product runs
  * instead. All of these choices are made on the device. */
-typedef enum { RERANK_FINAL_F32 = 0, RERANK_FINAL_BF16X3 = 1, RERANK_FINAL_SPARSE = 2 } rerank_final_prec;
+typedef enum {
+  RERANK_FINAL_F32 = 0,
+  RERANK_FINAL_BF16X3 = 1,
+  RERANK_FINAL_SPARSE = 2,
+  RERANK_FINAL_BF16 = 3
+} rerank_final_prec;
 
 typedef struct {
   int32_t n;          /* N = Q + G rows of X_u, N >= 2 */

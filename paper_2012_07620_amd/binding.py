@@ -20,7 +20,7 @@ IN_F32, IN_BF16 = 0, 1
 SIM = {"f32": 0, "bf16": 1, "fp8": 2}
 NODE = {"adj": 0, "raw": 1, "adj_raw": 2}
 AGG = {"sum": 0, "mean": 1, "max": 2}
-FINAL = {"f32": 0, "bf16x3": 1, "sparse": 2}
+FINAL = {"f32": 0, "bf16x3": 1, "sparse": 2, "bf16": 3}
 
 EXPORTS = (
     "rerank_default_params", "rerank_validate", "rerank_workspace_bytes", "rerank_create", "rerank_destroy",

@@ -36,7 +36,7 @@ template <int MODE, int EPI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_FP8 && EPI == EPI_SIM_SYM16 ? 3 : 1)))
 void gemm_nt_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   constexpr bool SYM = EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16;
-  constexpr int KS = EPI == EPI_DIST ? DIST_KS : SYM ? SIM_KS : 1;
+  constexpr int KS = (EPI == EPI_DIST && MODE == MODE_F32) ? DIST_KS : SYM ? SIM_KS : 1;
   __shared__ __attribute__((aligned(16))) uint8_t lds[SYM ? sim_lds_bytes(EPI) : gemm_stage_lds(KS)];
   const int pid = xcd_linear(blockIdx.x, gridDim.x);
   int tm, tn;
@@ -77,7 +77,9 @@ static hipError_t launch_gemm_t(const void* a, int M, int64_t lda, const void* b
                                 const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s) {
   const int tm = (M + BM - 1) / BM, tn = (Nn + BN - 1) / BN;
   const int64_t nwg = (EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16) ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tm * tn;
-  constexpr int KS = EPI == EPI_DIST ? DIST_KS : (EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16) ? SIM_KS : 1;
+  constexpr int KS = (EPI == EPI_DIST && MODE == MODE_F32) ? DIST_KS
+                     : (EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16) ? SIM_KS
+                                                                   : 1;
   if (nwg <= 0 || nwg > 0x7FFFFFFF || kbytes % (BKB * KS) || kbytes <= 0) return hipErrorInvalidValue;
   GemmArgs g{(const uint8_t*)a, (const uint8_t*)b, M, Nn, lda, ldb, (int)(kbytes / BKB), sa, sb, out, ldo};
   hipLaunchKernelGGL((gemm_nt_kernel<MODE, EPI>), dim3((unsigned)nwg), dim3(256), 0, s, g, tm, tn);
@@ -238,6 +240,13 @@ __global__ __launch_bounds__(256) void gemm_x3_kernel(GemmX3Args g, int tiles_m,
   extern __shared__ __attribute__((aligned(16))) uint8_t lds_x3[];
   const TileMap t = grouped_order(xcd_linear(blockIdx.x, gridDim.x), tiles_m, tiles_n);
   gemm_tile_x3(g, t.tm, t.tn, lds_x3);
+}
+
+hipError_t launch_gemm_dist_bf16(const uint16_t* a, int M, const uint16_t* b, int Nn, int64_t ld_elems,
+                                 int64_t kelems, const float* sa, const float* sb, float* out, int64_t ldo,
+                                 hipStream_t s) {
+  if (kelems % 64 || ld_elems % 64) return hipErrorInvalidValue;  // whole 128-byte bf16 slices
+  return launch_gemm_t<MODE_BF16, EPI_DIST>(a, M, ld_elems * 2, b, Nn, ld_elems * 2, kelems * 2, sa, sb, out, ldo, s);
 }
 
 // Raises the dynamic-LDS limit of gemm_x3_kernel once per process

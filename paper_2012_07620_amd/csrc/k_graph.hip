@@ -313,7 +313,7 @@ __global__ void split_bf16_kernel(const float* __restrict__ h, int64_t total, ui
     const float v = h[t];
     const uint16_t a = bf16_rne(v);
     hi[t] = a;
-    lo[t] = bf16_rne(v - __uint_as_float((uint32_t)a << 16));
+    if (lo) lo[t] = bf16_rne(v - __uint_as_float((uint32_t)a << 16));
   }
 }
 

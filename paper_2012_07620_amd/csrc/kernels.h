@@ -7,7 +7,7 @@
 namespace rr {
 
 enum class SimPrec : int { F32 = 0, BF16 = 1, FP8 = 2 };
-enum class FinalPrec : int { F32 = 0, BF16X3 = 1, SPARSE = 2 };
+enum class FinalPrec : int { F32 = 0, BF16X3 = 1, SPARSE = 2, BF16 = 3 };
 
 // Sparse layers (used with the sparse final product): every propagated row is
 // stored as CSR entries (columns ascending) in a slot of the layer's output
@@ -76,6 +76,11 @@ hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes
 hipError_t launch_gemm_dist(const float* a, int M, const float* b, int Nn, int64_t ld_elems, int64_t kelems,
                             const float* sa, const float* sb, float* out, int64_t ldo, float* ws, int64_t ws_bytes,
                             hipStream_t s);
+// Final product on bfloat16 operands (rows rounded to bf16, row stride
+// ld_elems, K = kelems): D = 1 - sa[i] * sb[j] * acc, FP32 accumulation.
+hipError_t launch_gemm_dist_bf16(const uint16_t* a, int M, const uint16_t* b, int Nn, int64_t ld_elems,
+                                 int64_t kelems, const float* sa, const float* sb, float* out, int64_t ldo,
+                                 hipStream_t s);
 hipError_t launch_gemm_dist_bf16x3(const uint16_t* a_hi, const uint16_t* a_lo, int M, const uint16_t* b_hi,
                                    const uint16_t* b_lo, int Nn, int64_t ld_elems, int64_t kelems,
                                    const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s);

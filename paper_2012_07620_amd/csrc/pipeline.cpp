@@ -146,7 +146,7 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
   float* kv = at<float>(ws, P.o_kv);
   float* sa = at<float>(ws, P.o_sa);
   float* sb = at<float>(ws, P.o_sb);
-  uint16_t* hi = P.fprec == FinalPrec::BF16X3 ? at<uint16_t>(ws, P.o_hi) : nullptr;
+  uint16_t* hi = (P.fprec == FinalPrec::BF16X3 || P.fprec == FinalPrec::BF16) ? at<uint16_t>(ws, P.o_hi) : nullptr;
   uint16_t* lo = P.fprec == FinalPrec::BF16X3 ? at<uint16_t>(ws, P.o_lo) : nullptr;
 
   const float* cur;
@@ -251,6 +251,9 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
       RR_TRY(launch_sparse_final(cur, P.n, P.q, P.ldH, csig, dist, pool, (int64_t)P.n * P.ldH * 4,
                                  at<int32_t>(ws, P.o_sp), nullptr, nullptr, ki, P.k1, s));
     }
+  } else if (P.fprec == FinalPrec::BF16) {  // the last layer wrote the rows rounded to bfloat16
+    if (P.layers == 0) RR_TRY(launch_split_bf16(cur, P.n, P.ldH, hi, nullptr, s));
+    RR_TRY(launch_gemm_dist_bf16(hi, P.q, hi + (size_t)P.q * P.ldH, P.g, P.ldH, P.ldH, csig, csig + P.q, dist, P.g, s));
   } else {
     if (P.layers == 0) RR_TRY(launch_split_bf16(cur, P.n, P.ldH, hi, lo, s));
     RR_TRY(launch_gemm_dist_bf16x3(hi, lo, P.q, hi + (size_t)P.q * P.ldH, lo + (size_t)P.q * P.ldH, P.g, P.ldH,

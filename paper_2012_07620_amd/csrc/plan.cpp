@@ -21,7 +21,7 @@ rerank_status validate_params(const rerank_params* p, std::string* why) {
   if (p->node != RERANK_NODE_ADJ_SYM && p->node != RERANK_NODE_RAW && p->node != RERANK_NODE_ADJ)
     return bad(why, "unknown node mode");
   if (p->aggregator < RERANK_AGG_SUM || p->aggregator > RERANK_AGG_MAX) return bad(why, "unknown aggregator");
-  if (p->final_prec < RERANK_FINAL_F32 || p->final_prec > RERANK_FINAL_SPARSE) return bad(why, "unknown final_prec");
+  if (p->final_prec < RERANK_FINAL_F32 || p->final_prec > RERANK_FINAL_BF16) return bad(why, "unknown final_prec");
   if (p->final_prec == RERANK_FINAL_SPARSE && p->node == RERANK_NODE_RAW)
     return bad(why, "the sparse final product needs adjacency node features (node != RAW)");
   if (p->extra_cand < -1) return bad(why, "extra_cand must be >= -1");
@@ -100,10 +100,8 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o, bool dense_layers
       P.o_slg = take((size_t)(P.layers + 1) * sizeof(SlGate));
       P.o_slr = take(2 * (2 * n + 4) * 4);  // row starts (n + 1) and counts (n) of two layers
     }
-    if (P.fprec == FinalPrec::BF16X3) {
-      P.o_hi = take(n * P.ldH * 2);
-      P.o_lo = take(n * P.ldH * 2);
-    }
+    if (P.fprec == FinalPrec::BF16X3 || P.fprec == FinalPrec::BF16) P.o_hi = take(n * P.ldH * 2);
+    if (P.fprec == FinalPrec::BF16X3) P.o_lo = take(n * P.ldH * 2);
   }
   P.total = off;
 }

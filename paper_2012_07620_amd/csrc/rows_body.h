@@ -355,7 +355,7 @@ __device__ __forceinline__ void split_store4(uint16_t* __restrict__ hi, uint16_t
     l4[e] = bf16_rne(acc[e] - __uint_as_float((uint32_t)h4[e] << 16));
   }
   *(uint2*)(hi + at) = make_uint2(h4[0] | ((uint32_t)h4[1] << 16), h4[2] | ((uint32_t)h4[3] << 16));
-  *(uint2*)(lo + at) = make_uint2(l4[0] | ((uint32_t)l4[1] << 16), l4[2] | ((uint32_t)l4[3] << 16));
+  if (lo) *(uint2*)(lo + at) = make_uint2(l4[0] | ((uint32_t)l4[1] << 16), l4[2] | ((uint32_t)l4[3] << 16));
 }
 
 // Coefficients of row i. Message r is e_ir^alpha h_{j_r} (member 0 is the row

@@ -92,7 +92,7 @@ def test_null_arguments_are_rejected_without_a_device():
 
 def test_unknown_enums_rejected():
     lib = binding.library()
-    for field, bad in (("aggregator", 3), ("node", 3), ("sim_prec", 3), ("final_prec", 3), ("final_prec", -1)):
+    for field, bad in (("aggregator", 3), ("node", 3), ("sim_prec", 3), ("final_prec", 4), ("final_prec", -1)):
         p = _p()
         setattr(p, field, bad)
         assert lib.rerank_validate(ctypes.byref(p)) == binding.E_INVALID, field

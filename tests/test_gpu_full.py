@@ -31,6 +31,16 @@ def test_mid_final_bf16x3(gpu_lib, mid):
     assert err2.max() <= D_TOL["bf16"]
 
 
+def test_mid_final_bf16(gpu_lib, mid):
+    # bfloat16 final product (low-precision mode): the low-precision bar
+    p, ref = mid
+    for prec in ("bf16", "fp8"):
+        d, ki, kv = _gpu(p, prec, final_prec="bf16")
+        err = np.abs(d - ref.dist)
+        print(f"{prec} sim + bf16 final: D vs FP64 max {err.max():.3e} mean {err.mean():.3e}", flush=True)
+        assert err.max() <= D_TOL["bf16"]
+
+
 def test_mid_final_sparse(gpu_lib, mid):
     # sparse final product: same distances, FP32 tolerance
     p, ref = mid

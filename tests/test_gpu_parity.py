@@ -254,3 +254,28 @@ def test_many_layers(gpu_lib, layers, final_prec):
     x = synth.random_features(300, 32, seed=layers, n_ids=6)
     mx, mean, excused = _check_full(gpu_lib, x, 60, 12, 5, layers, final_prec=final_prec)
     print(f"L={layers} {final_prec}: max err {mx:.2e} mean {mean:.2e} excused {excused}")
+
+
+BF16_FINAL_CASES = [
+    # n, q, d, k1, k2, layers, node, sim
+    (1000, 100, 128, 10, 3, 1, "adj", "f32"),
+    (300, 100, 40, 12, 5, 0, "adj", "f32"),
+    (333, 33, 96, 20, 6, 2, "raw", "f32"),
+    (333, 33, 96, 20, 6, 0, "raw", "bf16"),
+    (2049, 333, 64, 20, 6, 2, "adj", "bf16"),
+    (5000, 700, 64, 20, 6, 1, "adj", "fp8"),
+]
+
+
+@pytest.mark.parametrize("n,q,d,k1,k2,layers,node,sim", BF16_FINAL_CASES)
+def test_final_bf16_within_low_precision_tolerance(gpu_lib, n, q, d, k1, k2, layers, node, sim):
+    # bfloat16 operands for the final product: a low-precision mode, held to
+    # the low-precision paths' bar (D within 2e-2 of the FP64 oracle); its
+    # error is bounded by about 2 * 2^-8 of |h_q| |h_g|
+    x = synth.random_features(n, d, seed=n + 3 * d + layers, n_ids=max(2, n // 20))
+    print(f"case bf16 final n={n} q={q} d={d} k1={k1} k2={k2} L={layers} node={node} sim={sim}", flush=True)
+    dg, ki, kv = _run(gpu_lib, x, q, k1, k2, layers, node=node, sim_prec=sim, final_prec="bf16")
+    ref = orc.rerank(x, q, k1, k2, layers, node=node)
+    err = np.abs(dg.astype(np.float64) - ref.dist)
+    print(f"bf16 final: D vs FP64 max {err.max():.2e} mean {err.mean():.2e}")
+    assert np.all(np.isfinite(dg)) and err.max() <= 2e-2
