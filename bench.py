@@ -259,18 +259,26 @@ def main() -> int:
 
     lowp = {}
     if not args.no_lowp:
+        ctx_fused = None  # similarity fused with the candidate selection (S never written)
         for name, prec, fprec in (("bf16", "bf16", "f32"), ("fp8", "fp8", "f32"),
                                   ("f32_final_bf16x3", "f32", "bf16x3"), ("bf16_final_bf16x3", "bf16", "bf16x3"),
                                   ("f32_final_sparse", "f32", "sparse"), ("bf16_final_sparse", "bf16", "sparse"),
                                   ("fp8_final_sparse", "fp8", "sparse"), ("bf16_final_bf16", "bf16", "bf16"),
-                                  ("fp8_final_bf16", "fp8", "bf16")):
+                                  ("fp8_final_bf16", "fp8", "bf16"), ("f32_fused_knn", "f32", "f32"),
+                                  ("bf16_fused_knn_final_sparse", "bf16", "sparse"),
+                                  ("fp8_fused_knn_final_sparse", "fp8", "sparse")):
             if args.variants and name not in args.variants.split(","):
                 continue
             log(f"timing {name} path")
+            fused = "_fused_knn" in name
+            if fused and ctx_fused is None:
+                ctx_fused = binding.Context(0, stage_timing=True, fused_knn=True)
             out_l = torch.empty_like(out)
-            ms_l, st_l = time_path(binding, torch, ctx, x, spec, prec, args.steps, args.warmup, out_l, fprec)
+            ms_l, st_l = time_path(binding, torch, ctx_fused if fused else ctx, x, spec, prec, args.steps, args.warmup,
+                                   out_l, fprec)
             wl = stage_work(spec, prec)
-            entry = {"similarity": prec, "final": fprec, "ms_per_request": ms_l, "value": spec.n ** 2 / (ms_l * 1e-3),
+            entry = {"similarity": prec, "final": fprec, "fused_knn": fused, "ms_per_request": ms_l,
+                     "value": spec.n ** 2 / (ms_l * 1e-3),
                      "speedup_vs_f32": ms / ms_l, "stages_ms": st_l,
                      "similarity_roofline": roofline_entry("similarity", *wl["similarity"], st_l["similarity"], prec),
                      "dist": out_l.cpu().numpy()}
@@ -291,7 +299,12 @@ def main() -> int:
                 entry["final_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
                                            "frac": gbs / PEAK["hbm_gbs"], "algorithmic_bytes": nbytes,
                                            "traffic": tr["bytes"] if tr else None, "traffic_detail": tr}
+            if fused:  # the similarity stage also selects the candidates; the full product is computed
+                entry["similarity_roofline"]["note"] = ("fused similarity + top-k: every tile of the N x N product "
+                                                        "(twice the symmetric product's flops), S never written")
             lowp[name] = entry
+        if ctx_fused is not None:
+            ctx_fused.close()
 
     quality = None
     if not args.no_quality:

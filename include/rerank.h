@@ -137,11 +137,22 @@ rerank_status rerank_workspace_bytes(const rerank_params* p, size_t* bytes);
  * rows and compact the last one before the product (the default keeps them as
  * CSR rows, see rerank_final_prec). The distances are the same either way. */
 #define RERANK_CTX_DENSE_LAYERS 2u
+/* FUSED_KNN (the similarity product fused with the candidate selection of
+ * Eq. 8): rerank_knn and rerank_run select each row's k1 + extra_cand
+ * candidates in the product's epilogue, so the N x N similarity S is never
+ * written; rerank_knn then needs no N x N buffer at all (its working set is
+ * the feature copies and O(N * (k1 + extra_cand)) lists). Every tile of the
+ * full N x N product is computed (no symmetric halving), so the product does
+ * twice the flops. The selected lists follow the same order and tie rule;
+ * with re-scoring they match the unfused path's. Requires
+ * k1 + extra_cand <= 64 (else RERANK_E_UNSUPPORTED). The serving calls
+ * (rerank_submit) ignore it. */
+#define RERANK_CTX_FUSED_KNN 4u
 
 /* Create a context on HIP device `hip_device`. The context never holds more
  * than `hbm_budget_bytes` of device memory (0 = 90% of the device's free
- * memory at creation). flags: 0 or an OR of RERANK_CTX_STAGE_TIMING and
- * RERANK_CTX_DENSE_LAYERS. */
+ * memory at creation). flags: 0 or an OR of RERANK_CTX_STAGE_TIMING,
+ * RERANK_CTX_DENSE_LAYERS and RERANK_CTX_FUSED_KNN. */
 rerank_status rerank_create(rerank_ctx** out, int hip_device, size_t hbm_budget_bytes, uint32_t flags);
 
 /* Wait for all work of the context, stop its scheduler, free its memory. */

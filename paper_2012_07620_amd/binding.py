@@ -30,6 +30,7 @@ EXPORTS = (
 )
 CTX_STAGE_TIMING = 1
 CTX_DENSE_LAYERS = 2
+CTX_FUSED_KNN = 4
 STAGES = ("prep", "similarity", "topk", "rescore", "adjacency", "propagate", "final")
 
 
@@ -118,10 +119,11 @@ class Context:
     """A library context on one HIP device (owns the working memory)."""
 
     def __init__(self, device: int = 0, budget_bytes: int = 0, stage_timing: bool = False,
-                 dense_layers: bool = False):
+                 dense_layers: bool = False, fused_knn: bool = False):
         lib = library()
         h = ctypes.c_void_p()
-        flags = (CTX_STAGE_TIMING if stage_timing else 0) | (CTX_DENSE_LAYERS if dense_layers else 0)
+        flags = ((CTX_STAGE_TIMING if stage_timing else 0) | (CTX_DENSE_LAYERS if dense_layers else 0)
+                 | (CTX_FUSED_KNN if fused_knn else 0))
         _check(lib.rerank_create(ctypes.byref(h), device, budget_bytes, flags))
         self.handle = h
         self.device = device

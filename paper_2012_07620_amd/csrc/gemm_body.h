@@ -32,7 +32,9 @@ enum { MODE_F32 = 0, MODE_BF16 = 1, MODE_FP8 = 2 };
 // paths, whose S only ranks candidates that are then re-scored in FP32).
 // EPI_PART: no epilogue; the raw accumulators of a K range go to a 128 x 128
 // partial tile (g.out, tile-local layout) for a later fixed-order sum.
-enum { EPI_DIST = 1, EPI_SIM_SYM = 2, EPI_SIM_SYM16 = 3, EPI_PART = 4 };
+// EPI_KNN: the similarity tile is not stored; its values are merged into the
+// running top-K lists of the tile's rows (knn_epilogue).
+enum { EPI_DIST = 1, EPI_SIM_SYM = 2, EPI_SIM_SYM16 = 3, EPI_PART = 4, EPI_KNN = 5 };
 // LDS of a similarity tile (one stage buffer, reused for staging the output
 // tile): FP32 S needs 128 x 132 floats, binary16 S fits in the stage buffer.
 __host__ __device__ constexpr int sim_lds_bytes(int epi) {
@@ -160,6 +162,170 @@ __device__ __forceinline__ void sim_epilogue(const GemmArgs& g, int tm, int tn, 
         for (int e = 0; e < V; e++) v[e] = T[(ch * V + e) * TS + lc];
         put(row, m0 + ch * V, g.M, v);
       }
+  }
+}
+
+// ---------------------------------------------------------------- fused top-k
+// The fused similarity + top-K workgroup keeps, per tile row, its list of the
+// K best selection keys so far (descending, key 0 = empty) in its own slice
+// of the per-range list buffer in global memory (read and written only by the
+// wave that owns the row), and in LDS after the stage buffers (which also
+// stage each tile) the row's K-th key and list length, then K, the list
+// buffer's base and the range index.
+struct KnnShared {
+  uint64_t tau[BM];  // K-th key of each tile row's list (0 while shorter than K)
+  int have[BM];      // entries in each tile row's list
+  uint64_t* lists;   // per-range lists, [range][M][K]
+  int K, range;
+  int first;         // the current tile is the first of the range (lists empty)
+};
+__host__ __device__ constexpr int knn_stage_bytes(int mode) {
+  return mode == MODE_F32 ? GEMM_LDS_BYTES : GEMM_LDS_1BUF;  // FP32 or binary16 tile staging
+}
+__host__ __device__ constexpr int knn_lds_bytes(int mode) { return knn_stage_bytes(mode) + (int)sizeof(KnnShared); }
+constexpr int KNN_LIST = 64;  // largest K: one key per lane of the merging wave
+constexpr int KNN_RC = 8;     // rows whose filter and list loads are issued together
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Selection key of staged tile element (lr, c) for row i (0 outside the matrix).
+template <typename OT>
+__device__ __forceinline__ uint64_t knn_key(const OT* T, int TS, int lr, int i, int c, int n0, const GemmArgs& g) {
+  const int col = n0 + c;
+  if (i >= g.M || col >= g.Nn) return 0ull;
+  return col == i ? self_key((uint32_t)i) : sel_key((float)T[lr * TS + c], (uint32_t)col);
+}
+
+__device__ __forceinline__ uint64_t* knn_list(const KnnShared& ks, int i, int M) {
+  return ks.lists + ((int64_t)ks.range * M + i) * ks.K;
+}
+
+__device__ __forceinline__ void knn_set_row(KnnShared& ks, int lr, int n_new, uint64_t kth) {
+  if ((threadIdx.x & 63) == 0) {
+    ks.tau[lr] = n_new == ks.K ? kth : 0ull;
+    ks.have[lr] = n_new;
+  }
+}
+
+// First tile of a range: row lr's list is the K best of the tile's 128 keys.
+template <typename OT>
+__device__ __forceinline__ void knn_first_row(const OT* T, int TS, KnnShared& ks, int lr, int i, int n0,
+                                              const GemmArgs& g) {
+  const int lane = threadIdx.x & 63;
+  const int K = ks.K;
+  uint64_t v[2] = {knn_key(T, TS, lr, i, lane, n0, g), knn_key(T, TS, lr, i, 64 + lane, n0, g)};
+  const int cnt = __popcll(__ballot(v[0] != 0ull)) + __popcll(__ballot(v[1] != 0ull));
+  wave_sort_desc<2>(v);
+  if (lane < K) knn_list(ks, i, g.M)[lane] = v[0];
+  knn_set_row(ks, lr, min(K, cnt), readlane_u64(v[0], K - 1));
+}
+
+// Later tiles: the keys of row lr that beat its K-th key merged into its list
+// L (lane e holds entry e). Keys are distinct, so an element's place in the
+// merged list is the number of elements of both sets above it: found with one
+// pass over the new keys, then every element is stored once.
+template <typename OT>
+__device__ __forceinline__ void knn_rank_merge(const OT* T, int TS, KnnShared& ks, int lr, int i, int n0,
+                                               const GemmArgs& g, uint64_t L) {
+  const int lane = threadIdx.x & 63;
+  const int K = ks.K;
+  uint64_t* gl = knn_list(ks, i, g.M);
+  const uint64_t tau = ks.tau[lr];
+  const uint64_t k0 = knn_key(T, TS, lr, i, lane, n0, g), k1 = knn_key(T, TS, lr, i, 64 + lane, n0, g);
+  const bool s0 = k0 > tau, s1 = k1 > tau;
+  const uint64_t p0 = __ballot(s0), p1 = __ballot(s1);
+  int up = 0, r0 = 0, r1 = 0, a0 = 0, a1 = 0;
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    uint64_t pend = h ? p1 : p0;
+    while (pend) {
+      const int l = __ffsll((unsigned long long)pend) - 1;
+      pend &= pend - 1;
+      const uint64_t x = readlane_u64(h ? k1 : k0, l);
+      up += x > L;
+      r0 += x > k0;
+      r1 += x > k1;
+      const int above = __popcll(__ballot(L > x));
+      if (lane == l) {
+        if (h) a1 = above;
+        else a0 = above;
+      }
+    }
+  }
+  const int dL = lane + up, d0 = r0 + a0, d1 = r1 + a1;
+  if (L != 0ull && dL < K) gl[dL] = L;
+  if (s0 && d0 < K) gl[d0] = k0;
+  if (s1 && d1 < K) gl[d1] = k1;
+  // the entry that lands at K - 1 is the new K-th key
+  const uint64_t mL = __ballot(L != 0ull && dL == K - 1), m0 = __ballot(s0 && d0 == K - 1),
+                 m1 = __ballot(s1 && d1 == K - 1);
+  const uint64_t kth = mL   ? readlane_u64(L, __ffsll((unsigned long long)mL) - 1)
+                       : m0 ? readlane_u64(k0, __ffsll((unsigned long long)m0) - 1)
+                       : m1 ? readlane_u64(k1, __ffsll((unsigned long long)m1) - 1)
+                            : 0ull;
+  knn_set_row(ks, lr, min(K, ks.have[lr] + __popcll(p0) + __popcll(p1)), kth);
+}
+
+// Similarity tile (tm, tn), scaled exactly as the stored similarity (binary16
+// rounding in the low-precision modes, as their S), merged into the K best
+// keys of each tile row under (similarity desc, column asc), the row's own
+// column first. Wave w owns tile rows 32w .. 32w + 31; after the first tile it
+// finds, eight rows at a time, the rows with a key beating their K-th key,
+// loads those rows' lists and merges them.
+template <int MODE>
+__device__ __forceinline__ void knn_epilogue(const GemmArgs& g, int tm, int tn, const f32x16 (&acc)[2][2],
+                                             uint8_t* lds) {
+  using OT = typename std::conditional<MODE == MODE_F32, float, _Float16>::type;
+  constexpr int TS = BN + 16 / (int)sizeof(OT);
+  static_assert(BM * TS * (int)sizeof(OT) <= knn_stage_bytes(MODE), "staged tile must fit the stage buffers");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = tm * BM, n0 = tn * BN;
+  OT* T = (OT*)lds;
+  KnnShared& ks = *(KnnShared*)(lds + knn_stage_bytes(MODE));
+#pragma unroll
+  for (int sm = 0; sm < 2; sm++)
+#pragma unroll
+    for (int sn = 0; sn < 2; sn++) {
+      const int lc = wn * 64 + sn * 32 + (lane & 31);
+      const int col = n0 + lc;
+      const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int row = m0 + lr;
+        T[lr * TS + lc] = (OT)((row < g.M && col < g.Nn) ? acc[sm][sn][r] * g.sa[row] * scol + 0.0f : 0.f);
+      }
+    }
+  __syncthreads();
+  if (ks.first) {
+    for (int lr = wave * 32; lr < wave * 32 + 32 && m0 + lr < g.M; lr++) knn_first_row(T, TS, ks, lr, m0 + lr, n0, g);
+    return;
+  }
+  __threadfence_block();  // the lists stored by this wave's merges of earlier tiles
+  for (int r0 = wave * 32; r0 < wave * 32 + 32; r0 += KNN_RC) {
+    uint32_t todo = 0;
+#pragma unroll
+    for (int u = 0; u < KNN_RC; u++) {
+      const int lr = r0 + u, i = m0 + lr;
+      const uint64_t tau = ks.tau[lr];
+      const bool any = knn_key(T, TS, lr, i, lane, n0, g) > tau || knn_key(T, TS, lr, i, 64 + lane, n0, g) > tau;
+      if (__ballot(any)) todo |= 1u << u;
+    }
+    if (!todo) continue;
+    uint64_t L[KNN_RC];
+#pragma unroll
+    for (int u = 0; u < KNN_RC; u++) {
+      const int lr = r0 + u;
+      L[u] = ((todo >> u) & 1) && lane < ks.have[lr] ? knn_list(ks, m0 + lr, g.M)[lane] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < KNN_RC; u++)
+      if ((todo >> u) & 1) knn_rank_merge(T, TS, ks, r0 + u, m0 + r0 + u, n0, g, L[u]);
   }
 }
 
@@ -298,6 +464,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
         }
       }
     __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
+  } else if constexpr (EPI == EPI_KNN) {
+    knn_epilogue<MODE>(g, tm, tn, acc, lds);
+    __syncthreads();  // the staged tile is overwritten by the next tile's stages
   } else {
     sim_epilogue<EPI>(g, tm, tn, acc, lds);
     __syncthreads();  // LDS is reused by the next tile of a persistent workgroup

@@ -70,6 +70,19 @@ hipError_t launch_prep(const void* x, int in_bf16, int n, int d, float* xp, int6
 hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes,
                            const float* sa, void* out, int64_t ldo, bool half_out, float* ws, int64_t ws_bytes,
                            hipStream_t s);
+
+// a2 + a3 fused (S never written): the K best candidates of each of the M
+// rows of A (the Eq. 7 similarity of A with itself, scaled by sa and rounded
+// as launch_gemm_sim rounds it for prec), written as launch_topk writes them
+// (idx / val, M x K, the row itself first). K <= 64 and K <= M. part:
+// kKnnMaxRanges * M * K uint64 of scratch (per-range lists).
+constexpr int kKnnMaxRanges = 8;
+constexpr int KNN_LIST_MAX = 64;
+hipError_t launch_knn_fused(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes, const float* sa,
+                            int K, uint64_t* part, int32_t* idx, float* val, hipStream_t s);
+// Column ranges per row panel of the fused launch for a tiles_m x tiles_n tile
+// grid on `slots` resident workgroups (host function).
+int knn_fused_ranges(int tiles_m, int tiles_n, int slots);
 // Final epilogue: out[q][g] = 1 - sa[q] * sb[g] * acc, ldo floats.
 // Final product, D = 1 - sa[i] * sb[j] * acc. ws (ws_bytes, may be null):
 // scratch for splitting the last, partly filled round of tiles along K.

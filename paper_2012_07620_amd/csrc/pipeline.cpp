@@ -84,7 +84,7 @@ hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipS
   float* rn = at<float>(ws, P.o_rn);
   float* sl = at<float>(ws, P.o_sl);
   void* xl = P.lbytes ? at<void>(ws, P.o_xl) : nullptr;
-  float* S = at<float>(ws, P.o_a);
+  float* S = P.has_s ? at<float>(ws, P.o_a) : nullptr;
   int32_t* ci = at<int32_t>(ws, P.o_ci);
   float* cv = at<float>(ws, P.o_cv);
   int32_t* ki = at<int32_t>(ws, P.o_ki);
@@ -93,23 +93,31 @@ hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipS
   RR_TRY(launch_prep(x, in_bf16, P.n, P.d, xp, P.ldp, rn, P.prec, xl, P.ldl, sl, s));
   RR_STAGE(RERANK_STAGE_PREP, 1);
   RR_STAGE(RERANK_STAGE_SIMILARITY, 0);
-  // the feature buffer B (not yet in use) holds the partial tiles of a K-split
-  // last round; none for problems the serving path batches (as for the final)
-  float* sws = (P.o_b && P.n > kGroupedMaxN) ? at<float>(ws, P.o_b) : nullptr;
-  const int64_t sws_bytes = sws ? (int64_t)P.n * P.ldH * 4 : 0;
-  if (P.prec == SimPrec::F32)
-    RR_TRY(launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, S, P.ldN, false, sws, sws_bytes, s));
-  else
-    RR_TRY(launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, S, P.ldN, true, sws, sws_bytes,
-                           s));
-  RR_STAGE(RERANK_STAGE_SIMILARITY, 1);
-  RR_STAGE(RERANK_STAGE_TOPK, 0);
-  RR_TRY(launch_topk(S, P.prec != SimPrec::F32, P.ldN, P.n, P.n, P.kc, ci, cv, P.kc, s));
-  RR_STAGE(RERANK_STAGE_TOPK, 1);
+  if (P.fused) {  // S never written: the similarity stage also selects the candidates
+    const void* a = P.prec == SimPrec::F32 ? (const void*)xp : xl;
+    const int64_t row_bytes = P.prec == SimPrec::F32 ? P.ldp * 4 : P.ldl * P.lbytes;
+    RR_TRY(launch_knn_fused(P.prec, a, P.n, row_bytes, row_bytes, P.prec == SimPrec::F32 ? rn : sl, P.kc,
+                            at<uint64_t>(ws, P.o_fk), ci, cv, s));
+    RR_STAGE(RERANK_STAGE_SIMILARITY, 1);
+  } else {
+    // the feature buffer B (not yet in use) holds the partial tiles of a K-split
+    // last round; none for problems the serving path batches (as for the final)
+    float* sws = (P.o_b && P.n > kGroupedMaxN) ? at<float>(ws, P.o_b) : nullptr;
+    const int64_t sws_bytes = sws ? (int64_t)P.n * P.ldH * 4 : 0;
+    if (P.prec == SimPrec::F32)
+      RR_TRY(launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, S, P.ldN, false, sws, sws_bytes, s));
+    else
+      RR_TRY(launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, S, P.ldN, true, sws, sws_bytes,
+                             s));
+    RR_STAGE(RERANK_STAGE_SIMILARITY, 1);
+    RR_STAGE(RERANK_STAGE_TOPK, 0);
+    RR_TRY(launch_topk(S, P.prec != SimPrec::F32, P.ldN, P.n, P.n, P.kc, ci, cv, P.kc, s));
+    RR_STAGE(RERANK_STAGE_TOPK, 1);
+  }
   RR_STAGE(RERANK_STAGE_RESCORE, 0);
   if (P.rescore)
     RR_TRY(launch_rescore(xp, P.ldp, P.d, rn, P.n, ci, cv, P.kc, P.k1, rescore_skip2(P.prec == SimPrec::F32, P.ldp),
-                          ki, kv, (int32_t*)S, s));  // S is dead here
+                          ki, kv, at<int32_t>(ws, P.o_rsc), s));
   else
     RR_TRY(launch_take_prefix(ci, cv, P.n, P.kc, P.k1, ki, kv, s));
   RR_STAGE(RERANK_STAGE_RESCORE, 1);

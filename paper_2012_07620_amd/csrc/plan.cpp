@@ -35,7 +35,7 @@ rerank_status validate_params(const rerank_params* p, std::string* why) {
 
 static size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-void make_plan(const rerank_params* p, bool knn_only, Plan* o, bool dense_layers) {
+void make_plan(const rerank_params* p, bool knn_only, Plan* o, bool dense_layers, bool fused) {
   Plan& P = *o;
   P = Plan{};
   P.n = p->n;
@@ -74,7 +74,15 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o, bool dense_layers
   P.o_rn = take(n * 4);
   P.o_sl = take(n * 4);
   const size_t hrow = (size_t)(P.ldN > P.ldH ? P.ldN : P.ldH);
-  P.o_a = take(n * hrow * 4);
+  P.fused = fused;
+  P.has_s = !(fused && knn_only);
+  if (P.has_s) {
+    P.o_a = take(n * hrow * 4);
+    P.o_rsc = P.o_a;  // S is dead once the candidates are selected
+  } else {
+    P.o_rsc = take((size_t)(cluster_order_ints(P.n, P.n) + P.n) * 4);
+  }
+  if (fused) P.o_fk = take((size_t)kKnnMaxRanges * n * P.kc * 8);
   P.o_ci = take(n * P.kc * 4);
   P.o_cv = take(n * P.kc * 4);
   P.o_ki = take(n * P.k1 * 4);

@@ -34,16 +34,22 @@ struct Plan {
   size_t o_xp = 0, o_xl = 0, o_rn = 0, o_sl = 0, o_a = 0, o_b = 0, o_ci = 0, o_cv = 0, o_ki = 0, o_kv = 0,
          o_sa = 0, o_sb = 0, o_cnt = 0, o_hi = 0, o_lo = 0, o_mflag = 0, o_off = 0, o_inl = 0, o_sp = 0,
          o_slg = 0, o_slr = 0, o_part = 0,
-         o_ord = 0;
+         o_ord = 0,
+         o_fk = 0,   // per-range candidate lists of the fused similarity + top-k
+         o_rsc = 0;  // re-score scratch (the dead S buffer, or its own block without one)
   bool sparse_first = false;   // layer 1 built from the sparse A* / A rows (layers >= 1, sum or mean)
   bool sparse_layers = false;  // layers kept as CSR rows for the sparse final product
+  bool fused = false;          // similarity and top-k fused: S is never written
+  bool has_s = true;           // the N x N buffer A exists (knn-only fused plans have none)
   size_t total = 0;
 };
 
 // Returns RERANK_OK or an error with a reason in *why.
 rerank_status validate_params(const rerank_params* p, std::string* why);
 // Fills the layout for valid parameters. knn_only skips propagation buffers;
-// dense_layers keeps the layers dense under the sparse final product.
-void make_plan(const rerank_params* p, bool knn_only, Plan* out, bool dense_layers = false);
+// dense_layers keeps the layers dense under the sparse final product; fused
+// selects the fused similarity + top-k (a knn-only plan then holds no N x N
+// buffer).
+void make_plan(const rerank_params* p, bool knn_only, Plan* out, bool dense_layers = false, bool fused = false);
 
 }  // namespace rr

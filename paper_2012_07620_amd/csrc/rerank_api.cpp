@@ -149,13 +149,22 @@ rerank_status rerank_workspace_bytes(const rerank_params* p, size_t* bytes) {
   return RERANK_OK;
 }
 
+// The fused similarity + top-k keeps at most 64 candidates per row.
+static rerank_status check_fused(const Plan& P) {
+  if (P.fused && P.kc > KNN_LIST_MAX) {
+    set_error("RERANK_CTX_FUSED_KNN: k1 + extra_cand above 64 is outside the fused path's limits");
+    return RERANK_E_UNSUPPORTED;
+  }
+  return RERANK_OK;
+}
+
 rerank_status rerank_create(rerank_ctx** out, int hip_device, size_t hbm_budget_bytes, uint32_t flags) {
   if (!out) {
     set_error("out is NULL");
     return RERANK_E_INVALID;
   }
   *out = nullptr;
-  if (flags & ~(RERANK_CTX_STAGE_TIMING | RERANK_CTX_DENSE_LAYERS)) {
+  if (flags & ~(RERANK_CTX_STAGE_TIMING | RERANK_CTX_DENSE_LAYERS | RERANK_CTX_FUSED_KNN)) {
     set_error("unknown flags");
     return RERANK_E_INVALID;
   }
@@ -237,7 +246,8 @@ rerank_status rerank_run(rerank_ctx* ctx, const rerank_params* p, const void* d_
     return RERANK_E_INVALID;
   }
   Plan P;
-  make_plan(p, false, &P, (ctx->flags & RERANK_CTX_DENSE_LAYERS) != 0);
+  make_plan(p, false, &P, (ctx->flags & RERANK_CTX_DENSE_LAYERS) != 0, (ctx->flags & RERANK_CTX_FUSED_KNN) != 0);
+  if ((st = check_fused(P)) != RERANK_OK) return st;
   return with_ws(ctx, P, hip_stream, [&](hipStream_t s, const char** where) -> hipError_t {
     hipError_t e = enqueue_rerank(P, ctx->ws, d_x, in_dtype == RERANK_IN_BF16, d_dist, s, where, ctx->clock);
     if (e != hipSuccess) return e;
@@ -260,7 +270,8 @@ rerank_status rerank_knn(rerank_ctx* ctx, const rerank_params* p, const void* d_
     return RERANK_E_INVALID;
   }
   Plan P;
-  make_plan(p, true, &P);
+  make_plan(p, true, &P, false, (ctx->flags & RERANK_CTX_FUSED_KNN) != 0);
+  if ((st = check_fused(P)) != RERANK_OK) return st;
   return with_ws(ctx, P, hip_stream, [&](hipStream_t s, const char** where) -> hipError_t {
     hipError_t e = enqueue_knn(P, ctx->ws, d_x, in_dtype == RERANK_IN_BF16, s, where, ctx->clock);
     if (e != hipSuccess) return e;

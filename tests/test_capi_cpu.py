@@ -119,7 +119,7 @@ def test_context_flags_checked_before_any_device_call():
     # the flag check needs no GPU: unknown bits are rejected, known ones pass it
     lib = binding.library()
     h = ctypes.c_void_p()
-    assert lib.rerank_create(ctypes.byref(h), 0, 0, 4) == binding.E_INVALID
+    assert lib.rerank_create(ctypes.byref(h), 0, 0, 8) == binding.E_INVALID
     assert lib.rerank_create(ctypes.byref(h), 0, 0, 1 << 31) == binding.E_INVALID
     assert binding.CTX_STAGE_TIMING == 1 and binding.CTX_DENSE_LAYERS == 2
     hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "rerank.h")).read()
