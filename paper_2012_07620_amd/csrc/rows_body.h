@@ -1,6 +1,7 @@
 // Per-work-item bodies of the row-parallel kernels (a1, a3, a3b, a4, a6),
 // shared by the direct launches and the persistent grouped launches.
 #pragma once
+#include <type_traits>
 #include "../../include/rerank.h"
 #include "common.h"
 #include "kernels.h"
@@ -112,26 +113,40 @@ __device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, i
 #pragma unroll
   for (int r = 0; r < R; r++) best[r] = 0;
   uint64_t tau = 0;
+  float tf = -INFINITY;  // value of tau's key (all values pass while tau is 0)
   int head = 0, cnt = 0;
 
   constexpr int U = 4;
   constexpr int CH = 64 * 4 * U;
+  // chunk c0 into registers (zeros past N); the next chunk is loaded while
+  // the current one is processed
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+  typedef typename std::conditional<!ASC && sizeof(T) == 2, h4, f32x4>::type raw4;
+  auto load = [&](int c0, raw4 (&r)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int col = c0 + u * 256 + lane * 4;
+      if constexpr (!ASC) {  // S rows (FP32 or binary16): 256-byte aligned, padded to a multiple of 64 columns
+        r[u] = (col < N) ? *(const raw4*)(srow + col) : raw4{0, 0, 0, 0};
+      } else {  // caller's distance rows: any stride, no padding
+#pragma unroll
+        for (int e = 0; e < 4; e++) r[u][e] = (col + e < N) ? srow[col + e] : 0.f;
+      }
+    }
+  };
+  raw4 nxt[U];
+  load(0, nxt);
   for (int c0 = 0; c0 < N; c0 += CH) {
     f32x4 v[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      const int col = c0 + u * 256 + lane * 4;
-      if (!ASC && sizeof(T) == 4) {  // S rows: 256-byte aligned, padded to a multiple of 64 columns
-        v[u] = (col < N) ? *(const f32x4*)(srow + col) : f32x4{0.f, 0.f, 0.f, 0.f};
-      } else if (!ASC) {  // binary16 S rows, same padding
-        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-        const h4 hv = (col < N) ? *(const h4*)(srow + col) : h4{0, 0, 0, 0};
-        v[u] = f32x4{(float)hv.x, (float)hv.y, (float)hv.z, (float)hv.w};
-      } else {  // caller's distance rows: any stride, no padding
-#pragma unroll
-        for (int e = 0; e < 4; e++) v[u][e] = (col + e < N) ? srow[col + e] : 0.f;
+      if constexpr (!ASC && sizeof(T) == 2) {
+        v[u] = f32x4{(float)nxt[u].x, (float)nxt[u].y, (float)nxt[u].z, (float)nxt[u].w};
+      } else {
+        v[u] = nxt[u];
       }
     }
+    if (c0 + CH < N) load(c0 + CH, nxt);
     uint64_t lm = 0;
     if (c0 == 0) {
 #pragma unroll
@@ -146,12 +161,18 @@ __device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, i
       best[0] = lm;
       wave_sort_desc<R>(best);
       tau = wave_rank_key<R>(best, K - 1);
+      tf = tau ? key_val(tau) : -INFINITY;
     }
 #pragma unroll
     for (int u = 0; u < U; u++)
 #pragma unroll
       for (int e = 0; e < 4; e++) {
         const int col = c0 + u * 256 + lane * 4 + e;
+        // a key above tau has a value of at least tau's (or is the row's own
+        // column): full keys are built only when some lane has such a value
+        const float sv = ASC ? -v[u][e] : v[u][e];
+        const bool cand = col < N && (sv >= tf || (!ASC && col == i));
+        if (!__ballot(cand)) continue;
         uint64_t key = 0;
         if (col < N)
           key = ASC ? sel_key(-v[u][e], (uint32_t)col) : ((col == i) ? self_key(i) : sel_key(v[u][e], (uint32_t)col));
@@ -167,6 +188,7 @@ __device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, i
             cnt -= 64;
             wave_merge_batch<R>(best, b);
             tau = wave_rank_key<R>(best, K - 1);
+            tf = tau ? key_val(tau) : -INFINITY;
           }
         }
       }
