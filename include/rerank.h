@@ -50,7 +50,7 @@ typedef enum {
   RERANK_E_BUSY = 4,      /* request still running (rerank_poll/cancel) */
   RERANK_E_TIMEOUT = 5,   /* rerank_wait timed out; the request keeps running */
   RERANK_E_CANCELLED = 6, /* request was cancelled before it started */
-  RERANK_E_UNSUPPORTED = 7/* valid in the paper's terms but outside this build's limits */
+  RERANK_E_UNSUPPORTED = 7/* valid in the paper's terms but outside this library's limits */
 } rerank_status;
 
 /* Storage type of the caller's feature matrix. */

@@ -27,7 +27,7 @@ rerank_status validate_params(const rerank_params* p, std::string* why) {
   if (p->extra_cand < -1) return bad(why, "extra_cand must be >= -1");
   if (p->extra_cand == 0 && p->sim_prec != RERANK_SIM_F32)
     return bad(why, "low-precision similarity needs FP32 re-scoring (extra_cand != 0)");
-  if (p->k1 > kMaxCand) return bad(why, "k1 above 256 is outside this build's limits", RERANK_E_UNSUPPORTED);
+  if (p->k1 > kMaxCand) return bad(why, "k1 above 256 is outside this library's limits", RERANK_E_UNSUPPORTED);
   // 32-bit row indices and per-launch tile counts
   if ((int64_t)p->n * (int64_t)p->n / (128 * 128) > 0x7FFFFFFF) return bad(why, "n too large", RERANK_E_UNSUPPORTED);
   return RERANK_OK;

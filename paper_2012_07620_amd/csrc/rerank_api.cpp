@@ -322,7 +322,7 @@ rerank_status rerank_rank(rerank_ctx* ctx, const float* d_dist, int32_t q, int32
     return RERANK_E_INVALID;
   }
   if (r > kMaxCand) {
-    set_error("r above 256 is outside this build's limits");
+    set_error("r above 256 is outside this library's limits");
     return RERANK_E_UNSUPPORTED;
   }
   hipError_t e = hipSetDevice(ctx->device);
