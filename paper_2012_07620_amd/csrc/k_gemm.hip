@@ -31,9 +31,12 @@ constexpr int SIM_KS = 1;
 
 // FP8 similarity tiles are held to three waves per SIMD (168 registers; the
 // binary16 staging leaves LDS for three workgroups per CU): 0.64 -> 0.55 ms at
-// N = 19281. The others keep the compiler's allocation (BF16 already fits).
+// N = 19281. So is the BF16 final product (one 36 KB stage buffer; 172 -> 160
+// registers, no spills): 2.45 -> 2.38 ms (four waves spill and take 4.5 ms).
+// The others keep the compiler's allocation (the BF16 similarity already fits).
 template <int MODE, int EPI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_FP8 && EPI == EPI_SIM_SYM16 ? 3 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    (MODE == MODE_FP8 && EPI == EPI_SIM_SYM16) || (MODE == MODE_BF16 && EPI == EPI_DIST) ? 3 : 1)))
 void gemm_nt_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   constexpr bool SYM = EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16;
   constexpr int KS = (EPI == EPI_DIST && MODE == MODE_F32) ? DIST_KS : SYM ? SIM_KS : 1;
