@@ -121,9 +121,16 @@ def test_context_flags_checked_before_any_device_call():
     h = ctypes.c_void_p()
     assert lib.rerank_create(ctypes.byref(h), 0, 0, 8) == binding.E_INVALID
     assert lib.rerank_create(ctypes.byref(h), 0, 0, 1 << 31) == binding.E_INVALID
-    assert binding.CTX_STAGE_TIMING == 1 and binding.CTX_DENSE_LAYERS == 2
+    assert binding.CTX_STAGE_TIMING == 1 and binding.CTX_DENSE_LAYERS == 2 and binding.CTX_FUSED_KNN == 4
     hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "rerank.h")).read()
     assert "#define RERANK_CTX_STAGE_TIMING 1u" in hdr and "#define RERANK_CTX_DENSE_LAYERS 2u" in hdr
+    assert "#define RERANK_CTX_FUSED_KNN 4u" in hdr
+    # every known bit passes the flag check (what follows needs a device, absent here or not)
+    for flags in (1, 2, 4, 7):
+        st = lib.rerank_create(ctypes.byref(h), 0, 0, flags)
+        assert st != binding.E_INVALID, flags
+        if st == binding.OK:
+            assert lib.rerank_destroy(h) == binding.OK
 
 
 def test_evaluate_rejects_bad_arguments_before_any_device_call():
