@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void g_rescore(const BatchTable* __restrict__ 
     const ProbDesc& D = t->p[p];
     const int i = (item - t->start[GS_RESCORE][p]) * 4 + (threadIdx.x >> 6);
     if (i < D.n)
-      rescore_row<R>(D.xp, D.ldp, D.rn, i, D.ci, D.cv, D.kc, D.k1, rescore_skip2(D.lbytes == 0, D.ldp), D.ki, D.kv);
+      rescore_row<R>(D.xp, D.ldp, D.rn, i, D.ci, D.cv, D.kc, D.k1, rescore_skip2(D.lbytes, D.ldp), D.ki, D.kv);
   }
 }
 

@@ -111,15 +111,23 @@ hipError_t launch_topk(const void* S, bool half, int64_t ldS, int N, int rows, i
 inline int64_t cluster_order_ints(int64_t rows, int64_t n) { return (3 * n + rows + 1 + scan_parts(n) + 3) / 4 * 4; }
 hipError_t launch_cluster_order(const int32_t* lists, int rows, int w, int n, int32_t* scratch, int32_t* order,
                                 hipStream_t s);
-// 2 delta for the candidate skip of the FP32 re-score: delta bounds the
-// error of the FP32 similarity product over K padded terms, scaled by the two
-// inverse norms (|error| <= (K + 8) u / (1 - (K + 8) u) of |x_i| |x_j| by
-// Cauchy-Schwarz, u = 2^-24), here doubled for margin. The low-precision
-// products have no such tight bound: -1 (re-score every candidate).
-__host__ __device__ inline float rescore_skip2(bool f32_product, int64_t K) {
-  if (!f32_product) return -1.f;
+// 2 delta for the candidate skip of the re-score, for similarity products
+// whose low-precision copy has lbytes bytes per element (0: FP32), over at most
+// K terms; delta bounds |product value - re-scored value|.
+//  * FP32: (K + 8) u / (1 - (K + 8) u) of |x_i| |x_j| by Cauchy-Schwarz,
+//    u = 2^-24, scaled by the two inverse norms; here doubled for margin.
+//  * BF16: both operands rounded to bfloat16 (relative error <= 2^-9 each,
+//    so the summed product error is <= (2^-8 + 2^-18) |x_i| |x_j|), FP32
+//    accumulation (<= (K + 8) 2^-24 of the same), scaling by the inverse norms
+//    (< 1e-6) and binary16 storage (<= 2^-11 for |S| <= 1), plus 1e-6 for the
+//    re-score's own error.
+//  * FP8: e4m3 rounds to 2^-4, too coarse to skip anything: -1 (re-score
+//    every candidate).
+__host__ __device__ inline float rescore_skip2(int lbytes, int64_t K) {
   const double ku = (double)(K + 8) * 0x1p-24;
-  return (float)(2.0 * 2.0 * ku / (1.0 - ku));
+  if (lbytes == 0) return (float)(2.0 * 2.0 * ku / (1.0 - ku));
+  if (lbytes == 2) return (float)(2.0 * (0x1p-8 + 0x1p-18 + 2.0 * ku + 0x1p-11 + 2e-6));
+  return -1.f;
 }
 
 // a3b: FP32 compensated re-score of Kc candidates per row, then the k1 cut.

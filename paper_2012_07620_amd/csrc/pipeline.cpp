@@ -116,7 +116,7 @@ hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipS
   }
   RR_STAGE(RERANK_STAGE_RESCORE, 0);
   if (P.rescore)
-    RR_TRY(launch_rescore(xp, P.ldp, P.d, rn, P.n, ci, cv, P.kc, P.k1, rescore_skip2(P.prec == SimPrec::F32, P.ldp),
+    RR_TRY(launch_rescore(xp, P.ldp, P.d, rn, P.n, ci, cv, P.kc, P.k1, rescore_skip2(P.lbytes, P.ldp),
                           ki, kv, at<int32_t>(ws, P.o_rsc), s));
   else
     RR_TRY(launch_take_prefix(ci, cv, P.n, P.kc, P.k1, ki, kv, s));
