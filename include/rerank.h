@@ -149,6 +149,15 @@ rerank_status rerank_workspace_bytes(const rerank_params* p, size_t* bytes);
  * (rerank_submit) ignore it. */
 #define RERANK_CTX_FUSED_KNN 4u
 
+/* Bytes of library-owned device memory rerank_knn needs for *p in a context
+ * created with `flags` (the Eq. 7-8 k-NN graph alone). Without
+ * RERANK_CTX_FUSED_KNN this includes the N x N similarity buffer; with it the
+ * total is linear in N (feature copies, candidate and per-range lists).
+ * Pure host function. RERANK_E_INVALID for invalid parameters, unknown flags or
+ * a NULL `bytes`; RERANK_E_UNSUPPORTED when the fused path cannot take
+ * k1 + extra_cand. */
+rerank_status rerank_knn_workspace_bytes(const rerank_params* p, uint32_t flags, size_t* bytes);
+
 /* Create a context on HIP device `hip_device`. The context never holds more
  * than `hbm_budget_bytes` of device memory (0 = 90% of the device's free
  * memory at creation). flags: 0 or an OR of RERANK_CTX_STAGE_TIMING,

@@ -23,7 +23,8 @@ AGG = {"sum": 0, "mean": 1, "max": 2}
 FINAL = {"f32": 0, "bf16x3": 1, "sparse": 2, "bf16": 3}
 
 EXPORTS = (
-    "rerank_default_params", "rerank_validate", "rerank_workspace_bytes", "rerank_create", "rerank_destroy",
+    "rerank_default_params", "rerank_validate", "rerank_workspace_bytes", "rerank_knn_workspace_bytes",
+    "rerank_create", "rerank_destroy",
     "rerank_run", "rerank_knn", "rerank_similarity", "rerank_submit", "rerank_poll", "rerank_wait",
     "rerank_cancel", "rerank_status_str", "rerank_last_error", "rerank_stage_times", "rerank_stage_name",
     "rerank_rank", "rerank_evaluate",
@@ -67,6 +68,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
             "rerank_default_params": (None, [P, i32, i32, i32, i32, i32]),
             "rerank_validate": (ctypes.c_int, [P]),
             "rerank_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(sz)]),
+            "rerank_knn_workspace_bytes": (ctypes.c_int, [P, ctypes.c_uint32, ctypes.POINTER(sz)]),
             "rerank_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, sz, ctypes.c_uint32]),
             "rerank_destroy": (ctypes.c_int, [vp]),
             "rerank_run": (ctypes.c_int, [vp, P, vp, i32, vp, vp, vp, vp]),
@@ -112,6 +114,14 @@ def validate(p: Params) -> int:
 def workspace_bytes(p: Params) -> int:
     out = ctypes.c_size_t(0)
     _check(library().rerank_workspace_bytes(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
+
+
+def knn_workspace_bytes(p: Params, fused_knn: bool = False) -> int:
+    """Device bytes rerank_knn needs for ``p`` (with the fused similarity + selection: no N x N buffer)."""
+    out = ctypes.c_size_t(0)
+    _check(library().rerank_knn_workspace_bytes(ctypes.byref(p), CTX_FUSED_KNN if fused_knn else 0,
+                                                ctypes.byref(out)))
     return out.value
 
 

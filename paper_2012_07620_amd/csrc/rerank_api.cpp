@@ -158,6 +158,24 @@ static rerank_status check_fused(const Plan& P) {
   return RERANK_OK;
 }
 
+rerank_status rerank_knn_workspace_bytes(const rerank_params* p, uint32_t flags, size_t* bytes) {
+  std::string why;
+  rerank_status st = validate_params(p, &why);
+  if (st != RERANK_OK) {
+    set_error(why);
+    return st;
+  }
+  if (!bytes || (flags & ~(RERANK_CTX_STAGE_TIMING | RERANK_CTX_DENSE_LAYERS | RERANK_CTX_FUSED_KNN))) {
+    set_error("bytes is NULL or unknown flags");
+    return RERANK_E_INVALID;
+  }
+  Plan P;
+  make_plan(p, true, &P, false, (flags & RERANK_CTX_FUSED_KNN) != 0);
+  if ((st = check_fused(P)) != RERANK_OK) return st;
+  *bytes = P.total;
+  return RERANK_OK;
+}
+
 rerank_status rerank_create(rerank_ctx** out, int hip_device, size_t hbm_budget_bytes, uint32_t flags) {
   if (!out) {
     set_error("out is NULL");

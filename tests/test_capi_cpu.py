@@ -147,3 +147,35 @@ def test_evaluate_rejects_bad_arguments_before_any_device_call():
     assert lib.rerank_evaluate(p, p, 2, 3, 3, p, p, ks, 0, p, p, p, None) == binding.E_INVALID
     assert lib.rerank_evaluate(p, p, 2, 3, 3, p, p, ks, 17, p, p, p, None) == binding.E_INVALID
     assert lib.rerank_evaluate(p, p, 2, 3, 3, p, p, bad_k, 2, p, p, p, None) == binding.E_INVALID
+
+
+def test_knn_workspace_has_no_n_squared_term_with_the_fused_path():
+    n, d = 19281, 2048
+    ldn = (n + 63) // 64 * 64
+    p = binding.make_params(n, 1, d, 26, 1, 0)
+    plain = binding.knn_workspace_bytes(p)
+    fused = binding.knn_workspace_bytes(p, fused_knn=True)
+    assert plain >= n * ldn * 4  # the N x N similarity buffer
+    assert fused < plain - n * ldn * 4 + 8 * n * (26 + 8) * 8 + (1 << 20)
+    # linear in N: twice the rows, about twice the bytes
+    f2 = binding.knn_workspace_bytes(binding.make_params(2 * n, 1, d, 26, 1, 0), fused_knn=True)
+    assert 1.9 * fused < f2 < 2.1 * fused
+    # N = 300000, d = 512, BF16: S alone would be 360 GB; the fused k-NN graph needs a few GB
+    big = binding.make_params(300000, 1, 512, 20, 1, 0, sim_prec="bf16")
+    assert binding.knn_workspace_bytes(big) > 300000 * 300032 * 2
+    assert binding.knn_workspace_bytes(big, fused_knn=True) < 4 << 30
+
+
+def test_knn_workspace_checks():
+    lib = binding.library()
+    p = binding.make_params(1000, 1, 64, 60, 1, 0)  # 60 + 8 candidates
+    assert binding.knn_workspace_bytes(p) > 0
+    with pytest.raises(binding.RerankError) as e:
+        binding.knn_workspace_bytes(p, fused_knn=True)
+    assert e.value.status == binding.E_UNSUPPORTED
+    out = ctypes.c_size_t(0)
+    q = binding.make_params(1000, 1, 64, 10, 1, 0)
+    assert lib.rerank_knn_workspace_bytes(ctypes.byref(q), 8, ctypes.byref(out)) == binding.E_INVALID
+    assert lib.rerank_knn_workspace_bytes(ctypes.byref(q), 4, None) == binding.E_INVALID
+    bad = binding.make_params(1000, 1, 64, 10, 20, 0)  # k2 > k1
+    assert lib.rerank_knn_workspace_bytes(ctypes.byref(bad), 0, ctypes.byref(out)) == binding.E_INVALID
