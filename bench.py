@@ -302,6 +302,9 @@ def main() -> int:
             if fused:  # the similarity stage also selects the candidates; the full product is computed
                 entry["similarity_roofline"]["note"] = ("fused similarity + top-k: every tile of the N x N product "
                                                         "(twice the symmetric product's flops), S never written")
+                kp = binding.make_params(spec.n, spec.n_query, spec.dim, spec.k1, spec.k2, spec.layers, sim_prec=prec)
+                entry["knn_workspace_bytes"] = {"unfused": binding.knn_workspace_bytes(kp),
+                                                "fused": binding.knn_workspace_bytes(kp, fused_knn=True)}
             lowp[name] = entry
         if ctx_fused is not None:
             ctx_fused.close()
