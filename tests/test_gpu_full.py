@@ -11,7 +11,7 @@ import pytest
 
 from oracle import rerank_oracle as orc
 from paper_2012_07620_amd import synth
-from tests.parity import compare_distances, compare_lists, tainted_rows
+from tests.parity import check_run
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -50,9 +50,8 @@ def test_mid_final_sparse(gpu_lib, mid):
         err = np.abs(d - ref.dist)
         print(f"{prec} sim + sparse final: D vs FP64 max {err.max():.3e} mean {err.mean():.3e}", flush=True)
         if prec == "f32":
-            f1, f2 = compare_lists(ki, ref.graph, s.k2)
-            taint = tainted_rows(ref.graph.idx, ki, f1, f2, s.k2, s.layers)
-            compare_distances(d, ref.dist, s.n_query, taint, D_TOL["f32"])
+            r = check_run(p.x32, ref, ki, d, s.n_query, s.k2, s.layers, D_TOL["f32"])
+            print(f"f32 + sparse: tied rows {r['tied_rows_k1']}, pairs vs tie-breaks {r['pairs_vs_tie_breaks']}")
         else:
             assert err.max() <= D_TOL["bf16"]
 
@@ -90,11 +89,10 @@ def test_mid_full(gpu_lib, mid, prec):
     err_all = np.abs(d - ref.dist)
     print(f"{prec}: k1 overlap {overlap:.6f}; D vs FP64 max {err_all.max():.3e} mean {err_all.mean():.3e}", flush=True)
     if prec == "f32":
-        f1, f2 = compare_lists(ki, ref.graph, s.k2)
-        taint = tainted_rows(ref.graph.idx, ki, f1, f2, s.k2, s.layers)
-        mx, mean, excused = compare_distances(d, ref.dist, s.n_query, taint, D_TOL["f32"])
-        print(f"f32: flipped tied rows {len(f1)}, excused pairs {excused}", flush=True)
-        ok = ~np.isin(np.arange(s.n), f1)
+        r = check_run(p.x32, ref, ki, d, s.n_query, s.k2, s.layers, D_TOL["f32"])
+        print(f"f32: tied rows k1 {r['tied_rows_k1']} k2 {r['tied_rows_k2']}, pairs vs tie-breaks "
+              f"{r['pairs_vs_tie_breaks']}, max err {r['max_err']:.2e}", flush=True)
+        ok = ~np.isin(np.arange(s.n), r["flip1"])
         np.testing.assert_allclose(kv[ok], ref.graph.val[ok], atol=1e-6)
     else:
         assert overlap >= 0.995
@@ -117,11 +115,11 @@ def test_large_sampled(gpu_lib):
     for prec, fprec in (("f32", "f32"), ("bf16", "f32"), ("f32", "sparse")):
         print(f"case {s.name} prec={prec} final={fprec}", flush=True)
         d, ki, kv = _gpu(p, prec, final_prec=fprec)
-        f1, f2 = compare_lists(ki, g, s.k2) if prec == "f32" else (None, None)
         if prec == "f32":
-            taint = tainted_rows(g.idx, ki, f1, f2, s.k2, s.layers)
-            mx, mean, excused = compare_distances(d[q_rows], dref, s.n_query, taint, D_TOL[prec], q_rows=q_rows)
-            print(f"large f32/{fprec}: flipped tied rows {len(f1)}, D max err {mx:.2e} mean {mean:.2e}, excused {excused}")
+            r = check_run(p.x32, None, ki, d[q_rows], s.n_query, s.k2, s.layers, D_TOL[prec], q_rows=q_rows,
+                          graph=g, d_ref=dref)
+            print(f"large f32/{fprec}: tied rows {r['tied_rows_k1']}, D max err {r['max_err']:.2e} "
+                  f"mean {r['mean_err']:.2e}, pairs vs tie-breaks {r['pairs_vs_tie_breaks']}")
         else:
             same = np.mean(np.all(np.sort(ki, 1) == np.sort(g.idx, 1), axis=1))
             err = np.abs(d[q_rows] - dref)

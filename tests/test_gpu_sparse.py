@@ -16,7 +16,7 @@ import pytest
 
 from oracle import rerank_oracle as orc
 from paper_2012_07620_amd import synth
-from tests.parity import compare_distances, compare_lists, tainted_rows
+from tests.parity import check_run
 
 pytestmark = pytest.mark.gpu
 
@@ -40,10 +40,8 @@ def _check(x, q, k1, k2, layers, node="adj", agg="sum", alpha=2):
     print(f"case sparse n={len(x)} q={q} d={x.shape[1]} k1={k1} k2={k2} L={layers} node={node} agg={agg}", flush=True)
     dg, ki, kv = _run(x, q, k1, k2, layers, node=node, aggregator=agg, alpha=alpha, final_prec="sparse")
     ref = orc.rerank(x, q, k1, k2, layers, alpha=alpha, node=node, aggregator=agg)
-    f1, f2 = compare_lists(ki, ref.graph, k2)
-    taint = tainted_rows(ref.graph.idx, ki, f1, f2, k2, layers)
-    mx, mean, excused = compare_distances(dg, ref.dist, q, taint, D_TOL_F32)
-    print(f"sparse: max err {mx:.2e} mean {mean:.2e} excused {excused}")
+    r = check_run(x, ref, ki, dg, q, k2, layers, D_TOL_F32, alpha=alpha, node=node, aggregator=agg)
+    print(f"sparse: max err {r['max_err']:.2e} mean {r['mean_err']:.2e} pairs vs tie-breaks {r['pairs_vs_tie_breaks']}")
     return dg
 
 
@@ -143,7 +141,6 @@ def test_sparse_layers_match_dense_layers_bit_for_bit(gpu_lib, n, q, d, k1, k2, 
     ctx_d.close()
     ref = orc.rerank(x, q, k1, k2, layers, node=node, aggregator=agg)
     ki = ki.cpu().numpy()
-    f1, f2 = compare_lists(ki, ref.graph, k2)
-    taint = tainted_rows(ref.graph.idx, ki, f1, f2, k2, layers)
-    mx, mean, excused = compare_distances(d_csr.cpu().numpy(), ref.dist, q, taint, D_TOL_F32)
-    print(f"sparse layers: D vs FP64 max {mx:.2e} mean {mean:.2e}, flipped tied rows {len(f1)}, excused {excused}")
+    r = check_run(x, ref, ki, d_csr.cpu().numpy(), q, k2, layers, D_TOL_F32, node=node, aggregator=agg)
+    print(f"sparse layers: D vs FP64 max {r['max_err']:.2e} mean {r['mean_err']:.2e}, "
+          f"tied rows {r['tied_rows_k1']}, pairs vs tie-breaks {r['pairs_vs_tie_breaks']}")
