@@ -228,9 +228,20 @@ rerank_status rerank_evaluate(rerank_ctx* ctx, const float* d_dist, int32_t q, i
  * fits in the free part of the context budget; admitted requests run
  * concurrently on the context's streams. Each request's result is the same as
  * rerank_run on the same input. The caller keeps d_x and d_dist valid until
- * the request is reported done. Tickets are unique per context. */
+ * the request is reported done. Tickets are unique per context.
+ *   hip_stream  the stream (hipStream_t, NULL = the null stream) on which the
+ *               caller produced d_x: an event is recorded on it at submit and
+ *               the request's kernels start only after the work enqueued on
+ *               it before the call; it must belong to the context's device
+ *               (RERANK_E_HIP otherwise).
+ * The memory of the direct calls (rerank_run, rerank_knn, rerank_similarity)
+ * and of the serving requests comes from the one budget: a request that does
+ * not fit next to the direct calls' working set while no request runs gets
+ * that working set back (after its kernels finish; the next direct call
+ * allocates it again), and a direct call that does not fit gets the blocks the
+ * serving pool keeps cached. */
 rerank_status rerank_submit(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype,
-                            float* d_dist, uint64_t* ticket);
+                            float* d_dist, void* hip_stream, uint64_t* ticket);
 
 /* *done = 1 once the request finished (successfully or not), else 0. */
 rerank_status rerank_poll(rerank_ctx* ctx, uint64_t ticket, int* done);

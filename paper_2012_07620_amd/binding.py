@@ -74,7 +74,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
             "rerank_run": (ctypes.c_int, [vp, P, vp, i32, vp, vp, vp, vp]),
             "rerank_knn": (ctypes.c_int, [vp, P, vp, i32, vp, vp, vp]),
             "rerank_similarity": (ctypes.c_int, [vp, P, vp, i32, vp, ctypes.c_int64, vp]),
-            "rerank_submit": (ctypes.c_int, [vp, P, vp, i32, vp, ctypes.POINTER(u64)]),
+            "rerank_submit": (ctypes.c_int, [vp, P, vp, i32, vp, vp, ctypes.POINTER(u64)]),
             "rerank_poll": (ctypes.c_int, [vp, u64, ctypes.POINTER(ctypes.c_int)]),
             "rerank_wait": (ctypes.c_int, [vp, u64, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
             "rerank_cancel": (ctypes.c_int, [vp, u64]),
@@ -271,12 +271,16 @@ def evaluate(dist, q_labels, g_labels, ks=(1, 5, 10), ctx: Optional[Context] = N
 def submit(ctx: Context, x, out, n_query: int, k1: int, k2: int, layers: int = 1, alpha: int = 2,
            sim_prec: str = "f32", extra_cand: int = -1, node: str = "adj", final_prec: str = "f32",
            aggregator: str = "sum") -> int:
-    """Asynchronous request; ``out`` (Q x G float32) must stay alive until done."""
+    """Asynchronous request; ``out`` (Q x G float32) must stay alive until
+    done. The request starts after the work already enqueued on the current
+    stream of ``x``'s device (the stream that produced ``x``)."""
+    import torch
     dt = _x_args(x)
     n, d = x.shape
     p = make_params(n, n_query, d, k1, k2, layers, alpha, sim_prec, extra_cand, node, final_prec, aggregator)
     t = ctypes.c_uint64(0)
-    _check(library().rerank_submit(ctx.handle, ctypes.byref(p), x.data_ptr(), dt, out.data_ptr(), ctypes.byref(t)))
+    _check(library().rerank_submit(ctx.handle, ctypes.byref(p), x.data_ptr(), dt, out.data_ptr(),
+                                   _stream_ptr(torch, x.device), ctypes.byref(t)))
     return t.value
 
 

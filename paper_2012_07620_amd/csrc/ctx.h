@@ -12,6 +12,16 @@ namespace rr {
 class Server;
 void set_error(const std::string& msg);
 rerank_status hip_fail(hipError_t e, const char* what);
+
+// Take `bytes` out of the budget if they fit next to what is already held
+// (atomic: direct calls and the serving scheduler reserve from two threads).
+inline bool try_reserve(std::atomic<size_t>& reserved, size_t budget, size_t bytes) {
+  size_t cur = reserved.load();
+  do {
+    if (bytes > budget || cur > budget - bytes) return false;
+  } while (!reserved.compare_exchange_weak(cur, cur + bytes));
+  return true;
+}
 }  // namespace rr
 
 struct rerank_ctx {
@@ -21,7 +31,7 @@ struct rerank_ctx {
   void* ws = nullptr;        // working set of rerank_run / rerank_knn / rerank_similarity
   size_t ws_bytes = 0;
   hipEvent_t ws_free = nullptr;  // recorded after the last direct call's kernels
-  std::atomic<size_t> reserved{0};  // bytes held by the direct working set + admitted requests
+  std::atomic<size_t> reserved{0};  // bytes held by the direct working set + the serving pool
   uint32_t flags = 0;
   rr::StageClock* clock = nullptr;  // set with RERANK_CTX_STAGE_TIMING
   rr::Server* server = nullptr;     // serving scheduler, started on first submit

@@ -22,16 +22,13 @@ rerank_status hip_fail(hipError_t e, const char* what) {
 }
 
 // Grow the direct-call working set to `bytes` (device memory, within budget).
+// Blocks the serving pool keeps cached are given back first when the budget
+// needs them; memory held by running serving requests is not waited for.
 static rerank_status ensure_ws(rerank_ctx* c, size_t bytes) {
   if (bytes <= c->ws_bytes) return RERANK_OK;
   if (bytes > c->budget) {
     set_error("working set of " + std::to_string(bytes) + " bytes exceeds the context budget of " +
               std::to_string(c->budget));
-    return RERANK_E_NOMEM;
-  }
-  const size_t others = c->reserved.load() - c->ws_bytes;
-  if (others + bytes > c->budget) {
-    set_error("working set does not fit next to the admitted serving requests");
     return RERANK_E_NOMEM;
   }
   if (c->ws) {
@@ -43,13 +40,20 @@ static rerank_status ensure_ws(rerank_ctx* c, size_t bytes) {
     c->ws = nullptr;
     c->ws_bytes = 0;
   }
+  if (!try_reserve(c->reserved, c->budget, bytes)) {
+    server_release_cache(c);
+    if (!try_reserve(c->reserved, c->budget, bytes)) {
+      set_error("working set does not fit next to the running serving requests");
+      return RERANK_E_NOMEM;
+    }
+  }
   hipError_t e = hipMalloc(&c->ws, bytes);
   if (e != hipSuccess) {
     c->ws = nullptr;
+    c->reserved -= bytes;
     return hip_fail(e, "hipMalloc(working set)");
   }
   c->ws_bytes = bytes;
-  c->reserved += bytes;
   return RERANK_OK;
 }
 

@@ -14,7 +14,8 @@
 // batch then costs one graph launch. Larger problems run the direct pipeline
 // on the slot's stream. Working sets come from a caching pool bounded by the
 // budget; features, lists and feature buffers stay in HBM for the whole
-// request.
+// request. A request's kernels start after the work its caller had enqueued
+// on the stream named at submit time (an event recorded there).
 #include "serve.h"
 
 #include <chrono>
@@ -43,6 +44,7 @@ struct Request {
   const void* x = nullptr;
   int in_bf16 = 0;
   float* dist = nullptr;
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submit
   bool small = false;
   BatchKey key{};
   void* ws = nullptr;
@@ -86,20 +88,22 @@ class Pool {
       return p;
     }
     // make room: drop cached blocks while the budget does not allow a new one
-    while (reserved_->load() + bytes > budget_ && !free_.empty()) {
+    bool ok = try_reserve(*reserved_, budget_, bytes);
+    while (!ok && !free_.empty()) {
       auto it = free_.begin();
       hipFree(it->first);
       *reserved_ -= it->second;
       free_.erase(it);
+      ok = try_reserve(*reserved_, budget_, bytes);
     }
-    if (reserved_->load() + bytes > budget_) return nullptr;
+    if (!ok) return nullptr;
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
+      *reserved_ -= bytes;
       *fatal = true;
       return nullptr;
     }
-    *reserved_ += bytes;
     live_[p] = bytes;
     return p;
   }
@@ -176,10 +180,18 @@ class Server {
       for (auto& s : slots_)
         for (auto& r : s.reqs) pool_.release(r->ws);
       pool_.release_cache();
+      for (hipEvent_t ev : events_) hipEventDestroy(ev);
+      events_.clear();
     }
   }
 
-  rerank_status submit(const rerank_params* p, const void* x, int in_bf16, float* dist, uint64_t* ticket) {
+  void release_cache() {
+    std::lock_guard<std::mutex> lk(mu_);
+    pool_.release_cache();
+  }
+
+  rerank_status submit(const rerank_params* p, const void* x, int in_bf16, float* dist, hipStream_t stream,
+                       uint64_t* ticket) {
     auto r = std::make_shared<Request>();
     r->params = *p;
     make_plan(p, false, &r->plan, (ctx_->flags & RERANK_CTX_DENSE_LAYERS) != 0);
@@ -194,10 +206,30 @@ class Server {
     r->small = p->n <= kGroupedMaxN && r->plan.rescore && r->plan.fprec == FinalPrec::F32;
     r->key = BatchKey{(int)r->plan.prec, r->plan.kc <= 64 ? 1 : (r->plan.kc <= 128 ? 2 : 4), p->layers, p->node,
                       p->aggregator};
+    // the request's kernels wait for what the caller enqueued on `stream` so far
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (!events_.empty()) {
+        r->ready = events_.back();
+        events_.pop_back();
+      }
+    }
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    hipError_t e = hipSetDevice(ctx_->device);
+    if (e == hipSuccess && !r->ready) e = hipEventCreateWithFlags(&r->ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(r->ready, stream);
+    if (prev >= 0 && prev != ctx_->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (r->ready) events_.push_back(r->ready);
+      return hip_fail(e, "recording the request's ready event on hip_stream");
+    }
     r->t_submit = Clock::now();
     {
       std::lock_guard<std::mutex> lk(mu_);
       if (stopping_) {
+        events_.push_back(r->ready);
         set_error("context is being destroyed");
         return RERANK_E_INVALID;
       }
@@ -263,6 +295,10 @@ class Server {
 
  private:
   void finish(const std::shared_ptr<Request>& r, rerank_status st, const std::string& err) {
+    if (r->ready) {
+      events_.push_back(r->ready);
+      r->ready = nullptr;
+    }
     r->status = st;
     r->error = err;
     r->state = Request::DONE;
@@ -372,11 +408,14 @@ class Server {
   // after failing its requests.
   void launch(Slot& s) {
     hipError_t e = hipSuccess;
-    const char* where = "launch";
-    if (s.reqs.size() == 1 && !s.reqs[0]->small) {
+    const char* where = "hipStreamWaitEvent";
+    for (auto& r : s.reqs)
+      if (e == hipSuccess) e = hipStreamWaitEvent(s.stream, r->ready, 0);
+    if (e == hipSuccess && s.reqs.size() == 1 && !s.reqs[0]->small) {
       Request& r = *s.reqs[0];
+      where = "launch";
       e = enqueue_rerank(r.plan, r.ws, r.x, r.in_bf16, r.dist, s.stream, &where, nullptr);
-    } else {
+    } else if (e == hipSuccess) {
       const BatchKey key = s.reqs[0]->key;
       fill_table(s, key);
       hipGraphExec_t ex = nullptr;
@@ -410,6 +449,30 @@ class Server {
     s.busy = true;
   }
 
+  bool any_busy() const {
+    for (auto& s : slots_)
+      if (s.busy) return true;
+    return false;
+  }
+
+  // The direct calls' working set is kept for their next call. When the head
+  // request does not fit next to it and no serving request holds memory, give
+  // it back (once its kernels have finished; a direct call in progress keeps
+  // it and is waited for). Called with mu_ held; only tries the context lock.
+  bool reclaim_direct_ws() {
+    std::unique_lock<std::mutex> lk(ctx_->mu, std::try_to_lock);
+    if (!lk.owns_lock() || !ctx_->ws) return false;
+    if (hipEventQuery(ctx_->ws_free) != hipSuccess) return false;
+    if (hipFree(ctx_->ws) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    ctx_->reserved -= ctx_->ws_bytes;
+    ctx_->ws = nullptr;
+    ctx_->ws_bytes = 0;
+    return true;
+  }
+
   // Admit pending requests into idle slots (called with mu_ held).
   void dispatch() {
     while (!pending_.empty()) {
@@ -424,7 +487,12 @@ class Server {
       bool fatal = false;
       void* ws = pool_.alloc(head->ws_bytes, &fatal);
       if (!ws) {
-        if (!fatal) return;  // wait for memory to free up (arrival order is kept)
+        if (!fatal) {
+          // the pool has already dropped its cached blocks; with no request
+          // running, only the direct calls' working set can be in the way
+          if (!any_busy() && reclaim_direct_ws()) continue;
+          return;  // wait for memory to free up (arrival order is kept)
+        }
         pending_.pop_front();
         finish(head, RERANK_E_NOMEM, "device allocation of the working set failed");
         cv_done_.notify_all();
@@ -490,14 +558,15 @@ class Server {
       } else {
         dispatch();
       }
-      bool any_busy = false;
-      for (auto& s : slots_) any_busy |= s.busy;
-      if (any_busy) {
+      if (any_busy()) {
         lk.unlock();
         std::this_thread::sleep_for(std::chrono::microseconds(20));
         lk.lock();
       } else if (!stopping_) {
-        cv_work_.wait(lk, [&] { return stopping_ || !pending_.empty(); });
+        if (pending_.empty())
+          cv_work_.wait(lk, [&] { return stopping_ || !pending_.empty(); });
+        else  // the head waits for memory a direct call still uses: retry shortly
+          cv_work_.wait_for(lk, std::chrono::microseconds(200));
       }
     }
     // fail whatever is still pending at shutdown
@@ -512,6 +581,7 @@ class Server {
   std::mutex mu_;
   std::condition_variable cv_work_, cv_done_;
   std::deque<std::shared_ptr<Request>> pending_;
+  std::vector<hipEvent_t> events_;  // ready events of finished requests, for reuse
   std::map<uint64_t, std::shared_ptr<Request>> tickets_;
   uint64_t next_ticket_ = 1;
   bool stopping_ = false;
@@ -528,6 +598,10 @@ void server_stop(Server* s) {
 static Server* server_of(rerank_ctx* ctx) {
   std::lock_guard<std::mutex> lk(ctx->server_mu);
   return ctx->server;
+}
+
+void server_release_cache(rerank_ctx* ctx) {
+  if (Server* s = server_of(ctx)) s->release_cache();
 }
 
 static rerank_status get_server(rerank_ctx* ctx, Server** out) {
@@ -553,7 +627,7 @@ using namespace rr;
 extern "C" {
 
 rerank_status rerank_submit(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype, float* d_dist,
-                            uint64_t* ticket) {
+                            void* hip_stream, uint64_t* ticket) {
   if (!ctx || !ticket) {
     set_error("ctx or ticket is NULL");
     return RERANK_E_INVALID;
@@ -575,7 +649,7 @@ rerank_status rerank_submit(rerank_ctx* ctx, const rerank_params* p, const void*
   Server* s = nullptr;
   st = get_server(ctx, &s);
   if (st != RERANK_OK) return st;
-  return s->submit(p, d_x, in_dtype == RERANK_IN_BF16, d_dist, ticket);
+  return s->submit(p, d_x, in_dtype == RERANK_IN_BF16, d_dist, (hipStream_t)hip_stream, ticket);
 }
 
 rerank_status rerank_poll(rerank_ctx* ctx, uint64_t ticket, int* done) {

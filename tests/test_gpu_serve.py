@@ -169,3 +169,50 @@ def test_variants_same_alone_and_in_the_mix(gpu_lib, kw):
     for o, ref in zip(outs, solo):
         assert np.array_equal(o.cpu().numpy(), ref)
     ctx.close()
+
+
+def test_submit_waits_for_the_stream_that_produced_the_features(gpu_lib):
+    # x is written on the current stream behind a long queue of products, and
+    # submitted with no host synchronisation: the request must see the final x
+    import torch
+    from paper_2012_07620_amd import binding
+    probs = _requests(61, 3, 3000, 6000, dims=(256,))
+    solo = _solo(probs)
+    ctx = binding.Context(0)
+    src = [_dev(p) for p in probs]
+    xs = [torch.zeros_like(s) for s in src]
+    outs = [torch.full((p.spec.n_query, p.spec.n_gallery), float("nan"), device="cuda") for p in probs]
+    a = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    tickets = []
+    for p, s, x, o in zip(probs, src, xs, outs):
+        for _ in range(8):  # tens of milliseconds of queued work before the copy
+            a = torch.tanh(a @ a)
+        x.copy_(s)
+        sp = p.spec
+        tickets.append(binding.submit(ctx, x, o, sp.n_query, sp.k1, sp.k2, sp.layers))
+    for t in tickets:
+        binding.wait(ctx, t)
+    for o, ref in zip(outs, solo):
+        assert np.array_equal(o.cpu().numpy(), ref)
+    ctx.close()
+
+
+def test_direct_calls_and_requests_share_the_budget(gpu_lib):
+    # the direct call's working set stays cached in the context; a request that
+    # fits the budget alone (but not next to it) must still run, and a later
+    # direct call must get back the blocks the serving pool cached meanwhile
+    from paper_2012_07620_amd import binding
+    probs = _requests(71, 2, 6000, 6000, dims=(128,))
+    need = binding.workspace_bytes(binding.make_params(6000, 900, 128, 20, 6, 1))
+    solo = _solo(probs)
+    ctx = binding.Context(0, budget_bytes=int(need * 1.5))
+    s0, s1 = probs[0].spec, probs[1].spec
+    d0 = binding.run(_dev(probs[0]), s0.n_query, s0.k1, s0.k2, s0.layers, ctx=ctx)
+    xs, outs, tickets = _serve(ctx, probs[1:])
+    binding.wait(ctx, tickets[0], timeout_us=60_000_000)
+    d0b = binding.run(_dev(probs[0]), s0.n_query, s0.k1, s0.k2, s0.layers, ctx=ctx)
+    assert np.array_equal(d0.cpu().numpy(), solo[0])
+    assert np.array_equal(d0b.cpu().numpy(), solo[0])
+    assert np.array_equal(outs[0].cpu().numpy(), solo[1])
+    ctx.close()
