@@ -6,11 +6,26 @@ resident synthetic problem. Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mid|tiny|large]
 
-``value`` is N^2-elements per second of the FP32 path (N^2 / request time);
-``ms_per_step`` the FP32 request time. The same line carries the BF16 / FP8
-similarity variants on the same arrays, per-stage device times measured with
-HIP events on the launch stream, the roofline fraction of the dominant
-kernel, and the FP64 oracle timed on the host cores on the same problem.
+``value`` is N^2-elements per second of the FP32 path on the headline
+workload (mid_n19281_d2048: N^2 / request time); ``ms_per_step`` its request
+time. The same line carries:
+
+* ``stages_ms`` / ``stage_roofline``: per-stage device times measured with HIP
+  events that the library records on the launch stream, and each stage's
+  achieved rate against its roofline. The work per stage is what the kernels
+  that run for these parameters must move or compute (``stage_work``);
+* ``roofline``: the dominant kernel (the final FP32 product) against the FP32
+  matrix-core peak, with its HBM traffic from committed rocprofv3 counters;
+* ``variants``: the low-precision similarity paths (BF16; FP8 at the
+  top-(k1+16) candidates the workload names, and FP8 at k1+32) and the
+  final-product variants, each with its accuracy against the FP64 oracle;
+* ``large``: the large_n50000_d512 workload (two layers), FP32 and BF16 side
+  by side, with its own roofline and oracle baseline;
+* ``serving``: the request stream (Poisson arrivals, N ~ U[1000, 30000]):
+  closed-loop saturation, then open-loop p50 / p99 latency at 0.5 and 0.7 of
+  the FP32 saturation rate, for the FP32, BF16 and BF16 + sparse-final paths;
+* ``cpu_baseline``: the FP64 oracle timed on this host (model and threads
+  stated).
 """
 from __future__ import annotations
 
@@ -27,42 +42,92 @@ sys.path.insert(0, ROOT)
 
 METRIC = "re-rank ms/request + N²-elem/s (FP32 vs BF16), p50/p99 at fixed QPS"
 PEAK = {"fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2500.0, "fp8_mfma_tflops": 5000.0, "hbm_gbs": 8000.0}
+EXTRA = {"f32": 8, "bf16": 16, "fp8": 32}  # the library's default candidates beyond k1
 
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def stage_work(spec, prec: str):
-    """Algorithmic work of one request per stage: (unit, amount)."""
+def pad(v: int, m: int) -> int:
+    return (v + m - 1) // m * m
+
+
+def stage_work(spec, prec: str = "f32", extra=None, final: str = "f32", aggregator: str = "sum",
+               node: str = "adj"):
+    """Algorithmic work of one request per stage, on the path the library runs
+    for these parameters: {stage: (unit, amount)}, unit "flop" (matrix cores)
+    or "byte" (HBM). Bytes count what the stage's kernels must read or write
+    at least once; re-reads that the design serves from the L2 cache (the
+    re-score's candidate rows, the k2 neighbour rows of a dense layer) are not
+    counted, so a rate above the HBM peak cannot arise."""
     n, q, g, d = spec.n, spec.n_query, spec.n_gallery, spec.dim
     k1, k2, L = spec.k1, spec.k2, spec.layers
-    kc = min(k1 + {"f32": 8, "bf16": 16, "fp8": 32}[prec], n, 256)
-    return {
-        "similarity": ("flop", 1.0 * n * (n + 1) * d),  # unique entries of the symmetric S
-        "topk": ("byte", 4.0 * n * n),
-        "rescore": ("flop", 2.0 * n * kc * d),
-        "adjacency": ("byte", 4.0 * n * n),
-        "propagate": ("byte", L * (k2 + 2) * 4.0 * n * n),
-        "final": ("flop", 2.0 * q * g * n),
+    ldN, ldp = pad(n, 64), pad(d, 64)
+    ldH = ldp if node == "raw" else ldN
+    lb = {"f32": 0, "bf16": 2, "fp8": 1}[prec]
+    ldl = pad(d, 128 // lb) if lb else 0
+    kc = min(k1 + (EXTRA[prec] if extra is None or extra < 0 else extra), n, 256)
+    in_b = 2 if spec.dtype == "bf16" else 4
+    s_b = 4 if prec == "f32" else 2  # the low-precision paths store S as binary16
+    w = {
+        # read X; write the padded FP32 copy, the low-precision copy, norms and scales
+        "prep": ("byte", n * d * in_b + n * ldp * 4 + n * ldl * lb + 8 * n),
+        # the unique entries of the symmetric S
+        "similarity": ("flop", n * (n + 1) * d),
+        # read S once, write the candidate lists
+        "topk": ("byte", s_b * n * n + 8 * n * kc),
+        # every feature row at least once, the candidates in, the k1 lists out
+        "rescore": ("byte", n * ldp * 4 + 8 * n * kc + 8 * n * k1),
+        "final": ("flop", 2 * q * g * n),
     }
+    planes = {"bf16x3": 2, "bf16": 1}.get(final, 0)  # bf16 copies of the last layer
+    sparse_first = node != "raw" and L >= 1 and aggregator != "max"
+    prop = 0
+    if node == "raw":
+        w["adjacency"] = ("byte", 0)
+        dense = L
+    elif sparse_first:
+        # mutual flags (lists read, one byte per edge written) and the in-edge CSR
+        # (lists and flags read, in-edges written); A-row features need neither
+        w["adjacency"] = ("byte", (14 * n * k1 + 16 * n) if node == "adj" else 8 * n)
+        # layer 1 written once per row from the sparse rows (lists, weights, flags, CSR read)
+        prop += 4 * n * ldN + 13 * n * k1 + 4 * n
+        dense = L - 1
+    else:  # dense A* rows: zero fill plus the scatter of the lists
+        w["adjacency"] = ("byte", 4 * n * ldN + 12 * n * k1 + 8 * n)
+        dense = L
+    if dense > 0:  # each dense layer reads every row once and writes every row once
+        prop += dense * (8 * n * ldH + 8 * n * k2) + 4 * n * k1
+    if L >= 1:
+        prop += planes * 2 * n * ldH
+    w["propagate"] = ("byte", prop)
+    return w
 
 
-def roofline_entry(stage, unit, amount, ms, prec):
-    if ms <= 0:
+def mfma_peak(stage: str, prec: str, final: str) -> float:
+    if stage == "similarity":
+        return {"f32": PEAK["fp32_mfma_tflops"], "bf16": PEAK["bf16_mfma_tflops"],
+                "fp8": PEAK["fp8_mfma_tflops"]}[prec]
+    return {"f32": PEAK["fp32_mfma_tflops"], "bf16": PEAK["bf16_mfma_tflops"],
+            "bf16x3": PEAK["bf16_mfma_tflops"] / 3}[final]
+
+
+def roofline_entry(stage, unit, amount, ms, prec="f32", final="f32"):
+    """Achieved rate of one stage against its roofline (None if it did not run)."""
+    if ms <= 0 or amount <= 0:
         return None
     if unit == "flop":
         ach = amount / (ms * 1e-3) / 1e12
-        peak = PEAK["fp32_mfma_tflops"]
-        if stage == "similarity" and prec == "bf16":
-            peak = PEAK["bf16_mfma_tflops"]
-        if stage == "similarity" and prec == "fp8":
-            peak = PEAK["fp8_mfma_tflops"]
-        if stage == "rescore":
-            return {"bound": "alu", "achieved": ach, "unit": "TFLOP/s"}
-        return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak}
+        peak = mfma_peak(stage, prec, final)
+        e = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+             "work": amount}
+        if stage == "final" and final == "bf16x3":
+            e["unit"] = "TFLOP/s (FP32-equivalent: three bf16 products per FP32 product)"
+        return e
     ach = amount / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": ach / PEAK["hbm_gbs"]}
+    return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": ach / PEAK["hbm_gbs"],
+            "work": amount}
 
 
 # Source files each stage's kernels are compiled from: measured counters stay
@@ -73,6 +138,7 @@ KERNEL_SOURCES = {
     "topk": ("common.h", "rows_body.h", "k_topk.hip"),
     "rescore": ("common.h", "rows_body.h", "k_graph.hip"),
     "propagate": ("common.h", "rows_body.h", "k_graph.hip"),
+    "adjacency": ("common.h", "rows_body.h", "k_graph.hip"),
     "prep": ("common.h", "rows_body.h", "k_prep.hip"),
     "sparse_final": ("common.h", "kernels.h", "gemm_body.h", "rows_body.h", "k_sparse.hip"),
     "sparse_layers": ("common.h", "kernels.h", "gemm_body.h", "rows_body.h", "k_sparse.hip", "k_graph.hip"),
@@ -104,8 +170,20 @@ def measured_traffic(workload: str, path: str, role: str):
             "bytes": k["read_bytes"] + k["write_bytes"], "source": os.path.relpath(f, ROOT)}
 
 
-def time_path(binding, torch, ctx, x, spec, prec, steps, warmup, out, final_prec="f32"):
-    kw = dict(sim_prec=prec, ctx=ctx, out=out, final_prec=final_prec)
+def stage_rooflines(spec, stages, path="f32", prec="f32", final="f32", extra=None):
+    work = stage_work(spec, prec, extra, final)
+    out = {}
+    for k, (unit, amount) in work.items():
+        e = roofline_entry(k, unit, amount, stages.get(k, 0.0), prec, final)
+        if e is not None:
+            tr = measured_traffic(spec.name, path, k)
+            e["traffic"] = tr["bytes"] if tr else None
+        out[k] = e
+    return out
+
+
+def time_path(binding, torch, ctx, x, spec, prec, steps, warmup, out, final_prec="f32", extra=-1):
+    kw = dict(sim_prec=prec, ctx=ctx, out=out, final_prec=final_prec, extra_cand=extra)
     for _ in range(warmup):
         binding.run(x, spec.n_query, spec.k1, spec.k2, spec.layers, **kw)
     torch.cuda.synchronize()
@@ -121,57 +199,167 @@ def time_path(binding, torch, ctx, x, spec, prec, steps, warmup, out, final_prec
     return ms, ctx.stage_times()
 
 
-def serve_stream(binding, torch, synth, count, warmup, qps=None, prec="f32", reqs=None):
-    """Submit the requests of a serving stream and wait for all of them.
-
-    qps None: closed loop (everything submitted at once; the throughput is the
-    saturation rate). Otherwise requests are submitted at their Poisson arrival
-    times. Latency = submit -> completion, as measured by the library."""
-    ctx = binding.Context(0)
-    xs, outs, specs = reqs
-    # warm-up requests: compile graphs, fill the working-set cache
-    for i in range(warmup):
-        s = specs[i]
-        t = binding.submit(ctx, xs[i], outs[i], s.n_query, s.k1, s.k2, s.layers, sim_prec=prec)
-        binding.wait(ctx, t)
-    meas = range(warmup, warmup + count)
-    rng = np.random.default_rng(17)
-    gaps = rng.exponential(1.0 / qps, len(meas)) if qps else np.zeros(len(meas))
-    arrivals = np.cumsum(gaps) - gaps[0]
+def lists_of(binding, torch, ctx, x, spec, prec, final_prec="f32", extra=-1):
+    """One untimed run returning (D, lists) on the host, for the accuracy report."""
+    d, ki, _ = binding.run(x, spec.n_query, spec.k1, spec.k2, spec.layers, sim_prec=prec, final_prec=final_prec,
+                           extra_cand=extra, ctx=ctx, return_knn=True)
     torch.cuda.synchronize()
+    return d.cpu().numpy(), ki.cpu().numpy()
+
+
+def accuracy(d, ki, ref):
+    """Error of a GPU result against the FP64 oracle: mean top-k1 set overlap,
+    rows whose k1 set differs, and max / mean |D - D64|."""
+    k1 = ref.graph.idx.shape[1]
+    a = np.sort(ki, 1)
+    b = np.sort(ref.graph.idx, 1)
+    same = np.sum(a[:, :, None] == b[:, None, :], axis=(1, 2))
+    err = np.abs(d.astype(np.float64) - ref.dist)
+    return {"k1_overlap": float(same.mean() / k1), "rows_k1_set_differs": int(np.sum(same < k1)),
+            "d_max_abs_err_vs_fp64": float(err.max()), "d_mean_abs_err_vs_fp64": float(err.mean())}
+
+
+# ------------------------------------------------------------------ serving
+def serve_leg(binding, torch, reqs, count, warmup, prec, final="f32", qps=None, seed=17):
+    """One serving leg on a fresh context: `warmup` requests (closed loop, not
+    measured), then `count` measured submissions cycling through the distinct
+    problems in `reqs`. Submission k reuses the output buffer of k - P (P
+    distinct problems) only after k - P is done. qps None: closed loop with P
+    requests in flight (the saturation rate). Otherwise Poisson arrivals at
+    `qps`; latency = arrival -> completion (any delay of the submission past
+    its arrival time included)."""
+    xs, outs, specs = reqs
+    P = len(xs)
+    ctx = binding.Context(0)
+
+    def submit(k):
+        i = k % P
+        s = specs[i]
+        return binding.submit(ctx, xs[i], outs[i], s.n_query, s.k1, s.k2, s.layers, sim_prec=prec,
+                              final_prec=final)
+
+    wt = [submit(k) for k in range(min(warmup, P))]
+    for k in range(len(wt), warmup):
+        binding.wait(ctx, wt[k - P])
+        wt.append(submit(k))
+    for k in range(max(0, warmup - P), warmup):
+        binding.wait(ctx, wt[k])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / qps, count) if qps else np.zeros(count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    tickets, late, lat = [], np.zeros(count), np.zeros(count)
+    done = np.zeros(count, dtype=bool)
     t0 = time.perf_counter()
-    tickets = []
-    for k, i in enumerate(meas):
+    for k in range(count):
+        if k >= P and not done[k - P]:
+            lat[k - P] = binding.wait(ctx, tickets[k - P])
+            done[k - P] = True
         if qps:
             delay = t0 + arrivals[k] - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
-        s = specs[i]
-        tickets.append(binding.submit(ctx, xs[i], outs[i], s.n_query, s.k1, s.k2, s.layers, sim_prec=prec))
-    lat = [binding.wait(ctx, t) for t in tickets]
+            else:
+                late[k] = -delay * 1e3
+        tickets.append(submit(warmup + k))
+    for k in range(count):
+        if not done[k]:
+            lat[k] = binding.wait(ctx, tickets[k])
+            done[k] = True
     t1 = time.perf_counter()
     ctx.close()
-    n2 = sum(specs[i].n ** 2 for i in meas)
-    return {"requests": len(meas), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(np.mean(lat)), "req_per_s": len(meas) / (t1 - t0), "n2_per_s": n2 / (t1 - t0)}
+    lat = lat + late
+    n2 = sum(specs[(warmup + k) % P].n ** 2 for k in range(count))
+    return {"requests": count, "warmup": warmup, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(np.mean(lat)), "max_ms": float(lat.max()),
+            "req_per_s": count / (t1 - t0), "n2_per_s": n2 / (t1 - t0),
+            "late_submissions": int(np.sum(late > 0))}
 
 
-def serving_bench(binding, torch, synth, count, warmup):
+def serving_bench(binding, torch, synth, count, warmup, distinct, oracle_sample):
     stream = synth.StreamSpec()
-    specs = [s for _, s in synth.request_specs(stream, count + warmup, qps=1.0)]
+    specs = [s for _, s in synth.request_specs(stream, distinct, qps=1.0)]
     dev = torch.device("cuda:0")
     xs = [synth.make_features_device(s, dev) for s in specs]
     outs = [torch.empty((s.n_query, s.n_gallery), dtype=torch.float32, device=dev) for s in specs]
     torch.cuda.synchronize()
     reqs = (xs, outs, specs)
-    sat = serve_stream(binding, torch, synth, count, warmup, None, "f32", reqs)
-    qps = 0.7 * sat["req_per_s"]
-    res = {"stream": "N ~ U[1000, 30000], 15% queries, d in {512, 2048}, bf16, k1=20 k2=6 L=1, Poisson arrivals",
-           "saturation_f32_req_per_s": sat["req_per_s"], "qps": qps}
-    for prec in ("f32", "bf16"):
-        res[prec] = serve_stream(binding, torch, synth, count, warmup, qps, prec, reqs)
+    res = {"stream": ("Poisson arrivals; N ~ U[1000, 30000], 15% queries, d in {512, 2048} (p = 1/2), bf16 "
+                      "clustered features (N/20 identities, sigma 0.5, 5% distractors), k1=20 k2=6 L=1"),
+           "protocol": {"warmup_requests": warmup, "measured_requests": count, "distinct_problems": distinct,
+                        "latency": "arrival -> completion (rerank_wait), queueing included"},
+           "saturation": {}, "open_loop": {}}
+    for name, prec, final in (("f32", "f32", "f32"), ("bf16", "bf16", "f32"),
+                              ("bf16_final_sparse", "bf16", "sparse")):
+        log(f"serving: closed-loop saturation, {name}")
+        res["saturation"][name] = serve_leg(binding, torch, reqs, count, warmup, prec, final)
+    mu = res["saturation"]["f32"]["req_per_s"]
+    res["mu_f32_req_per_s"] = mu
+    for frac in (0.5, 0.7):
+        leg = {"qps": frac * mu}
+        for name, prec, final in (("f32", "f32", "f32"), ("bf16", "bf16", "f32"),
+                                  ("bf16_final_sparse", "bf16", "sparse")):
+            if frac == 0.5 and name == "bf16_final_sparse":
+                continue
+            log(f"serving: open loop at {frac} x mu_f32 = {frac * mu:.1f} req/s, {name}")
+            leg[name] = serve_leg(binding, torch, reqs, count, warmup, prec, final, qps=frac * mu)
+        res["open_loop"][str(frac)] = leg
+    if oracle_sample:
+        res["oracle"] = serving_oracle(torch, xs[:oracle_sample], specs[:oracle_sample])
     del xs, outs
     return res
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        logical = len(os.sched_getaffinity(0))
+    except AttributeError:
+        logical = os.cpu_count() or 1
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas = 1
+    return model, logical, int(blas)
+
+
+def timed_oracle(x32, spec):
+    from oracle import rerank_oracle as orc
+    t0 = time.perf_counter()
+    ref = orc.rerank(x32, spec.n_query, spec.k1, spec.k2, spec.layers)
+    return ref, time.perf_counter() - t0
+
+
+def cpu_baseline_entry(n2, seconds, sample):
+    model, logical, blas = cpu_info()
+    return {"value": n2 / seconds, "unit": "N^2-elem/s", "seconds": seconds, "cores": blas, "kind": "oracle",
+            "cpu_model": model, "logical_cpus_available": logical,
+            "threads": (f"float64 matrix products on {blas} BLAS threads; the per-row neighbour selection and "
+                        "the sparse propagation run on one thread"),
+            "sample": sample}
+
+
+def serving_oracle(torch, xs, specs):
+    """The FP64 oracle on the first requests of the serving stream."""
+    secs, n2 = 0.0, 0
+    for x, s in zip(xs, specs):
+        x32 = x.float().cpu().numpy()
+        _, t = timed_oracle(x32, s)
+        secs += t
+        n2 += s.n ** 2
+    e = cpu_baseline_entry(n2, secs, f"the whole FP64 oracle on the first {len(xs)} requests of the stream "
+                                     f"(N = {[s.n for s in specs]})")
+    e["req_per_s"] = len(xs) / secs
+    return e
 
 
 def quality_check(binding, torch, synth, spec, dev):
@@ -196,20 +384,115 @@ def quality_check(binding, torch, synth, spec, dev):
     return out
 
 
-def cpu_baseline(x32, spec):
-    """The FP64 oracle (as it stands) on the same problem, on this host."""
-    from oracle import rerank_oracle as orc
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    t0 = time.perf_counter()
-    ref = orc.rerank(x32, spec.n_query, spec.k1, spec.k2, spec.layers)
-    t = time.perf_counter() - t0
-    return ref, {"value": spec.n * spec.n / t, "unit": "N^2-elem/s", "ms_per_request": t * 1e3,
-                 "cores": int(threads), "kind": "oracle",
-                 "sample": f"the whole {spec.name} request (float64 NumPy/SciPy oracle, one pass)"}
+def device_x(torch, prob, dev):
+    if prob.spec.dtype == "bf16":
+        return torch.from_numpy(prob.x_bf16.view(np.int16)).to(dev).view(torch.bfloat16)
+    return torch.from_numpy(prob.x32).to(dev)
+
+
+def dominant_roofline(spec, stages, roof, path="f32"):
+    dominant = max((k for k in roof if roof[k] is not None), key=lambda k: stages[k])
+    dom = dict(roof[dominant])
+    tr = measured_traffic(spec.name, path, dominant)
+    dom.update({"kernel": dominant, "traffic": tr["bytes"] if tr else None, "traffic_detail": tr,
+                "ms_per_launch": stages[dominant]})
+    return dom
+
+
+# Variants timed on the headline workload: (name, similarity, final, extra candidates, fused k-NN)
+VARIANTS = (
+    ("bf16", "bf16", "f32", -1, False),
+    ("fp8", "fp8", "f32", 16, False),        # top-(k1 + 16) as the reduced-precision workload states
+    ("fp8_k1p32", "fp8", "f32", 32, False),  # the library's FP8 default
+    ("f32_final_bf16x3", "f32", "bf16x3", -1, False),
+    ("bf16_final_bf16x3", "bf16", "bf16x3", -1, False),
+    ("f32_final_sparse", "f32", "sparse", -1, False),
+    ("bf16_final_sparse", "bf16", "sparse", -1, False),
+    ("fp8_final_sparse", "fp8", "sparse", -1, False),
+    ("bf16_final_bf16", "bf16", "bf16", -1, False),
+    ("fp8_final_bf16", "fp8", "bf16", -1, False),
+    ("f32_fused_knn", "f32", "f32", -1, True),
+    ("bf16_fused_knn_final_sparse", "bf16", "sparse", -1, True),
+    ("fp8_fused_knn_final_sparse", "fp8", "sparse", -1, True),
+)
+
+
+def run_variants(binding, torch, spec, x, ctx, out, ms_ref, steps, warmup, selected):
+    res, results = {}, {}
+    ctx_fused = None
+    for name, prec, fprec, extra, fused in VARIANTS:
+        if selected and name not in selected:
+            continue
+        log(f"timing {name} path")
+        if fused and ctx_fused is None:
+            ctx_fused = binding.Context(0, stage_timing=True, fused_knn=True)
+        c = ctx_fused if fused else ctx
+        out_l = torch.empty_like(out)
+        ms_l, st_l = time_path(binding, torch, c, x, spec, prec, steps, warmup, out_l, fprec, extra)
+        wl = stage_work(spec, prec, extra, fprec)
+        entry = {"similarity": prec, "final": fprec, "extra_cand": extra if extra >= 0 else EXTRA[prec],
+                 "fused_knn": fused, "ms_per_request": ms_l, "value": spec.n ** 2 / (ms_l * 1e-3),
+                 "speedup_vs_f32": ms_ref / ms_l, "stages_ms": st_l,
+                 "similarity_roofline": roofline_entry("similarity", *wl["similarity"], st_l["similarity"], prec)}
+        if fprec in ("bf16x3", "bf16"):
+            entry["final_roofline"] = roofline_entry("final", *wl["final"], st_l["final"], prec, fprec)
+        if fprec == "sparse":
+            # the rows reach the product as CSR (a few hundred bytes each), so the floor is writing D once
+            nbytes = 4.0 * spec.n_query * spec.n_gallery
+            e = roofline_entry("final", "byte", nbytes, st_l["final"])
+            tr = measured_traffic(spec.name, name, "sparse_final")
+            e.update({"traffic": tr["bytes"] if tr else None, "traffic_detail": tr})
+            entry["final_roofline"] = e
+        if fused:  # the similarity stage also selects the candidates; the full product is computed
+            entry["similarity_roofline"]["note"] = ("fused similarity + top-k: every tile of the N x N product "
+                                                    "(twice the symmetric product's flops), S never written")
+            kp = binding.make_params(spec.n, spec.n_query, spec.dim, spec.k1, spec.k2, spec.layers, sim_prec=prec)
+            entry["knn_workspace_bytes"] = {"unfused": binding.knn_workspace_bytes(kp),
+                                            "fused": binding.knn_workspace_bytes(kp, fused_knn=True)}
+        results[name] = lists_of(binding, torch, c, x, spec, prec, fprec, extra)
+        res[name] = entry
+    if ctx_fused is not None:
+        ctx_fused.close()
+    return res, results
+
+
+def large_section(binding, torch, synth, steps, warmup, cpu_baseline):
+    """The large workload (N = 50000, d = 512, bf16 features, two layers):
+    FP32 and BF16 side by side, stage rooflines, and the oracle on the same
+    request."""
+    spec = synth.LARGE
+    log(f"workload {spec.name}: generating")
+    prob = synth.make_problem(spec)
+    dev = torch.device("cuda:0")
+    x = device_x(torch, prob, dev)
+    ctx = binding.Context(0, stage_timing=True)
+    out = torch.empty((spec.n_query, spec.n_gallery), dtype=torch.float32, device=dev)
+    log("timing large fp32 path")
+    ms, stages = time_path(binding, torch, ctx, x, spec, "f32", steps, warmup, out)
+    roof = stage_rooflines(spec, stages)
+    res = {"workload": spec.name, "steps": steps, "warmup": warmup,
+           "config": {"n": spec.n, "n_query": spec.n_query, "n_gallery": spec.n_gallery, "dim": spec.dim,
+                      "k1": spec.k1, "k2": spec.k2, "layers": spec.layers, "input_dtype": spec.dtype},
+           "ms_per_request": ms, "value": spec.n ** 2 / (ms * 1e-3), "unit": "N^2-elem/s", "stages_ms": stages,
+           "stage_roofline": roof, "roofline": dominant_roofline(spec, stages, roof), "paths": {}}
+    for name, prec, fprec in (("bf16", "bf16", "f32"), ("bf16_final_sparse", "bf16", "sparse"),
+                              ("bf16_final_bf16", "bf16", "bf16")):
+        log(f"timing large {name} path")
+        ms_l, st_l = time_path(binding, torch, ctx, x, spec, prec, steps, warmup, out, fprec)
+        wl = stage_work(spec, prec, None, fprec)
+        res["paths"][name] = {"ms_per_request": ms_l, "value": spec.n ** 2 / (ms_l * 1e-3),
+                              "speedup_vs_f32": ms / ms_l, "stages_ms": st_l,
+                              "similarity_roofline": roofline_entry("similarity", *wl["similarity"],
+                                                                    st_l["similarity"], prec)}
+    ctx.close()
+    del x, out
+    if cpu_baseline:
+        log("timing the FP64 oracle on the large workload")
+        _, t = timed_oracle(prob.x32, spec)
+        res["cpu_baseline"] = cpu_baseline_entry(spec.n ** 2, t, f"the whole {spec.name} request (float64 "
+                                                                   "NumPy/SciPy oracle, one pass)")
+        res["cpu_baseline"]["ms_per_request"] = t * 1e3
+    return res
 
 
 def main() -> int:
@@ -221,9 +504,14 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lowp", action="store_true", help="skip every variant line")
     ap.add_argument("--variants", default="", help="comma-separated variant names to time (default: all)")
+    ap.add_argument("--no-large", action="store_true", help="skip the large workload section")
+    ap.add_argument("--large-steps", type=int, default=4)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-quality", action="store_true", help="skip the mAP / Recall@K check")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-distinct", type=int, default=400)
+    ap.add_argument("--serve-oracle", type=int, default=12, help="requests of the stream the oracle is timed on")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy a 1 GiB float32 tensor once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -239,75 +527,21 @@ def main() -> int:
     log(f"workload {spec.name}: generating")
     prob = synth.make_problem(spec)
     dev = torch.device("cuda:0")
-    if spec.dtype == "bf16":
-        x = torch.from_numpy(prob.x_bf16.view(np.int16)).to(dev).view(torch.bfloat16)
-    else:
-        x = torch.from_numpy(prob.x32).to(dev)
+    x = device_x(torch, prob, dev)
     ctx = binding.Context(0, stage_timing=True)
     out = torch.empty((spec.n_query, spec.n_gallery), dtype=torch.float32, device=dev)
 
     log("timing fp32 path")
     ms, stages = time_path(binding, torch, ctx, x, spec, "f32", args.steps, args.warmup, out)
-    d_f32 = out.cpu().numpy()
-    work = stage_work(spec, "f32")
-    roof = {k: roofline_entry(k, *work[k], stages[k], "f32") for k in work}
-    dominant = max(work, key=lambda k: stages[k])
-    dom = dict(roof[dominant])
-    tr = measured_traffic(spec.name, "f32", dominant)
-    dom.update({"kernel": dominant, "traffic": tr["bytes"] if tr else None, "traffic_detail": tr,
-                "ms_per_launch": stages[dominant]})
+    roof = stage_rooflines(spec, stages)
+    dom = dominant_roofline(spec, stages, roof)
+    results = {"f32": lists_of(binding, torch, ctx, x, spec, "f32")}
 
     lowp = {}
     if not args.no_lowp:
-        ctx_fused = None  # similarity fused with the candidate selection (S never written)
-        for name, prec, fprec in (("bf16", "bf16", "f32"), ("fp8", "fp8", "f32"),
-                                  ("f32_final_bf16x3", "f32", "bf16x3"), ("bf16_final_bf16x3", "bf16", "bf16x3"),
-                                  ("f32_final_sparse", "f32", "sparse"), ("bf16_final_sparse", "bf16", "sparse"),
-                                  ("fp8_final_sparse", "fp8", "sparse"), ("bf16_final_bf16", "bf16", "bf16"),
-                                  ("fp8_final_bf16", "fp8", "bf16"), ("f32_fused_knn", "f32", "f32"),
-                                  ("bf16_fused_knn_final_sparse", "bf16", "sparse"),
-                                  ("fp8_fused_knn_final_sparse", "fp8", "sparse")):
-            if args.variants and name not in args.variants.split(","):
-                continue
-            log(f"timing {name} path")
-            fused = "_fused_knn" in name
-            if fused and ctx_fused is None:
-                ctx_fused = binding.Context(0, stage_timing=True, fused_knn=True)
-            out_l = torch.empty_like(out)
-            ms_l, st_l = time_path(binding, torch, ctx_fused if fused else ctx, x, spec, prec, args.steps, args.warmup,
-                                   out_l, fprec)
-            wl = stage_work(spec, prec)
-            entry = {"similarity": prec, "final": fprec, "fused_knn": fused, "ms_per_request": ms_l,
-                     "value": spec.n ** 2 / (ms_l * 1e-3),
-                     "speedup_vs_f32": ms / ms_l, "stages_ms": st_l,
-                     "similarity_roofline": roofline_entry("similarity", *wl["similarity"], st_l["similarity"], prec),
-                     "dist": out_l.cpu().numpy()}
-            if fprec == "bf16x3":
-                fl = wl["final"][1] / (st_l["final"] * 1e-3) / 1e12
-                entry["final_roofline"] = {"bound": "mfma", "achieved": fl, "peak": PEAK["bf16_mfma_tflops"] / 3,
-                                           "unit": "TFLOP/s (FP32-equivalent; 3 bf16 products per FP32 product)",
-                                           "frac": fl / (PEAK["bf16_mfma_tflops"] / 3)}
-            if fprec == "bf16":
-                fl = wl["final"][1] / (st_l["final"] * 1e-3) / 1e12
-                entry["final_roofline"] = {"bound": "mfma", "achieved": fl, "peak": PEAK["bf16_mfma_tflops"],
-                                           "unit": "TFLOP/s", "frac": fl / PEAK["bf16_mfma_tflops"]}
-            if fprec == "sparse":
-                # the rows reach the product as CSR (a few hundred bytes each), so the floor is writing D once
-                nbytes = 4.0 * spec.n_query * spec.n_gallery
-                gbs = nbytes / (st_l["final"] * 1e-3) / 1e9
-                tr = measured_traffic(spec.name, name, "sparse_final")
-                entry["final_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                                           "frac": gbs / PEAK["hbm_gbs"], "algorithmic_bytes": nbytes,
-                                           "traffic": tr["bytes"] if tr else None, "traffic_detail": tr}
-            if fused:  # the similarity stage also selects the candidates; the full product is computed
-                entry["similarity_roofline"]["note"] = ("fused similarity + top-k: every tile of the N x N product "
-                                                        "(twice the symmetric product's flops), S never written")
-                kp = binding.make_params(spec.n, spec.n_query, spec.dim, spec.k1, spec.k2, spec.layers, sim_prec=prec)
-                entry["knn_workspace_bytes"] = {"unfused": binding.knn_workspace_bytes(kp),
-                                                "fused": binding.knn_workspace_bytes(kp, fused_knn=True)}
-            lowp[name] = entry
-        if ctx_fused is not None:
-            ctx_fused.close()
+        sel = [v for v in args.variants.split(",") if v]
+        lowp, res_l = run_variants(binding, torch, spec, x, ctx, out, ms, args.steps, args.warmup, sel)
+        results.update(res_l)
 
     quality = None
     if not args.no_quality:
@@ -321,23 +555,37 @@ def main() -> int:
         torch.mul(a, 2.0, out=b)  # reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del a, b
+    ctx.close()
+    del x, out
+    torch.cuda.empty_cache()
+
+    large = None
+    if not args.no_large and spec.name != synth.LARGE.name:
+        large = large_section(binding, torch, synth, args.large_steps, 1, not args.no_cpu_baseline)
+        torch.cuda.empty_cache()
 
     serving = None
     if not args.no_serve:
-        log("serving stream")
-        del out
-        serving = serving_bench(binding, torch, synth, args.serve_requests, 20)
+        serving = serving_bench(binding, torch, synth, args.serve_requests, args.serve_warmup, args.serve_distinct,
+                                0 if args.no_cpu_baseline else args.serve_oracle)
+        torch.cuda.empty_cache()
 
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
-        ref, cpu = cpu_baseline(prob.x32, spec)
-        parity = {"f32_max_abs_err_vs_fp64": float(np.abs(d_f32 - ref.dist).max())}
-        for prec, r in lowp.items():
-            parity[f"{prec}_max_abs_err_vs_fp64"] = float(np.abs(r["dist"] - ref.dist).max())
-    for r in lowp.values():
-        r.pop("dist", None)
+        ref, t = timed_oracle(prob.x32, spec)
+        cpu = cpu_baseline_entry(spec.n ** 2, t, f"the whole {spec.name} request (float64 NumPy/SciPy oracle, "
+                                                  "one pass)")
+        cpu["ms_per_request"] = t * 1e3
+        parity = {name: accuracy(d, ki, ref) for name, (d, ki) in results.items()}
+        for name, tol in (("f32", 1e-4),):
+            parity[name]["meets_tolerance"] = parity[name]["d_max_abs_err_vs_fp64"] <= tol
+        for name in lowp:
+            p = parity[name]
+            tol = 1e-4 if lowp[name]["similarity"] == "f32" and lowp[name]["final"] != "bf16" else 2e-2
+            p["tolerance"] = tol
+            p["meets_tolerance"] = p["d_max_abs_err_vs_fp64"] <= tol and (tol == 1e-4 or p["k1_overlap"] >= 0.995)
 
     phase1 = sum(stages[k] for k in ("prep", "similarity", "topk", "rescore", "adjacency"))
     phase2 = stages["propagate"] + stages["final"]
@@ -365,6 +613,7 @@ def main() -> int:
         "stage_roofline": roof,
         "variants": lowp,
         "parity": parity,
+        "large": large,
         "serving": serving,
         "quality": quality,
     }

@@ -23,16 +23,48 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 def test_stage_work_of_the_mid_workload():
     s = synth.MID  # Q = 3368, G = 15913, N = 19281, d = 2048, k1 = 26, k2 = 7, L = 1
-    n = 19281
+    n, ldn = 19281, 19328
     w = bench.stage_work(s, "f32")
     assert w["similarity"] == ("flop", n * (n + 1) * 2048)  # unique entries of the symmetric S
     assert w["final"] == ("flop", 2 * 3368 * 15913 * n)     # 2.067e12
-    assert w["topk"] == ("byte", 4 * n * n)                 # S read once, 1.487e9
-    assert w["propagate"] == ("byte", 1 * (7 + 2) * 4 * n * n)
-    assert w["rescore"] == ("flop", 2 * n * (26 + 8) * 2048)
-    assert bench.stage_work(s, "bf16")["rescore"][1] == 2 * n * (26 + 16) * 2048
-    assert bench.stage_work(s, "fp8")["rescore"][1] == 2 * n * (26 + 32) * 2048
+    assert w["topk"] == ("byte", 4 * n * n + 8 * n * 34)    # S read once, candidates written
+    # L = 1 with A* rows and the sum aggregator: the first layer is built from the
+    # sparse rows and written once (no dense A*, no dense layer)
+    assert w["propagate"] == ("byte", 4 * n * ldn + 13 * n * 26 + 4 * n)
+    assert w["adjacency"] == ("byte", 14 * n * 26 + 16 * n)
+    assert w["rescore"] == ("byte", n * 2048 * 4 + 8 * n * 34 + 8 * n * 26)
+    assert bench.stage_work(s, "bf16")["topk"][1] == 2 * n * n + 8 * n * 42  # binary16 S
+    assert bench.stage_work(s, "fp8", extra=16)["topk"][1] == 2 * n * n + 8 * n * 42
+    assert bench.stage_work(s, "fp8")["topk"][1] == 2 * n * n + 8 * n * 58
     assert abs(w["final"][1] - 2.067e12) / 2.067e12 < 1e-3
+
+
+def test_stage_work_of_the_large_workload():
+    s = synth.LARGE  # N = 50000, d = 512 (bf16 input), k1 = 20, k2 = 6, L = 2
+    n, ldn = 50000, 50048
+    w = bench.stage_work(s, "f32")
+    # layer 1 from the sparse rows, layer 2 dense: every row read once and written once
+    assert w["propagate"] == ("byte", 4 * n * ldn + 13 * n * 20 + 4 * n + 8 * n * ldn + 8 * n * 6 + 4 * n * 20)
+    assert w["prep"] == ("byte", n * 512 * 2 + n * 512 * 4 + 8 * n)
+
+
+# Stage times (ms) measured on one MI355X (bench.py's HIP events and the
+# rocprofv3 kernel traces committed under profiles/).
+MEASURED = {
+    "mid_n19281_d2048": {"prep": 0.078, "similarity": 6.45, "topk": 0.299, "rescore": 0.402, "adjacency": 0.072,
+                         "propagate": 0.245, "final": 15.2},
+    "large_n50000_d512": {"prep": 0.0514, "similarity": 12.53, "topk": 1.721, "rescore": 0.272, "adjacency": 0.12,
+                          "propagate": 9.85, "final": 284.4},
+}
+
+
+@pytest.mark.parametrize("spec", [synth.MID, synth.LARGE])
+def test_no_roofline_fraction_above_one_at_measured_times(spec):
+    # the work charged to a stage cannot have been done faster than the peak
+    roof = bench.stage_rooflines(spec, MEASURED[spec.name])
+    for stage, e in roof.items():
+        assert e is None or 0 < e["frac"] <= 1.0, (stage, e)
+    assert roof["final"]["bound"] == "mfma" and roof["topk"]["bound"] == "hbm"
 
 
 def test_roofline_entries():
@@ -43,9 +75,17 @@ def test_roofline_entries():
     assert e["frac"] == pytest.approx(e["achieved"] / 157.3)
     assert bench.roofline_entry("similarity", "flop", 1e12, 1.0, "bf16")["peak"] == 2500.0
     assert bench.roofline_entry("similarity", "flop", 1e12, 1.0, "fp8")["peak"] == 5000.0
+    assert bench.roofline_entry("final", "flop", 1e12, 1.0, "bf16", "bf16")["peak"] == 2500.0
+    assert bench.roofline_entry("final", "flop", 1e12, 1.0, "bf16", "bf16x3")["peak"] == pytest.approx(2500.0 / 3)
     h = bench.roofline_entry("topk", "byte", 1.487e9, 0.3, "f32")
     assert h["bound"] == "hbm" and h["unit"] == "GB/s" and h["frac"] == pytest.approx(1.487e9 / 0.3e-3 / 1e9 / 8000)
     assert bench.roofline_entry("final", "flop", 1.0, 0.0, "f32") is None
+
+
+def test_cpu_baseline_entry_states_the_host():
+    e = bench.cpu_baseline_entry(1e8, 2.0, "sample")
+    assert e["value"] == pytest.approx(5e7) and e["kind"] == "oracle" and e["cores"] >= 1
+    assert isinstance(e["cpu_model"], str) and e["cpu_model"]
 
 
 def test_committed_traffic_matches_the_current_kernel_sources():
