@@ -178,6 +178,24 @@ rerank_status rerank_destroy(rerank_ctx* ctx);
 rerank_status rerank_run(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype,
                          float* d_dist, int32_t* d_knn_idx, float* d_knn_val, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation, kernels and results as rerank_run, with the problem's working
+ * set in a static device array of RERANK_STATIC_BYTES that every GPU holds
+ * from the library's first use on it until the process ends. The call makes
+ * no device or host allocation and no stage timing. Arguments as for
+ * rerank_run; ctx supplies the device and its DENSE_LAYERS / FUSED_KNN flags.
+ * RERANK_E_NOMEM (nothing enqueued) when rerank_workspace_bytes(p) exceeds
+ * RERANK_STATIC_BYTES (for example N = 5000, d = 512, FP32, one layer fits).
+ * All calls on one GPU share its array and find the previous call's contents
+ * there: calls whose work overlaps on the device (unordered streams, several
+ * host threads) race and give undefined results; order them, e.g. on one
+ * stream. The array is separate from the context's own working set, so
+ * rerank_run and rerank_run_static do not interfere. */
+#define RERANK_STATIC_BYTES ((size_t)256 << 20)
+rerank_status rerank_run_static(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype,
+                                float* d_dist, int32_t* d_knn_idx, float* d_knn_val, void* hip_stream);
+
 /* Phase 1 only (Eq. 7-8, the k-NN graph): the N x k1 neighbour lists and
  * their similarities, same argument meaning as rerank_run. */
 rerank_status rerank_knn(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype,

@@ -25,7 +25,7 @@ FINAL = {"f32": 0, "bf16x3": 1, "sparse": 2, "bf16": 3}
 EXPORTS = (
     "rerank_default_params", "rerank_validate", "rerank_workspace_bytes", "rerank_knn_workspace_bytes",
     "rerank_create", "rerank_destroy",
-    "rerank_run", "rerank_knn", "rerank_similarity", "rerank_submit", "rerank_poll", "rerank_wait",
+    "rerank_run", "rerank_run_static", "rerank_knn", "rerank_similarity", "rerank_submit", "rerank_poll", "rerank_wait",
     "rerank_cancel", "rerank_status_str", "rerank_last_error", "rerank_stage_times", "rerank_stage_name",
     "rerank_rank", "rerank_evaluate",
 )
@@ -72,6 +72,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
             "rerank_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, sz, ctypes.c_uint32]),
             "rerank_destroy": (ctypes.c_int, [vp]),
             "rerank_run": (ctypes.c_int, [vp, P, vp, i32, vp, vp, vp, vp]),
+            "rerank_run_static": (ctypes.c_int, [vp, P, vp, i32, vp, vp, vp, vp]),
             "rerank_knn": (ctypes.c_int, [vp, P, vp, i32, vp, vp, vp]),
             "rerank_similarity": (ctypes.c_int, [vp, P, vp, i32, vp, ctypes.c_int64, vp]),
             "rerank_submit": (ctypes.c_int, [vp, P, vp, i32, vp, vp, ctypes.POINTER(u64)]),
@@ -200,6 +201,30 @@ def run(x, n_query: int, k1: int, k2: int, layers: int = 2, alpha: int = 2, sim_
                                 ki.data_ptr() if ki is not None else None, kv.data_ptr() if kv is not None else None,
                                 _stream_ptr(torch, x.device)))
     return (dist, ki, kv) if return_knn else dist
+
+
+STATIC_BYTES = 256 << 20  # RERANK_STATIC_BYTES
+
+
+def run_static(x, n_query: int, k1: int, k2: int, layers: int = 2, alpha: int = 2, sim_prec: str = "f32",
+               extra_cand: int = -1, node: str = "adj", final_prec: str = "f32", ctx: Optional[Context] = None,
+               out=None, knn_out=None, aggregator: str = "sum"):
+    """rerank_run_static: the full method with the working set in the
+    library's static device array (no device allocation by the library).
+    ``out`` (Q x G float32) and ``knn_out`` (a pair of N x k1 int32 / float32
+    tensors, optional) are caller-owned; returns ``out``."""
+    import torch
+    dt = _x_args(x)
+    n, d = x.shape
+    p = make_params(n, n_query, d, k1, k2, layers, alpha, sim_prec, extra_cand, node, final_prec, aggregator)
+    ctx = ctx or default_context(x.device.index or 0)
+    if out is None:
+        raise ValueError("run_static needs a caller-owned `out` tensor")
+    ki, kv = knn_out if knn_out is not None else (None, None)
+    _check(library().rerank_run_static(ctx.handle, ctypes.byref(p), x.data_ptr(), dt, out.data_ptr(),
+                                       ki.data_ptr() if ki is not None else None,
+                                       kv.data_ptr() if kv is not None else None, _stream_ptr(torch, x.device)))
+    return out
 
 
 def knn(x, k1: int, sim_prec: str = "f32", extra_cand: int = -1, ctx: Optional[Context] = None):

@@ -24,6 +24,19 @@ inline bool try_reserve(std::atomic<size_t>& reserved, size_t budget, size_t byt
 }
 }  // namespace rr
 
+struct rerank_ctx;
+
+namespace rr {
+// Shared by rerank_run and rerank_run_static (rerank_api.cpp).
+rerank_status prepare_run(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype, float* d_dist,
+                          int32_t* d_knn_idx, float* d_knn_val, Plan* P);
+hipError_t enqueue_run(const Plan& P, void* ws, const void* d_x, int32_t in_dtype, float* d_dist, int32_t* d_knn_idx,
+                       float* d_knn_val, hipStream_t s, const char** where, StageClock* clk);
+// Device address of the static working set of rerank_run_static on `device`
+// (the current device), looked up once per device (static_ws.cpp).
+hipError_t static_scratch_setup(int device);
+}  // namespace rr
+
 struct rerank_ctx {
   int device = 0;
   size_t budget = 0;

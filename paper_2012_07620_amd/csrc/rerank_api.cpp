@@ -106,6 +106,48 @@ static rerank_status with_ws(rerank_ctx* ctx, const Plan& P, void* hip_stream, F
   return RERANK_OK;
 }
 
+// Argument checks and plan of rerank_run (shared with rerank_run_static).
+rerank_status prepare_run(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype, float* d_dist,
+                          int32_t* d_knn_idx, float* d_knn_val, Plan* P) {
+  rerank_status st = check_common(ctx, p, d_x, in_dtype);
+  if (st != RERANK_OK) return st;
+  if (!d_dist || !aligned(d_dist, 4)) {
+    set_error("d_dist is NULL or misaligned");
+    return RERANK_E_INVALID;
+  }
+  if ((d_knn_idx && !aligned(d_knn_idx, 4)) || (d_knn_val && !aligned(d_knn_val, 4))) {
+    set_error("knn output misaligned");
+    return RERANK_E_INVALID;
+  }
+  make_plan(p, false, P, (ctx->flags & RERANK_CTX_DENSE_LAYERS) != 0, (ctx->flags & RERANK_CTX_FUSED_KNN) != 0);
+  if (P->fused && P->kc > KNN_LIST_MAX) {
+    set_error("RERANK_CTX_FUSED_KNN: k1 + extra_cand above 64 is outside the fused path's limits");
+    return RERANK_E_UNSUPPORTED;
+  }
+  return RERANK_OK;
+}
+
+// The kernels of rerank_run on working set `ws` (P.total bytes), then the
+// optional copies of the neighbour lists.
+hipError_t enqueue_run(const Plan& P, void* ws, const void* d_x, int32_t in_dtype, float* d_dist, int32_t* d_knn_idx,
+                       float* d_knn_val, hipStream_t s, const char** where, StageClock* clk) {
+  hipError_t e = enqueue_rerank(P, ws, d_x, in_dtype == RERANK_IN_BF16, d_dist, s, where, clk);
+  if (e != hipSuccess) return e;
+  const int64_t cnt = (int64_t)P.n * P.k1;
+  if (d_knn_idx) {
+    e = launch_copy_i32((const int32_t*)((char*)ws + P.o_ki), d_knn_idx, cnt, s);
+    if (e != hipSuccess) {
+      *where = "launch_copy_i32";
+      return e;
+    }
+  }
+  if (d_knn_val) {
+    e = launch_copy_f32((const float*)((char*)ws + P.o_kv), d_knn_val, cnt, s);
+    if (e != hipSuccess) *where = "launch_copy_f32";
+  }
+  return e;
+}
+
 }  // namespace rr
 
 using namespace rr;
@@ -207,6 +249,11 @@ rerank_status rerank_create(rerank_ctx** out, int hip_device, size_t hbm_budget_
     set_error("host allocation failed");
     return RERANK_E_NOMEM;
   }
+  e = static_scratch_setup(hip_device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipGetSymbolAddress(static working set)");
+  }
   c->device = hip_device;
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
   c->flags = flags;
@@ -257,29 +304,11 @@ rerank_status rerank_destroy(rerank_ctx* ctx) {
 
 rerank_status rerank_run(rerank_ctx* ctx, const rerank_params* p, const void* d_x, int32_t in_dtype, float* d_dist,
                          int32_t* d_knn_idx, float* d_knn_val, void* hip_stream) {
-  rerank_status st = check_common(ctx, p, d_x, in_dtype);
-  if (st != RERANK_OK) return st;
-  if (!d_dist || !aligned(d_dist, 4)) {
-    set_error("d_dist is NULL or misaligned");
-    return RERANK_E_INVALID;
-  }
-  if ((d_knn_idx && !aligned(d_knn_idx, 4)) || (d_knn_val && !aligned(d_knn_val, 4))) {
-    set_error("knn output misaligned");
-    return RERANK_E_INVALID;
-  }
   Plan P;
-  make_plan(p, false, &P, (ctx->flags & RERANK_CTX_DENSE_LAYERS) != 0, (ctx->flags & RERANK_CTX_FUSED_KNN) != 0);
-  if ((st = check_fused(P)) != RERANK_OK) return st;
+  rerank_status st = prepare_run(ctx, p, d_x, in_dtype, d_dist, d_knn_idx, d_knn_val, &P);
+  if (st != RERANK_OK) return st;
   return with_ws(ctx, P, hip_stream, [&](hipStream_t s, const char** where) -> hipError_t {
-    hipError_t e = enqueue_rerank(P, ctx->ws, d_x, in_dtype == RERANK_IN_BF16, d_dist, s, where, ctx->clock);
-    if (e != hipSuccess) return e;
-    const int64_t cnt = (int64_t)P.n * P.k1;
-    if (d_knn_idx) {
-      e = launch_copy_i32((const int32_t*)((char*)ctx->ws + P.o_ki), d_knn_idx, cnt, s);
-      if (e != hipSuccess) return e;
-    }
-    if (d_knn_val) e = launch_copy_f32((const float*)((char*)ctx->ws + P.o_kv), d_knn_val, cnt, s);
-    return e;
+    return enqueue_run(P, ctx->ws, d_x, in_dtype, d_dist, d_knn_idx, d_knn_val, s, where, ctx->clock);
   });
 }
 

@@ -85,6 +85,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.rerank_workspace_bytes(ctypes.byref(p), None) == binding.E_INVALID
     assert lib.rerank_validate(None) == binding.E_INVALID
     assert lib.rerank_run(None, ctypes.byref(p), None, 0, None, None, None, None) == binding.E_INVALID
+    assert lib.rerank_run_static(None, ctypes.byref(p), None, 0, None, None, None, None) == binding.E_INVALID
     assert lib.rerank_create(None, 0, 0, 0) == binding.E_INVALID
     for s in range(8):
         assert lib.rerank_status_str(s)
@@ -179,3 +180,9 @@ def test_knn_workspace_checks():
     assert lib.rerank_knn_workspace_bytes(ctypes.byref(q), 4, None) == binding.E_INVALID
     bad = binding.make_params(1000, 1, 64, 10, 20, 0)  # k2 > k1
     assert lib.rerank_knn_workspace_bytes(ctypes.byref(bad), 0, ctypes.byref(out)) == binding.E_INVALID
+
+
+def test_static_array_size_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define RERANK_STATIC_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == binding.STATIC_BYTES
