@@ -82,6 +82,7 @@ def stage_work(spec, prec: str = "f32", extra=None, final: str = "f32", aggregat
         "final": ("flop", 2 * q * g * n),
     }
     planes = {"bf16x3": 2, "bf16": 1}.get(final, 0)  # bf16 copies of the last layer
+    last_write = planes * 2 * n * ldH if planes else 4 * n * ldH  # the last layer's rows (or planes) written once
     sparse_first = node != "raw" and L >= 1 and aggregator != "max"
     prop = 0
     if node == "raw":
@@ -91,16 +92,16 @@ def stage_work(spec, prec: str = "f32", extra=None, final: str = "f32", aggregat
         # mutual flags (lists read, one byte per edge written) and the in-edge CSR
         # (lists and flags read, in-edges written); A-row features need neither
         w["adjacency"] = ("byte", (14 * n * k1 + 16 * n) if node == "adj" else 8 * n)
-        # layer 1 written once per row from the sparse rows (lists, weights, flags, CSR read)
-        prop += 4 * n * ldN + 13 * n * k1 + 4 * n
-        dense = L - 1
+        # layers before the last are CSR rows (their few entries per row not
+        # counted), the last one is written once as dense rows from the sparse
+        # rows before it (lists, weights, flags read)
+        prop += L * 13 * n * k1 + 4 * n + last_write
+        dense = 0
     else:  # dense A* rows: zero fill plus the scatter of the lists
         w["adjacency"] = ("byte", 4 * n * ldN + 12 * n * k1 + 8 * n)
         dense = L
     if dense > 0:  # each dense layer reads every row once and writes every row once
-        prop += dense * (8 * n * ldH + 8 * n * k2) + 4 * n * k1
-    if L >= 1:
-        prop += planes * 2 * n * ldH
+        prop += dense * (4 * n * ldH + 8 * n * k2) + (dense - 1) * 4 * n * ldH + last_write + 4 * n * k1
     w["propagate"] = ("byte", prop)
     return w
 

@@ -133,9 +133,12 @@ rerank_status rerank_workspace_bytes(const rerank_params* p, size_t* bytes);
  * the direct calls (on the call's stream) so rerank_stage_times can report
  * per-stage device time; it adds no synchronisation. */
 #define RERANK_CTX_STAGE_TIMING 1u
-/* DENSE_LAYERS: with RERANK_FINAL_SPARSE, write the propagation layers as dense
- * rows and compact the last one before the product (the default keeps them as
- * CSR rows, see rerank_final_prec). The distances are the same either way. */
+/* DENSE_LAYERS: write every propagation layer as dense N x N rows. By default
+ * (sum or mean aggregator, A* or A features, layers >= 1) the layers are kept
+ * as CSR rows wherever that is possible: all of them for RERANK_FINAL_SPARSE
+ * (see rerank_final_prec), and all but the last for the other final products,
+ * whose last layer is then written densely from the CSR rows before it. The
+ * distances are the same either way, bit for bit. */
 #define RERANK_CTX_DENSE_LAYERS 2u
 /* FUSED_KNN (the similarity product fused with the candidate selection of
  * Eq. 8): rerank_knn and rerank_run select each row's k1 + extra_cand

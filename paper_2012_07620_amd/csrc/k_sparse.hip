@@ -110,18 +110,46 @@ __global__ __launch_bounds__(256) void propagate_gated_kernel(const float* __res
                                                               const int32_t* __restrict__ knn,
                                                               const float* __restrict__ kv, int k1, int k2, int alpha,
                                                               int agg, float* __restrict__ hout,
-                                                              float* __restrict__ sout, SlGate* gates, int l) {
+                                                              float* __restrict__ sout, SlGate* gates, int l,
+                                                              uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
   if (!gates[l - 1].dense) return;
   __shared__ PropShared sh;
-  propagate_row(hin, sin, ld, ld, knn, kv, k1, k2, alpha, agg, hout, sout, nullptr, nullptr, blockIdx.x, sh);
+  propagate_row(hin, sin, ld, ld, knn, kv, k1, k2, alpha, agg, hout, sout, hi, lo, blockIdx.x, sh);
 }
 
 hipError_t launch_propagate_gated(const float* hin, const float* sin, int n, int64_t ld, const int32_t* knn_idx,
                                   const float* knn_val, int k1, int k2, int alpha, int agg, float* hout, float* sout,
-                                  SlGate* gates, int l, hipStream_t s) {
+                                  SlGate* gates, int l, hipStream_t s, uint16_t* hi, uint16_t* lo) {
   if (l < 1 || k2 < 1 || k2 > 256 || (ld & 3)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(propagate_gated_kernel, dim3(n), dim3(256), 0, s, hin, sin, ld, knn_idx, knn_val, k1, k2, alpha,
-                     agg, hout, sout, gates, l);
+                     agg, hout, sout, gates, l, hi, lo);
+  return hipGetLastError();
+}
+
+// Last layer of a dense final product from the CSR rows of the layer before:
+// the row builder's dense writer (zeros written outside the row's support),
+// so the layer costs one write of the dense rows instead of k2 dense reads
+// per row.
+__global__ __launch_bounds__(256) void sparse_prop_dense_kernel(SlRows in, const float* __restrict__ sin,
+                                                                const int32_t* __restrict__ knn,
+                                                                const float* __restrict__ kv, int k1, int k2,
+                                                                int alpha, int agg, int64_t ld,
+                                                                float* __restrict__ hout, float* __restrict__ sout,
+                                                                uint16_t* __restrict__ hi, uint16_t* __restrict__ lo,
+                                                                const SlGate* gate_in) {
+  if (gate_in->dense) return;
+  __shared__ FirstShared sh;
+  const CsrSrc src{in};
+  sparse_row_core(src, sin, knn, kv, k1, k2, alpha, agg, ld, hout, hi, lo, sout, nullptr, blockIdx.x, sh);
+}
+
+hipError_t launch_sparse_prop_dense(SlRows in, const float* sin, const int32_t* knn_idx, const float* knn_val, int n,
+                                    int k1, int k2, int alpha, int agg, int64_t ld, float* hout, float* sout,
+                                    uint16_t* hi, uint16_t* lo, const SlGate* gate_in, hipStream_t s) {
+  if (k2 < 1 || k2 > 256 || (ld & 3) || agg == RERANK_AGG_MAX || !gate_in || !in.col || !in.so || !in.cnt)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sparse_prop_dense_kernel, dim3(n), dim3(256), 0, s, in, sin, knn_idx, knn_val, k1, k2, alpha,
+                     agg, ld, hout, sout, hi, lo, gate_in);
   return hipGetLastError();
 }
 

@@ -202,7 +202,14 @@ hipError_t launch_sparse_prop(SlRows in, const float* sin, const int32_t* knn_id
 // The dense layer, run only when gates[l - 1] is dense.
 hipError_t launch_propagate_gated(const float* hin, const float* sin, int n, int64_t ld, const int32_t* knn_idx,
                                   const float* knn_val, int k1, int k2, int alpha, int agg, float* hout, float* sout,
-                                  SlGate* gates, int l, hipStream_t s);
+                                  SlGate* gates, int l, hipStream_t s, uint16_t* hi = nullptr, uint16_t* lo = nullptr);
+// Layer l + 1 written as dense rows (hout, or the bf16 hi / lo planes of a
+// last layer) from the CSR rows `in` of layer l, unless gates[l] says layer l
+// was dense (then launch_propagate_gated for layer l + 1 computes it). The
+// same sums and norms as the dense layer, bit for bit.
+hipError_t launch_sparse_prop_dense(SlRows in, const float* sin, const int32_t* knn_idx, const float* knn_val, int n,
+                                    int k1, int k2, int alpha, int agg, int64_t ld, float* hout, float* sout,
+                                    uint16_t* hi, uint16_t* lo, const SlGate* gate_in, hipStream_t s);
 // Ranking list: per row of D (q rows, stride g), the r smallest positions in
 // ascending order, ties to the lower position (r <= 256).
 hipError_t launch_rank(const float* D, int q, int g, int r, int32_t* out, hipStream_t s);

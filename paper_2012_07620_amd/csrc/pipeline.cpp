@@ -177,7 +177,7 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
       RR_STAGE(RERANK_STAGE_ADJACENCY, 1);
       RR_STAGE(RERANK_STAGE_PROPAGATE, 0);
       const bool last = (P.layers == 1);
-      if (P.sparse_layers) {
+      if (P.sparse_layers || P.sparse_mid) {  // layer 1 as CSR rows
         SlGate* gates = at<SlGate>(ws, P.o_slg);
         RR_TRY(launch_fill_zero((float*)gates, (int64_t)(P.layers + 1) * (sizeof(SlGate) / 4), s));
         const SlOut o = sl_out(P, ws, B, 1);
@@ -210,7 +210,7 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
     RR_STAGE(RERANK_STAGE_PROPAGATE, 0);
   }
   const int32_t* order = nullptr;  // dense layers walk rows in cluster order
-  if (first < P.layers && !P.sparse_layers) {
+  if (first < P.layers && !P.sparse_layers && !P.sparse_mid) {
     int32_t* oscr = at<int32_t>(ws, P.o_ord);
     int32_t* ord = oscr + cluster_order_ints(P.n, P.n);
     RR_TRY(launch_cluster_order(ki, P.n, P.k1, P.n, oscr, ord, s));
@@ -220,7 +220,17 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
     float* out = (cur == A) ? B : A;
     float* osig = (csig == sa) ? sb : sa;
     const bool last = (l == P.layers - 1);
-    if (P.sparse_layers) {  // layer l + 1 from the CSR rows of layer l (or dense once a layer turned dense)
+    if (P.sparse_mid && last) {
+      // the last layer of a dense final product: dense rows from the CSR rows of
+      // layer l, or the dense layer when layer l had to be written densely
+      SlGate* gates = at<SlGate>(ws, P.o_slg);
+      const SlOut prev = sl_out(P, ws, (float*)cur, l);
+      RR_TRY(launch_sparse_prop_dense(prev.rows, csig, ki, kv, P.n, P.k1, P.k2, P.alpha, P.agg, P.ldH, out, osig, hi,
+                                      lo, prev.gate, s));
+      RR_TRY(launch_propagate_gated(cur, csig, P.n, P.ldH, ki, kv, P.k1, P.k2, P.alpha, P.agg, out, osig, gates, l + 1,
+                                    s, hi, lo));
+    } else if (P.sparse_layers || P.sparse_mid) {
+      // layer l + 1 from the CSR rows of layer l (or dense once a layer turned dense)
       SlGate* gates = at<SlGate>(ws, P.o_slg);
       const SlOut prev = sl_out(P, ws, (float*)cur, l);
       const SlOut next = sl_out(P, ws, out, l + 1);

@@ -104,7 +104,8 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o, bool dense_layers
     }
     if (P.fprec == FinalPrec::SPARSE) P.o_sp = take(sparse_final_ints(P.n, P.ldN) * 4);
     P.sparse_layers = P.fprec == FinalPrec::SPARSE && P.sparse_first && !dense_layers;
-    if (P.sparse_layers) {
+    P.sparse_mid = P.fprec != FinalPrec::SPARSE && P.sparse_first && P.layers >= 2 && !dense_layers;
+    if (P.sparse_layers || P.sparse_mid) {
       P.o_slg = take((size_t)(P.layers + 1) * sizeof(SlGate));
       P.o_slr = take(2 * (2 * n + 4) * 4);  // row starts (n + 1) and counts (n) of two layers
     }

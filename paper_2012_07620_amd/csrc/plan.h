@@ -39,6 +39,7 @@ struct Plan {
          o_rsc = 0;  // re-score scratch (the dead S buffer, or its own block without one)
   bool sparse_first = false;   // layer 1 built from the sparse A* / A rows (layers >= 1, sum or mean)
   bool sparse_layers = false;  // layers kept as CSR rows for the sparse final product
+  bool sparse_mid = false;     // dense final products, layers >= 2: layers 1..L-1 as CSR rows, the last dense
   bool fused = false;          // similarity and top-k fused: S is never written
   bool has_s = true;           // the N x N buffer A exists (knn-only fused plans have none)
   size_t total = 0;

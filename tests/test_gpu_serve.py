@@ -64,9 +64,12 @@ def _serve(ctx, probs, prec="f32", **kw):
 def test_results_same_alone_and_in_the_mix(gpu_lib, prec):
     from paper_2012_07620_amd import binding
     # sizes below and above the batching limit (8192); at 7800..8192 the final
-    # product has more 128 x 128 tiles than the device holds at once
+    # product has more 128 x 128 tiles than the device holds at once; the
+    # largest requests of the benchmarked stream (N up to 30000, d = 2048,
+    # bf16 features) run next to them
     probs = (_requests(11, 14, 300, 3000) + _requests(12, 3, 9000, 12000, dims=(512,))
-             + _requests(13, 2, 7800, 8192, dims=(128,)))
+             + _requests(13, 2, 7800, 8192, dims=(128,))
+             + _requests(14, 2, 26000, 30000, dims=(2048,), dtype="bf16"))
     rng = np.random.default_rng(3)
     probs = [probs[i] for i in rng.permutation(len(probs))]
     print(f"case mix prec={prec} n={[p.spec.n for p in probs]}", flush=True)

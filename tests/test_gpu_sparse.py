@@ -144,3 +144,40 @@ def test_sparse_layers_match_dense_layers_bit_for_bit(gpu_lib, n, q, d, k1, k2, 
     r = check_run(x, ref, ki, d_csr.cpu().numpy(), q, k2, layers, D_TOL_F32, node=node, aggregator=agg)
     print(f"sparse layers: D vs FP64 max {r['max_err']:.2e} mean {r['mean_err']:.2e}, "
           f"tied rows {r['tied_rows_k1']}, pairs vs tie-breaks {r['pairs_vs_tie_breaks']}")
+
+
+MID_CASES = [
+    # n, q, d, k1, k2, layers, node, agg, n_ids, final
+    (1000, 100, 128, 10, 3, 2, "adj", "sum", 50, "f32"),
+    (1000, 100, 128, 10, 3, 3, "adj", "sum", 50, "bf16x3"),
+    (2049, 333, 64, 20, 6, 2, "adj", "sum", 60, "bf16"),
+    (300, 60, 48, 12, 5, 2, "adj", "mean", 9, "f32"),
+    (300, 60, 48, 12, 5, 2, "adj_raw", "sum", 9, "f32"),
+    (300, 60, 48, 12, 5, 4, "adj", "sum", 9, "f32"),  # slot bounds outgrow the buffer: later layers turn dense
+    (8000, 700, 64, 120, 8, 2, "adj", "sum", 0, "bf16x3"),  # layer 2 turns dense
+    (12000, 500, 64, 40, 8, 3, "adj", "sum", 0, "f32"),
+]
+
+
+@pytest.mark.parametrize("n,q,d,k1,k2,layers,node,agg,n_ids,final", MID_CASES)
+def test_csr_middle_layers_match_dense_layers_bit_for_bit(gpu_lib, n, q, d, k1, k2, layers, node, agg, n_ids, final):
+    # dense final products with two or more layers keep the layers before the
+    # last as CSR rows and build the last one densely from them: the same sums
+    # in the same order as dense layers, so identical distances
+    import torch
+    from paper_2012_07620_amd import binding
+    x = synth.random_features(n, d, seed=7 * n + d + layers, n_ids=n_ids)
+    print(f"case csr middle layers n={n} q={q} k1={k1} k2={k2} L={layers} node={node} agg={agg} final={final}",
+          flush=True)
+    kw = dict(node=node, aggregator=agg, final_prec=final)
+    ctx_d = binding.Context(0, dense_layers=True)
+    d_dense = binding.run(_dev(x), q, k1, k2, layers, ctx=ctx_d, **kw)
+    d_mid, ki, _ = binding.run(_dev(x), q, k1, k2, layers, return_knn=True, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(d_dense, d_mid)
+    ctx_d.close()
+    if final == "f32":
+        ref = orc.rerank(x, q, k1, k2, layers, node=node, aggregator=agg)
+        r = check_run(x, ref, ki.cpu().numpy(), d_mid.cpu().numpy(), q, k2, layers, D_TOL_F32, node=node,
+                      aggregator=agg)
+        print(f"csr middle layers: D vs FP64 max {r['max_err']:.2e}")
