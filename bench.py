@@ -138,7 +138,7 @@ KERNEL_SOURCES = {
     "final": ("common.h", "gemm_body.h", "k_gemm.hip"),
     "topk": ("common.h", "rows_body.h", "k_topk.hip"),
     "rescore": ("common.h", "rows_body.h", "k_graph.hip"),
-    "propagate": ("common.h", "rows_body.h", "k_graph.hip"),
+    "propagate": ("common.h", "kernels.h", "rows_body.h", "k_graph.hip", "k_sparse.hip"),
     "adjacency": ("common.h", "rows_body.h", "k_graph.hip"),
     "prep": ("common.h", "rows_body.h", "k_prep.hip"),
     "sparse_final": ("common.h", "kernels.h", "gemm_body.h", "rows_body.h", "k_sparse.hip"),
