@@ -444,9 +444,9 @@ def run_variants(binding, torch, spec, x, ctx, out, ms_ref, steps, warmup, selec
             tr = measured_traffic(spec.name, name, "sparse_final")
             e.update({"traffic": tr["bytes"] if tr else None, "traffic_detail": tr})
             entry["final_roofline"] = e
-        if fused:  # the similarity stage also selects the candidates; the full product is computed
-            entry["similarity_roofline"]["note"] = ("fused similarity + top-k: every tile of the N x N product "
-                                                    "(twice the symmetric product's flops), S never written")
+        if fused:  # the similarity stage also selects the candidates
+            entry["similarity_roofline"]["note"] = ("fused similarity + top-k: a stored column sample, then each "
+                                                    "upper-triangle tile once; S never written")
             kp = binding.make_params(spec.n, spec.n_query, spec.dim, spec.k1, spec.k2, spec.layers, sim_prec=prec)
             entry["knn_workspace_bytes"] = {"unfused": binding.knn_workspace_bytes(kp),
                                             "fused": binding.knn_workspace_bytes(kp, fused_knn=True)}

@@ -142,20 +142,25 @@ rerank_status rerank_workspace_bytes(const rerank_params* p, size_t* bytes);
 #define RERANK_CTX_DENSE_LAYERS 2u
 /* FUSED_KNN (the similarity product fused with the candidate selection of
  * Eq. 8): rerank_knn and rerank_run select each row's k1 + extra_cand
- * candidates in the product's epilogue, so the N x N similarity S is never
- * written; rerank_knn then needs no N x N buffer at all (its working set is
- * the feature copies and O(N * (k1 + extra_cand)) lists). Every tile of the
- * full N x N product is computed (no symmetric halving), so the product does
- * twice the flops. The selected lists follow the same order and tie rule;
- * with re-scoring they match the unfused path's. Requires
- * k1 + extra_cand <= 64 (else RERANK_E_UNSUPPORTED). The serving calls
- * (rerank_submit) ignore it. */
+ * candidates from the product's tiles, so the N x N similarity S is never
+ * written; rerank_knn then needs no N x N buffer at all. A sample of whole
+ * column panels is multiplied first to give each row a lower bound on its
+ * (k1 + extra_cand)-th best similarity; then every upper-triangle tile of
+ * the rest is computed once and its values at or above a row's bound are kept
+ * for that row (S is symmetric: each tile serves its rows and its columns).
+ * The selected lists follow the same order and tie rule as the unfused
+ * path's and are the same lists on the same bits. Working set: the feature
+ * copies, the stored sample and the candidate slots, which together grow as
+ * N^1.5 (about 0.3 GB at N = 19281, k1 = 26, FP32, against 1.5 GB for S).
+ * Requires k1 + extra_cand <= 64 (else RERANK_E_UNSUPPORTED). The serving
+ * calls (rerank_submit) ignore it. */
 #define RERANK_CTX_FUSED_KNN 4u
 
 /* Bytes of library-owned device memory rerank_knn needs for *p in a context
  * created with `flags` (the Eq. 7-8 k-NN graph alone). Without
- * RERANK_CTX_FUSED_KNN this includes the N x N similarity buffer; with it the
- * total is linear in N (feature copies, candidate and per-range lists).
+ * RERANK_CTX_FUSED_KNN this includes the N x N similarity buffer; with it
+ * there is none (feature copies, the stored column sample and the candidate
+ * slots).
  * Pure host function. RERANK_E_INVALID for invalid parameters, unknown flags or
  * a NULL `bytes`; RERANK_E_UNSUPPORTED when the fused path cannot take
  * k1 + extra_cand. */

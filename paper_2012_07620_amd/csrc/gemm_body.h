@@ -83,6 +83,15 @@ __device__ __forceinline__ void mfma_stage(f32x16 (&acc)[2][2], const u32x4 (&a)
   }
 }
 
+// Stored similarity of an accumulator value with its row and column inverse
+// norms: FP32, or binary16 rounded to nearest even in the low-precision
+// paths; -0 becomes +0. Every kernel that writes or keys on S uses this one
+// expression, so all of them see the same bits.
+template <typename OT>
+__device__ __forceinline__ OT sim_value(float acc, float sa, float sb) {
+  return (OT)(acc * sa * sb + 0.0f);
+}
+
 struct GemmArgs {
   const uint8_t* A;
   const uint8_t* B;
@@ -128,7 +137,7 @@ __device__ __forceinline__ void sim_epilogue(const GemmArgs& g, int tm, int tn, 
       for (int r = 0; r < 16; r++) {
         const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
         const int row = m0 + lr;
-        T[lr * TS + lc] = (OT)((row < g.M && col < g.Nn) ? acc[sm][sn][r] * g.sa[row] * scol + 0.0f : 0.f);
+        T[lr * TS + lc] = (row < g.M && col < g.Nn) ? sim_value<OT>(acc[sm][sn][r], g.sa[row], scol) : (OT)0.f;
       }
     }
   __syncthreads();
@@ -298,7 +307,7 @@ __device__ __forceinline__ void knn_epilogue(const GemmArgs& g, int tm, int tn, 
       for (int r = 0; r < 16; r++) {
         const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
         const int row = m0 + lr;
-        T[lr * TS + lc] = (OT)((row < g.M && col < g.Nn) ? acc[sm][sn][r] * g.sa[row] * scol + 0.0f : 0.f);
+        T[lr * TS + lc] = (row < g.M && col < g.Nn) ? sim_value<OT>(acc[sm][sn][r], g.sa[row], scol) : (OT)0.f;
       }
     }
   __syncthreads();
@@ -341,9 +350,12 @@ __host__ __device__ constexpr int gemm_stage_lds(int ks) { return 2 * BM * (ks *
 // KS slices; the similarity's mirror staging fits in the same LDS); the K
 // range [st0, st1), counted in slices, must then be whole stages. EPI_SIM_SYM / EPI_SIM_SYM16 (A == B, tm <= tn): also stores the
 // mirrored tile C^T, so only the upper triangle of tiles is computed.
-template <int MODE, int EPI, int NBUF = 1, int KS = 1>
-__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uint8_t* lds, int st0 = 0,
-                                          int st1 = -1) {
+// gemm_tile_acc: the products of tile (tm, tn) over K slices [st0, st1) into
+// `acc` (FP32, the 32x32 MFMA layout), no epilogue; LDS is free again when it
+// returns. gemm_tile: the same followed by the EPI epilogue.
+template <int MODE, int NBUF = 1, int KS = 1>
+__device__ __forceinline__ void gemm_tile_acc(const GemmArgs& g, int tm, int tn, uint8_t* lds, f32x16 (&acc)[2][2],
+                                              int st0 = 0, int st1 = -1) {
   static_assert(KS == 1 || (NBUF == 1 && gemm_stage_lds(KS) <= GEMM_LDS_BYTES), "wide stages: one buffer");
   constexpr int SB = KS * BKB;      // bytes per row per LDS stage
   constexpr int LR = SB + 16;       // padded LDS row
@@ -382,7 +394,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
     }
   };
 
-  f32x16 acc[2][2];
 #pragma unroll
   for (int sm = 0; sm < 2; sm++)
 #pragma unroll
@@ -439,7 +450,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
     }
     __syncthreads();
   }
+}
 
+template <int MODE, int EPI, int NBUF = 1, int KS = 1>
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uint8_t* lds, int st0 = 0,
+                                          int st1 = -1) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = tm * BM, n0 = tn * BN;
+  f32x16 acc[2][2];
+  gemm_tile_acc<MODE, NBUF, KS>(g, tm, tn, lds, acc, st0, st1);
   // 32x32 accumulator layout: register r of lane l holds
   // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of its block.
   if constexpr (EPI == EPI_PART) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 namespace rr {
 
 enum class SimPrec : int { F32 = 0, BF16 = 1, FP8 = 2 };
@@ -74,15 +76,72 @@ hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes
 // a2 + a3 fused (S never written): the K best candidates of each of the M
 // rows of A (the Eq. 7 similarity of A with itself, scaled by sa and rounded
 // as launch_gemm_sim rounds it for prec), written as launch_topk writes them
-// (idx / val, M x K, the row itself first). K <= 64 and K <= M. part:
-// kKnnMaxRanges * M * K uint64 of scratch (per-range lists).
-constexpr int kKnnMaxRanges = 8;
+// (idx / val, M x K, the row itself first). K <= 64 and K <= M. ws: the
+// scratch described by fused_layout(M, K, prec).
+//
+// Method: a sample of the columns (P whole column panels of 128, evenly
+// spread) is multiplied first and stored; from it each row gets tau_i, a
+// similarity value at or below its K-th best. The upper-triangle tiles of the
+// other panels are then computed once each and every element of a tile is
+// offered to both of its rows (i, j) and (j, i), the stored sample tiles
+// likewise; an element is appended to its row's candidate buffer only if its
+// value is at least that row's tau. A superset of each row's K best is kept,
+// so the K best of the buffer are exact. A row whose buffer overflows (more
+// than C values at or above its tau) is recomputed, with its whole row panel,
+// by the row-panel kernel that merges running lists.
+//
+// Sizes: for a uniformly drawn sample of m of the M columns, the number of
+// keys at or above the K-th best of the sample has mean about K M / m and
+// relative standard deviation about 1 / sqrt(K); C allows f = 1 + 6 / sqrt(K)
+// times the mean, plus 128. m balances the stored sample (M m sbytes) against
+// the candidate slots (8 M C): m = sqrt(8 f K M / sbytes), rounded up to
+// whole panels, at least 8 panels (all of them for M <= 1024). The scratch
+// grows as M^1.5: for M = 19281 and K = 34 (FP32) it is about 0.4 GB against
+// 1.5 GB for S.
+constexpr int kKnnMaxRanges = 32;  // column ranges of the row-panel kernel
 constexpr int KNN_LIST_MAX = 64;
+struct FusedLayout {
+  int T;          // row / column panels of 128
+  int P, sp, so;  // sample panels: so + t * sp for t < P
+  int64_t m;      // stored sample columns per row (P * 128)
+  int64_t C;      // candidate slots per row
+  size_t o_samp, o_cand, o_tau, o_cnt, o_flag, bytes;
+};
+// sbytes: bytes per stored similarity (4 for FP32, 2 for binary16).
+inline FusedLayout fused_layout(int64_t n, int K, int sbytes) {
+  FusedLayout L{};
+  L.T = (int)((n + 127) / 128);
+  const double f = 1.0 + 6.0 / std::sqrt((double)K);
+  const double mopt = std::sqrt(8.0 * f * K * (double)n / sbytes);
+  int64_t P = (int64_t)std::ceil(mopt / 128.0);
+  if (P < 8) P = 8;
+  if (P > L.T) P = L.T;
+  L.P = (int)P;
+  L.sp = L.T / L.P;
+  L.so = L.sp / 2;
+  L.m = (int64_t)L.P * 128;
+  const int64_t mv = L.m < n ? L.m : n;
+  const int64_t c = (int64_t)std::ceil(f * K * (double)n / (double)mv) + 128;
+  L.C = c < n ? c : n;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t at = off;
+    off += (b + 255) & ~(size_t)255;
+    return at;
+  };
+  L.o_samp = take((size_t)n * L.m * sbytes);
+  L.o_cand = take((size_t)n * L.C * 8);
+  L.o_tau = take((size_t)n * 4);
+  L.o_cnt = take((size_t)n * 4);
+  L.o_flag = take((size_t)L.T * 4);
+  L.bytes = off;
+  return L;
+}
+inline FusedLayout fused_layout(int64_t n, int K, SimPrec prec) {
+  return fused_layout(n, K, prec == SimPrec::F32 ? 4 : 2);
+}
 hipError_t launch_knn_fused(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes, const float* sa,
-                            int K, uint64_t* part, int32_t* idx, float* val, hipStream_t s);
-// Column ranges per row panel of the fused launch for a tiles_m x tiles_n tile
-// grid on `slots` resident workgroups (host function).
-int knn_fused_ranges(int tiles_m, int tiles_n, int slots);
+                            int K, void* ws, int32_t* idx, float* val, hipStream_t s);
 // Final epilogue: out[q][g] = 1 - sa[q] * sb[g] * acc, ldo floats.
 // Final product, D = 1 - sa[i] * sb[j] * acc. ws (ws_bytes, may be null):
 // scratch for splitting the last, partly filled round of tiles along K.

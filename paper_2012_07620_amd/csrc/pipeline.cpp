@@ -97,7 +97,7 @@ hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipS
     const void* a = P.prec == SimPrec::F32 ? (const void*)xp : xl;
     const int64_t row_bytes = P.prec == SimPrec::F32 ? P.ldp * 4 : P.ldl * P.lbytes;
     RR_TRY(launch_knn_fused(P.prec, a, P.n, row_bytes, row_bytes, P.prec == SimPrec::F32 ? rn : sl, P.kc,
-                            at<uint64_t>(ws, P.o_fk), ci, cv, s));
+                            at<void>(ws, P.o_fk), ci, cv, s));
     RR_STAGE(RERANK_STAGE_SIMILARITY, 1);
   } else {
     // the feature buffer B (not yet in use) holds the partial tiles of a K-split

@@ -82,7 +82,7 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o, bool dense_layers
   } else {
     P.o_rsc = take((size_t)(cluster_order_ints(P.n, P.n) + P.n) * 4);
   }
-  if (fused) P.o_fk = take((size_t)kKnnMaxRanges * n * P.kc * 8);
+  if (fused) P.o_fk = take(fused_layout(P.n, P.kc, P.prec).bytes);
   P.o_ci = take(n * P.kc * 4);
   P.o_cv = take(n * P.kc * 4);
   P.o_ki = take(n * P.k1 * 4);

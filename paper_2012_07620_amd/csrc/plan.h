@@ -35,7 +35,7 @@ struct Plan {
          o_sa = 0, o_sb = 0, o_cnt = 0, o_hi = 0, o_lo = 0, o_mflag = 0, o_off = 0, o_inl = 0, o_sp = 0,
          o_slg = 0, o_slr = 0, o_part = 0,
          o_ord = 0,
-         o_fk = 0,   // per-range candidate lists of the fused similarity + top-k
+         o_fk = 0,   // scratch of the fused similarity + top-k (fused_layout)
          o_rsc = 0;  // re-score scratch (the dead S buffer, or its own block without one)
   bool sparse_first = false;   // layer 1 built from the sparse A* / A rows (layers >= 1, sum or mean)
   bool sparse_layers = false;  // layers kept as CSR rows for the sparse final product

@@ -150,21 +150,53 @@ def test_evaluate_rejects_bad_arguments_before_any_device_call():
     assert lib.rerank_evaluate(p, p, 2, 3, 3, p, p, bad_k, 2, p, p, p, None) == binding.E_INVALID
 
 
-def test_knn_workspace_has_no_n_squared_term_with_the_fused_path():
+def _fused_scratch(n, K, sbytes):
+    """The fused path's scratch as the library sizes it: a stored sample of
+    P panels of 128 columns per row and C candidate slots per row, with
+    f = 1 + 6 / sqrt(K) slots per expected key and P balancing the two."""
+    import math
+    T = (n + 127) // 128
+    f = 1.0 + 6.0 / math.sqrt(K)
+    P = min(T, max(8, math.ceil(math.sqrt(8.0 * f * K * n / sbytes) / 128.0)))
+    m = P * 128
+    C = min(n, math.ceil(f * K * n / min(m, n)) + 128)
+    up = lambda b: (b + 255) // 256 * 256
+    return up(n * m * sbytes) + up(n * C * 8) + up(n * 4) + up(n * 4) + up(T * 4)
+
+
+def test_knn_workspace_of_the_fused_path_has_no_n_by_n_buffer():
     n, d = 19281, 2048
     ldn = (n + 63) // 64 * 64
     p = binding.make_params(n, 1, d, 26, 1, 0)
     plain = binding.knn_workspace_bytes(p)
     fused = binding.knn_workspace_bytes(p, fused_knn=True)
     assert plain >= n * ldn * 4  # the N x N similarity buffer
-    assert fused < plain - n * ldn * 4 + 8 * n * (26 + 8) * 8 + (1 << 20)
-    # linear in N: twice the rows, about twice the bytes
+    # the S buffer is replaced by the sample and candidate scratch (26 + 8 candidates, FP32 sample)
+    assert abs(fused - (plain - n * ldn * 4 + _fused_scratch(n, 34, 4))) < (1 << 20)
+    assert fused < plain / 3
+    # the scratch grows as N^1.5: twice the rows, about 2.8 times the scratch
+    s1, s2 = _fused_scratch(n, 34, 4), _fused_scratch(2 * n, 34, 4)
+    assert 2.5 < s2 / s1 < 3.1
     f2 = binding.knn_workspace_bytes(binding.make_params(2 * n, 1, d, 26, 1, 0), fused_knn=True)
-    assert 1.9 * fused < f2 < 2.1 * fused
-    # N = 300000, d = 512, BF16: S alone would be 360 GB; the fused k-NN graph needs a few GB
+    assert abs((f2 - fused) - (s2 - s1) - (plain - n * ldn * 4)) < (4 << 20)
+    # N = 300000, d = 512, BF16: S alone would be 180 GB; the fused k-NN graph needs about 12 GB
     big = binding.make_params(300000, 1, 512, 20, 1, 0, sim_prec="bf16")
     assert binding.knn_workspace_bytes(big) > 300000 * 300032 * 2
-    assert binding.knn_workspace_bytes(big, fused_knn=True) < 4 << 30
+    assert binding.knn_workspace_bytes(big, fused_knn=True) < 14e9
+
+
+def test_kernel_names_do_not_depend_on_unnamed_types():
+    """A kernel whose signature mentions a type built from an unnamed enum or
+    lambda is mangled with a per-pass number ($_N) that the host and device
+    compilations can assign differently; the host then registers a name the
+    device code object lacks and the launch aborts. No such name may exist."""
+    lib = binding.library()
+    path = lib._name
+    blob = open(path, "rb").read()
+    names = set(re.findall(rb"_ZN2rr[A-Za-z0-9_$]+", blob))
+    assert names, "no kernel names found in the library"
+    bad = sorted(n.decode() for n in names if b"$_" in n)
+    assert not bad, bad[:5]
 
 
 def test_knn_workspace_checks():

@@ -148,3 +148,50 @@ def test_fused_run_matches_unfused_above_the_batching_limit(gpu_lib, fused_ctx, 
     print(f"{sim}/{final}: rows with identical lists {same_rows:.6f}")
     assert torch.equal(ka, kb) and torch.equal(va, vb)
     assert torch.equal(a, b)
+
+
+def _sample_panels(n, K, sbytes):
+    """Column panels (of 128) the fused path multiplies first, as the library
+    lays them out: P panels spaced T // P apart from (T // P) // 2, with P the
+    memory-balancing sample size (at least 8 panels, at most all of them)."""
+    import math
+    T = (n + 127) // 128
+    f = 1.0 + 6.0 / math.sqrt(K)
+    P = min(T, max(8, math.ceil(math.sqrt(8.0 * f * K * n / sbytes) / 128.0)))
+    sp = T // P
+    return [sp // 2 + t * sp for t in range(P)]
+
+
+@pytest.mark.parametrize("sim", ["f32", "bf16"])
+def test_fused_overflowing_rows_are_recomputed_by_their_row_panel(gpu_lib, fused_ctx, sim):
+    """Rows of the sample panels form one cluster, every other row a second,
+    orthogonal one: an outside row's bound comes from similarities near 0, so
+    nearly all of its own cluster passes it and its candidate buffer
+    overflows; those panels are recomputed by the row-panel kernel, the
+    sample rows take the normal path. Both must give the exact lists."""
+    n, d, k1 = 4096, 64, 20
+    K = k1 + (8 if sim == "f32" else 16)
+    panels = _sample_panels(n, K, 4 if sim == "f32" else 2)
+    assert len(panels) < (n + 127) // 128  # some panels lie outside the sample
+    rng = np.random.Generator(np.random.PCG64(2024))
+    in_sample = np.zeros(n, bool)
+    for p in panels:
+        in_sample[p * 128:(p + 1) * 128] = True
+    a = np.zeros(d, np.float32)
+    a[0] = 1.0
+    b = np.zeros(d, np.float32)
+    b[1] = 1.0
+    x = np.where(in_sample[:, None], a, b) + rng.standard_normal((n, d)).astype(np.float32) * 0.3
+    x = np.ascontiguousarray(x.astype(np.float32))
+    print(f"case {sim} n={n} K={K} sample panels {panels}", flush=True)
+    ki, kv = _knn(x, k1, fused_ctx, sim_prec=sim)
+    ui, uv = _knn(x, k1, None, sim_prec=sim)
+    assert np.all(ki[:, 0] == np.arange(n))
+    same = np.mean(np.all(ki == ui, axis=1))
+    print(f"{sim}: rows identical to the unfused path: {same:.5f}")
+    if sim == "f32":
+        assert np.array_equal(ki, ui) and np.array_equal(kv, uv)
+        g = orc.knn_lists(x, k1, 3)
+        compare_lists(ki, g, 3, x=x)
+    else:
+        assert same >= 0.999
