@@ -189,7 +189,7 @@ __host__ __device__ inline float rescore_skip2(int lbytes, int64_t K) {
   return -1.f;
 }
 
-// a3b: FP32 compensated re-score of Kc candidates per row, then the k1 cut.
+// a3b: re-score of Kc candidates per row (FP32 products summed in FP64), then the k1 cut.
 // cval: the candidates' product values (sorted descending, as top-k writes
 // them); skip2 = rescore_skip2(...) skips candidates that cannot reach the
 // top k1 (-1: re-score all). scratch (cluster_order_ints(n, n) + n int32,

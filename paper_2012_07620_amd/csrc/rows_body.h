@@ -214,21 +214,40 @@ __device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, i
 }
 
 // ============================================================== a3b: re-score
-// Candidates of row i re-scored as cos(x_i, x_j) with a compensated FP32 dot
-// product (error about one rounding of the result, far below the spacing of
-// distinct similarities the tie rule has to resolve), then sorted under
-// (similarity desc, column asc) with the row itself first; the first k1 are
-// N(i, k1) of Eq. 8. One wavefront per row; 16 lanes per candidate, four
-// candidates at a time.
-template <int R>
-__device__ __forceinline__ void rescore_row(const float* __restrict__ xp, int64_t ldp, const float* __restrict__ rn,
-                                            int i, const int32_t* __restrict__ cand, const float* __restrict__ cval,
-                                            int Kc, int k1, float skip2, int32_t* __restrict__ kidx,
-                                            float* __restrict__ kval) {
+// Candidates of row i re-scored as cos(x_i, x_j): the FP32 products are exact
+// in FP64 and summed there (the sum's error, a few units of 2^-53 of
+// sum |x_ik x_jk|, is far below one FP32 rounding), scaled by the inverse
+// norms in FP64 and rounded to FP32 once; then sorted under (similarity
+// desc, column asc) with the row itself first; the first k1 are N(i, k1) of
+// Eq. 8. FP64 FMAs run at the rate of unpacked FP32 ones on gfx950, so this is
+// cheaper than a compensated FP32 sum.
+//
+// One wavefront per row. The row is taken in blocks of 256 U features (U
+// 16-byte loads per lane, x_i's block held in registers; U from the row
+// length: 8 for rows over 1024 features, down to 1 up to 256); each
+// candidate's block is read by the whole wavefront, max(1, 8 / U) candidates
+// per step, the next step's loads in flight while a step is multiplied, and
+// the partial dot products are summed across the wavefront in a fixed order
+// (the result does not depend on the launch).
+__host__ __device__ constexpr int rescore_u(int64_t ldp) {
+  return ldp > 1024 ? 8 : ldp > 512 ? 4 : ldp > 256 ? 2 : 1;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+
+template <int R, int U>
+__device__ __forceinline__ void rescore_row_u(const float* __restrict__ xp, int64_t ldp,
+                                              const float* __restrict__ rn, int i, const int32_t* __restrict__ cand,
+                                              const float* __restrict__ cval, int Kc, int k1, float skip2,
+                                              int32_t* __restrict__ kidx, float* __restrict__ kval) {
+  constexpr int C = U >= 8 ? 1 : 8 / U;  // candidates per step (two steps' loads in flight)
   const int lane = threadIdx.x & 63;
-  const int sub = lane >> 4, sl = lane & 15;
   const float* xi = xp + (int64_t)i * ldp;
-  const float rni = rn[i];
+  const int32_t* ci = cand + (int64_t)i * Kc;
   // Candidates arrive sorted by their product values g. With skip2 = 2 delta
   // >= 0 (delta bounds |g - exact|), a candidate past position k1 can enter
   // the exact top-k1 only if g >= g[k1 - 1] - skip2: those form a prefix,
@@ -243,41 +262,62 @@ __device__ __forceinline__ void rescore_row(const float* __restrict__ xp, int64_
     for (int m = 32; m >= 1; m >>= 1) last = max(last, __shfl_xor(last, m, kWave));
     cnt = last + 1;
   }
-  uint64_t keys[R];
+  double dotv[R];  // lane l, slot r: the dot product of candidate 64 r + l
 #pragma unroll
-  for (int r = 0; r < R; r++) keys[r] = 0;
-  for (int c0 = 0; c0 < cnt; c0 += 4) {
-    const int c = c0 + sub;
-    const int j = (c < cnt) ? cand[(int64_t)i * Kc + c] : i;
-    DF acc{0.f, 0.f};
-    if (j != i) {
-      const float* xj = xp + (int64_t)j * ldp;
-      for (int k = sl * 4; k < ldp; k += 64) {
-        const f32x4 a = *(const f32x4*)(xi + k);
-        const f32x4 b = *(const f32x4*)(xj + k);
-        dot2_acc(acc, a.x, b.x);
-        dot2_acc(acc, a.y, b.y);
-        dot2_acc(acc, a.z, b.z);
-        dot2_acc(acc, a.w, b.w);
+  for (int r = 0; r < R; r++) dotv[r] = 0.0;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  for (int64_t k0 = 0; k0 < ldp; k0 += 256 * U) {
+    f32x4 a[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t k = k0 + u * 256 + lane * 4;
+      a[u] = k < ldp ? *(const f32x4*)(xi + k) : zero;
+    }
+    // candidates c .. c + C - 1 of block k0 into b (zeros past cnt and for the row itself)
+    auto fetch = [&](f32x4 (&b)[C][U], int c) {
+#pragma unroll
+      for (int q = 0; q < C; q++) {
+        const int j = c + q < cnt ? ci[c + q] : i;
+        const float* xj = xp + (int64_t)j * ldp;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const int64_t k = k0 + u * 256 + lane * 4;
+          b[q][u] = (k < ldp && j != i) ? *(const f32x4*)(xj + k) : zero;
+        }
       }
-    }
+    };
+    f32x4 nb[C][U];  // the next step's blocks, loaded while this step's are multiplied
+    fetch(nb, 0);
+    for (int c = 0; c < cnt; c += C) {
+      f32x4 b[C][U];
 #pragma unroll
-    for (int m = 8; m > 0; m >>= 1) {
-      DF o{__shfl_xor(acc.hi, m, kWave), __shfl_xor(acc.lo, m, kWave)};
-      acc = df_add(acc, o);
-    }
-    const float dot = acc.hi + acc.lo;
-    const uint64_t key = (j == i) ? self_key((uint32_t)i) : sel_key((dot * rni) * rn[j], (uint32_t)j);
-    // candidate c0 + s is held by lane (c0 + s) % 64 of slot (c0 + s) / 64
+      for (int q = 0; q < C; q++)
 #pragma unroll
-    for (int s = 0; s < 4; s++) {
-      const uint64_t ks = shfl_u64(key, s * 16);
-      const int cs = c0 + s;
-      if (cs < cnt) {
+        for (int u = 0; u < U; u++) b[q][u] = nb[q][u];
+      if (c + C < cnt) fetch(nb, c + C);
+#pragma unroll
+      for (int q = 0; q < C; q++) {
+        double sq = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+          for (int e = 0; e < 4; e++) sq = __builtin_fma((double)a[u][e], (double)b[q][u][e], sq);
+        sq = wave_sum_f64(sq);
 #pragma unroll
         for (int r = 0; r < R; r++)
-          if ((cs >> 6) == r && lane == (cs & 63)) keys[r] = ks;
+          if (((c + q) >> 6) == r && lane == ((c + q) & 63)) dotv[r] += sq;
       }
+    }
+  }
+  const double rni = rn[i];
+  uint64_t keys[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int c = r * 64 + lane;
+    keys[r] = 0ull;
+    if (c < cnt) {
+      const int j = ci[c];
+      keys[r] = j == i ? self_key((uint32_t)i) : sel_key((float)(dotv[r] * rni * (double)rn[j]), (uint32_t)j);
     }
   }
   wave_sort_desc<R>(keys);
@@ -289,6 +329,27 @@ __device__ __forceinline__ void rescore_row(const float* __restrict__ xp, int64_
       kidx[(int64_t)i * k1 + e] = (int32_t)j;
       kval[(int64_t)i * k1 + e] = (j == (uint32_t)i) ? 1.0f : key_val(keys[r]);
     }
+  }
+}
+
+// The re-score of row i with the block size its row length calls for.
+template <int R>
+__device__ __forceinline__ void rescore_row(const float* __restrict__ xp, int64_t ldp, const float* __restrict__ rn,
+                                            int i, const int32_t* __restrict__ cand, const float* __restrict__ cval,
+                                            int Kc, int k1, float skip2, int32_t* __restrict__ kidx,
+                                            float* __restrict__ kval) {
+  switch (rescore_u(ldp)) {
+    case 8:
+      rescore_row_u<R, 8>(xp, ldp, rn, i, cand, cval, Kc, k1, skip2, kidx, kval);
+      break;
+    case 4:
+      rescore_row_u<R, 4>(xp, ldp, rn, i, cand, cval, Kc, k1, skip2, kidx, kval);
+      break;
+    case 2:
+      rescore_row_u<R, 2>(xp, ldp, rn, i, cand, cval, Kc, k1, skip2, kidx, kval);
+      break;
+    default:
+      rescore_row_u<R, 1>(xp, ldp, rn, i, cand, cval, Kc, k1, skip2, kidx, kval);
   }
 }
 
