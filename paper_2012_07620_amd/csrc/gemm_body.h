@@ -102,6 +102,11 @@ struct GemmArgs {
   const float* sb;
   float* out;
   int64_t ldo;  // floats
+  // similarity epilogues: when set, bm[b * ldbm + i] = the largest stored
+  // similarity of row i over column block b (columns 128 b .. 128 b + 127);
+  // block-major, so a tile's rows write one contiguous run
+  float* bm = nullptr;
+  int64_t ldbm = 0;
 };
 
 // Similarity epilogue of tile (tm, tn) from its accumulators (EPI_SIM_SYM or
@@ -154,23 +159,67 @@ __device__ __forceinline__ void sim_epilogue(const GemmArgs& g, int tm, int tn, 
         if (col0 + e < lim) out[row * g.ldo + col0 + e] = v[e];
     }
   };
-  // the tile: lanes along a row
-  for (int lr = tid / CPR; lr < BM; lr += RPP) {
+  // the tile: lanes along a row (CPR consecutive lanes of one wavefront per
+  // row; a group of CPR lanes takes rows grp, grp + RPP, ..., NP of them)
+  constexpr int NP = BM / RPP;
+  static_assert(NP == CPR / 2, "each lane pair of a group ends with one row's maximum");
+  const int grp = tid / CPR, ch = tid % CPR;
+  float rm[NP];  // this lane's maximum over its V columns of each of its rows
+#pragma unroll
+  for (int k = 0; k < NP; k++) {
+    const int lr = grp + k * RPP;
     const int row = m0 + lr;
-    if (row >= g.M) continue;
-    const int ch = tid % CPR;
-    put(row, n0 + ch * V, g.Nn, *(const ov*)(T + lr * TS + ch * V));
+    const ov v = *(const ov*)(T + lr * TS + ch * V);
+    if (row < g.M) put(row, n0 + ch * V, g.Nn, v);
+    rm[k] = -__builtin_inff();
+#pragma unroll
+    for (int e = 0; e < V; e++)
+      if (n0 + ch * V + e < g.Nn) rm[k] = fmaxf(rm[k], (float)v[e]);
+  }
+  if (g.bm) {
+    // each row's maximum over this column block, by a reduce-scatter over the
+    // group's lanes: at step m the lane with bit m set keeps the upper half of
+    // the rows it still holds and takes its partner's values for them; the
+    // pair (2j, 2j + 1) ends holding one row, whose index is read off the bits
+    int k = 0;
+#pragma unroll
+    for (int m = CPR / 2; m >= 2; m >>= 1) {
+      const int h = NP * m / CPR;  // rows still held per lane after this step
+      const bool up = (ch & m) != 0;
+#pragma unroll
+      for (int j = 0; j < NP / 2; j++) {
+        if (j < h) {
+          const float send = up ? rm[j] : rm[j + h];
+          const float keep = up ? rm[j + h] : rm[j];
+          rm[j] = fmaxf(keep, __shfl_xor(send, m, kWave));
+        }
+      }
+      if (up) k += h;
+    }
+    rm[0] = fmaxf(rm[0], __shfl_xor(rm[0], 1, kWave));
+    const int row = m0 + grp + k * RPP;
+    if ((ch & 1) == 0 && row < g.M) g.bm[(int64_t)tn * g.ldbm + row] = rm[0];
   }
   if (tm != tn) {  // the transpose: lane = tile column, one V-run of tile rows each
     const int lc = tid & 127;
     const int row = n0 + lc;
-    if (row < g.Nn)
-      for (int ch = tid >> 7; ch < BM / V; ch += 2) {
-        ov v;
+    float cmx = -__builtin_inff();
+    for (int ch = tid >> 7; ch < BM / V; ch += 2) {
+      ov v;
 #pragma unroll
-        for (int e = 0; e < V; e++) v[e] = T[(ch * V + e) * TS + lc];
-        put(row, m0 + ch * V, g.M, v);
-      }
+      for (int e = 0; e < V; e++) v[e] = T[(ch * V + e) * TS + lc];
+      if (row < g.Nn) put(row, m0 + ch * V, g.M, v);
+#pragma unroll
+      for (int e = 0; e < V; e++)
+        if (m0 + ch * V + e < g.M) cmx = fmaxf(cmx, (float)v[e]);
+    }
+    if (g.bm) {  // row n0 + lc's maximum over column block tm: two halves, joined in LDS after the tile
+      float* cm = (float*)(lds + ((BM * TS * (int)sizeof(OT) + 15) & ~15));
+      static_assert(((BM * TS * (int)sizeof(OT) + 15) & ~15) + 256 * 4 <= sim_lds_bytes(EPI), "room for the join");
+      cm[tid] = cmx;
+      __syncthreads();
+      if (tid < BN && row < g.Nn) g.bm[(int64_t)tm * g.ldbm + row] = fmaxf(cm[tid], cm[tid + BN]);
+    }
   }
 }
 

@@ -77,14 +77,15 @@ static int tail_parts(int64_t tiles, int slots, int nst, int64_t tile_bytes, int
 
 template <int MODE, int EPI>
 static hipError_t launch_gemm_t(const void* a, int M, int64_t lda, const void* b, int Nn, int64_t ldb, int64_t kbytes,
-                                const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s) {
+                                const float* sa, const float* sb, float* out, int64_t ldo, hipStream_t s,
+                                float* bm = nullptr, int64_t ldbm = 0) {
   const int tm = (M + BM - 1) / BM, tn = (Nn + BN - 1) / BN;
   const int64_t nwg = (EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16) ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tm * tn;
   constexpr int KS = (EPI == EPI_DIST && MODE == MODE_F32) ? DIST_KS
                      : (EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16) ? SIM_KS
                                                                    : 1;
   if (nwg <= 0 || nwg > 0x7FFFFFFF || kbytes % (BKB * KS) || kbytes <= 0) return hipErrorInvalidValue;
-  GemmArgs g{(const uint8_t*)a, (const uint8_t*)b, M, Nn, lda, ldb, (int)(kbytes / BKB), sa, sb, out, ldo};
+  GemmArgs g{(const uint8_t*)a, (const uint8_t*)b, M, Nn, lda, ldb, (int)(kbytes / BKB), sa, sb, out, ldo, bm, ldbm};
   hipLaunchKernelGGL((gemm_nt_kernel<MODE, EPI>), dim3((unsigned)nwg), dim3(256), 0, s, g, tm, tn);
   return hipGetLastError();
 }
@@ -135,7 +136,7 @@ static int sim_slots() {
 
 template <int MODE, int EPI>
 static hipError_t launch_sim_t(const void* a, int M, int64_t lda, int64_t kbytes, const float* sa, float* out,
-                               int64_t ldo, float* ws, int64_t ws_bytes, hipStream_t s) {
+                               int64_t ldo, float* ws, int64_t ws_bytes, hipStream_t s, float* bm, int64_t ldbm) {
   const int T = (M + BM - 1) / BM;
   const int64_t nwg = (int64_t)T * (T + 1) / 2;
   if (nwg <= 0 || nwg > 0x7FFFFFFF || kbytes % (BKB * SIM_KS) || kbytes <= 0) return hipErrorInvalidValue;
@@ -146,9 +147,9 @@ static hipError_t launch_sim_t(const void* a, int M, int64_t lda, int64_t kbytes
   const int parts =
       ws ? tail_parts(nwg, sim_slots<MODE, EPI>(), nst / SIM_KS, (int64_t)BM * BN * 4, ws_bytes, 2, &rem) : 1;
   if (parts == 1)
-    return launch_gemm_t<MODE, EPI>(a, M, lda, a, M, lda, kbytes, sa, sa, out, ldo, s);
+    return launch_gemm_t<MODE, EPI>(a, M, lda, a, M, lda, kbytes, sa, sa, out, ldo, s, bm, ldbm);
   const int64_t first = nwg - rem;
-  GemmArgs g{(const uint8_t*)a, (const uint8_t*)a, M, M, lda, lda, nst, sa, sa, out, ldo};
+  GemmArgs g{(const uint8_t*)a, (const uint8_t*)a, M, M, lda, lda, nst, sa, sa, out, ldo, bm, ldbm};
   hipLaunchKernelGGL((gemm_nt_kernel<MODE, EPI>), dim3((unsigned)first), dim3(256), 0, s, g, T, T);
   hipLaunchKernelGGL((sim_part_kernel<MODE>), dim3((unsigned)(rem * parts)), dim3(256), 0, s, g, T, (int)first, parts,
                      ws);
@@ -158,18 +159,21 @@ static hipError_t launch_sim_t(const void* a, int M, int64_t lda, int64_t kbytes
 }
 
 hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes, const float* sa,
-                           void* out, int64_t ldo, bool half_out, float* ws, int64_t ws_bytes, hipStream_t s) {
+                           void* out, int64_t ldo, bool half_out, float* ws, int64_t ws_bytes, hipStream_t s,
+                           float* bm, int64_t ldbm) {
   float* o = (float*)out;
   if (half_out && prec == SimPrec::F32) return hipErrorInvalidValue;  // the FP32 path keeps S exact
   switch (prec) {
     case SimPrec::F32:
-      return launch_sim_t<MODE_F32, EPI_SIM_SYM>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s);
+      return launch_sim_t<MODE_F32, EPI_SIM_SYM>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s, bm, ldbm);
     case SimPrec::BF16:
-      return half_out ? launch_sim_t<MODE_BF16, EPI_SIM_SYM16>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s)
-                      : launch_sim_t<MODE_BF16, EPI_SIM_SYM>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s);
+      return half_out
+                 ? launch_sim_t<MODE_BF16, EPI_SIM_SYM16>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s, bm, ldbm)
+                 : launch_sim_t<MODE_BF16, EPI_SIM_SYM>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s, bm, ldbm);
     case SimPrec::FP8:
-      return half_out ? launch_sim_t<MODE_FP8, EPI_SIM_SYM16>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s)
-                      : launch_sim_t<MODE_FP8, EPI_SIM_SYM>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s);
+      return half_out
+                 ? launch_sim_t<MODE_FP8, EPI_SIM_SYM16>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s, bm, ldbm)
+                 : launch_sim_t<MODE_FP8, EPI_SIM_SYM>(a, M, lda_bytes, kbytes, sa, o, ldo, ws, ws_bytes, s, bm, ldbm);
   }
   return hipErrorInvalidValue;
 }

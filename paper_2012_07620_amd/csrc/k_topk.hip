@@ -36,6 +36,42 @@ hipError_t launch_topk(const void* S, bool half, int64_t ldS, int N, int rows, i
   return hipGetLastError();
 }
 
+template <int R, typename T>
+__global__ __launch_bounds__(256) void topk_pruned_kernel(const T* __restrict__ S, int64_t ldS, int N, int rows, int K,
+                                                          const float* __restrict__ bm, int64_t ldbm,
+                                                          int32_t* __restrict__ oidx, float* __restrict__ oval,
+                                                          int ldo) {
+  __shared__ uint64_t ring_all[4][128];
+  __shared__ int list_all[4][512];
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 4 + w;
+  if (i >= rows) return;  // waves are independent
+  topk_pruned_row<R, T>(S, ldS, N, i, K, bm, ldbm, oidx, oval, ldo, ring_all[w], list_all[w]);
+}
+
+template <typename T>
+static void launch_topk_pruned_t(const T* S, int64_t ldS, int N, int rows, int K, const float* bm, int64_t ldbm,
+                                 int32_t* idx, float* val, int ldo, hipStream_t s) {
+  dim3 grid((rows + 3) / 4), block(256);
+  if (K <= 64)
+    hipLaunchKernelGGL((topk_pruned_kernel<1, T>), grid, block, 0, s, S, ldS, N, rows, K, bm, ldbm, idx, val, ldo);
+  else if (K <= 128)
+    hipLaunchKernelGGL((topk_pruned_kernel<2, T>), grid, block, 0, s, S, ldS, N, rows, K, bm, ldbm, idx, val, ldo);
+  else
+    hipLaunchKernelGGL((topk_pruned_kernel<4, T>), grid, block, 0, s, S, ldS, N, rows, K, bm, ldbm, idx, val, ldo);
+}
+
+hipError_t launch_topk_pruned(const void* S, bool half, int64_t ldS, int N, int rows, int K, const float* bm,
+                              int64_t ldbm, int32_t* idx, float* val, int ldo, hipStream_t s) {
+  if (K < 1 || K > 256 || K > N || N > kPrunedMaxN || (ldS & 3) || !bm || ldbm < rows)
+    return hipErrorInvalidValue;
+  if (half)
+    launch_topk_pruned_t((const _Float16*)S, ldS, N, rows, K, bm, ldbm, idx, val, ldo, s);
+  else
+    launch_topk_pruned_t((const float*)S, ldS, N, rows, K, bm, ldbm, idx, val, ldo, s);
+  return hipGetLastError();
+}
+
 // Ranking list (Algorithm 1): per row of D, the r smallest in ascending order.
 template <int R>
 __global__ __launch_bounds__(256) void rank_kernel(const float* __restrict__ D, int q, int g, int r,

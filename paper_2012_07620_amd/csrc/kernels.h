@@ -69,9 +69,11 @@ hipError_t launch_prep(const void* x, int in_bf16, int n, int d, float* xp, int6
 // error of the BF16 / FP8 product itself) to halve S's bytes. ws (ws_bytes,
 // may be null): scratch for splitting the last, partly filled round of tiles
 // along K (fixed ranges summed in order: deterministic).
+// bm (may be null): also the largest stored similarity of each row over each
+// block of 128 columns, bm[b * ldbm + i] (ldbm >= M).
 hipError_t launch_gemm_sim(SimPrec prec, const void* a, int M, int64_t lda_bytes, int64_t kbytes,
                            const float* sa, void* out, int64_t ldo, bool half_out, float* ws, int64_t ws_bytes,
-                           hipStream_t s);
+                           hipStream_t s, float* bm = nullptr, int64_t ldbm = 0);
 
 // a2 + a3 fused (S never written): the K best candidates of each of the M
 // rows of A (the Eq. 7 similarity of A with itself, scaled by sa and rounded
@@ -162,6 +164,13 @@ hipError_t launch_gemm_dist_bf16x3(const uint16_t* a_hi, const uint16_t* a_lo, i
 // column asc), the row's own column first.
 hipError_t launch_topk(const void* S, bool half, int64_t ldS, int N, int rows, int K, int32_t* idx, float* val,
                        int ldo, hipStream_t s);
+// The same lists from S and its block maxima bm (as launch_gemm_sim writes
+// them): only the column blocks whose maximum reaches a lower bound on the
+// row's K-th best value are read. N <= kPrunedMaxN (at most 512 blocks per
+// row).
+constexpr int kPrunedMaxN = 512 * 128;
+hipError_t launch_topk_pruned(const void* S, bool half, int64_t ldS, int N, int rows, int K, const float* bm,
+                              int64_t ldbm, int32_t* idx, float* val, int ldo, hipStream_t s);
 
 // Cluster order of rows [0, rows) of `lists` (row width w, entries < n):
 // the rows sorted by the key min(i, entries of row i), rows of one key in

@@ -104,14 +104,21 @@ hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipS
     // last round; none for problems the serving path batches (as for the final)
     float* sws = (P.o_b && P.n > kGroupedMaxN) ? at<float>(ws, P.o_b) : nullptr;
     const int64_t sws_bytes = sws ? (int64_t)P.n * P.ldH * 4 : 0;
+    // the product also records each row's largest similarity per block of
+    // 128 columns, so the selection reads only the blocks that can hold a member
+    float* bm = P.o_bm ? at<float>(ws, P.o_bm) : nullptr;
     if (P.prec == SimPrec::F32)
-      RR_TRY(launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, S, P.ldN, false, sws, sws_bytes, s));
+      RR_TRY(launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, S, P.ldN, false, sws, sws_bytes, s, bm,
+                             P.n));
     else
       RR_TRY(launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, S, P.ldN, true, sws, sws_bytes,
-                             s));
+                             s, bm, P.n));
     RR_STAGE(RERANK_STAGE_SIMILARITY, 1);
     RR_STAGE(RERANK_STAGE_TOPK, 0);
-    RR_TRY(launch_topk(S, P.prec != SimPrec::F32, P.ldN, P.n, P.n, P.kc, ci, cv, P.kc, s));
+    if (bm)
+      RR_TRY(launch_topk_pruned(S, P.prec != SimPrec::F32, P.ldN, P.n, P.n, P.kc, bm, P.n, ci, cv, P.kc, s));
+    else
+      RR_TRY(launch_topk(S, P.prec != SimPrec::F32, P.ldN, P.n, P.n, P.kc, ci, cv, P.kc, s));
     RR_STAGE(RERANK_STAGE_TOPK, 1);
   }
   RR_STAGE(RERANK_STAGE_RESCORE, 0);

@@ -30,12 +30,14 @@ struct Plan {
   int lbytes = 0;   // bytes per low-precision element
   int64_t ldN = 0;  // similarity / A* row stride
   int64_t ldH = 0;  // propagated feature row stride (ldN, or ldp in raw mode)
+  int64_t tb = 0;   // column blocks of 128 per S row (the block maxima's row stride)
   // byte offsets into the working set
   size_t o_xp = 0, o_xl = 0, o_rn = 0, o_sl = 0, o_a = 0, o_b = 0, o_ci = 0, o_cv = 0, o_ki = 0, o_kv = 0,
          o_sa = 0, o_sb = 0, o_cnt = 0, o_hi = 0, o_lo = 0, o_mflag = 0, o_off = 0, o_inl = 0, o_sp = 0,
          o_slg = 0, o_slr = 0, o_part = 0,
          o_ord = 0,
          o_fk = 0,   // scratch of the fused similarity + top-k (fused_layout)
+         o_bm = 0,   // block maxima of S for the pruned top-k (n x tb floats), 0 = none
          o_rsc = 0;  // re-score scratch (the dead S buffer, or its own block without one)
   bool sparse_first = false;   // layer 1 built from the sparse A* / A rows (layers >= 1, sum or mean)
   bool sparse_layers = false;  // layers kept as CSR rows for the sparse final product

@@ -213,6 +213,113 @@ __device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, i
   }
 }
 
+// a3 with block maxima. bm[b * ldbm + i] holds the largest stored similarity
+// of row i in column block b (128 columns). The row itself ranks first, so
+// K - 1 other members are needed; blocks are disjoint, so any K - 1 blocks'
+// maxima are K - 1 distinct elements of the row, and the (K - 1)-th largest of
+// any set of non-diagonal block maxima is at or below the value of the row's
+// K-th member. The wave takes that bound t0 over each lane's largest
+// non-diagonal block maximum (a 64-entry sort), lists the blocks whose
+// maximum reaches t0 (and the diagonal block) in LDS, and reads only those,
+// four at a time; keys with a value of at least t0 that beat the K-th best so
+// far go through an LDS ring into the sorted list (as topk_row). Every member
+// lies in a listed block, so the lists are exactly topk_row's. With more than
+// 65 candidates (K - 1 > 64) every block is read.
+template <int R, typename T>
+__device__ __forceinline__ void topk_pruned_row(const T* __restrict__ S, int64_t ldS, int N, int i, int K,
+                                                const float* __restrict__ bm, int64_t ldbm,
+                                                int32_t* __restrict__ oidx, float* __restrict__ oval, int ldo,
+                                                uint64_t* ring, int* list) {
+  constexpr int NB = 8;  // up to 512 blocks: lane l holds blocks l, l + 64, ...
+  constexpr int Q = 4;   // blocks read per step
+  constexpr float NEG = -__builtin_inff();
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int TB = (N + 127) / 128, dblk = i / 128;
+  const T* srow = S + (int64_t)i * ldS;
+  float bx[NB];
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    const int t = b * 64 + lane;
+    bx[b] = t < TB ? bm[(int64_t)t * ldbm + i] : NEG;
+  }
+  float t0 = NEG;
+  if (K == 1) {
+    t0 = __builtin_inff();
+  } else if (K - 1 <= 64) {
+    float lm = NEG;
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+      if (b * 64 + lane != dblk) lm = fmaxf(lm, bx[b]);
+    uint64_t k[1] = {((uint64_t)ord_f32(lm) << 32) | (uint64_t)lane};
+    wave_sort_desc<1>(k);
+    const uint64_t kk = wave_rank_key<1>(k, K - 2);
+    t0 = unord_f32((uint32_t)(kk >> 32));  // -inf when fewer than K - 1 blocks exist
+  }
+  // the listed blocks, in block order
+  int nl = 0;
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    const int t = b * 64 + lane;
+    const bool sel = t < TB && (bx[b] >= t0 || t == dblk);
+    const uint64_t m = __ballot(sel);
+    if (sel) list[nl + __popcll(m & below)] = t;
+    nl += __popcll(m);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  uint64_t best[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) best[r] = (r == 0 && lane == 0) ? self_key((uint32_t)i) : 0ull;
+  uint64_t tau = K == 1 ? self_key((uint32_t)i) : 0ull;  // the K-th best key so far
+  int head = 0, cnt = 0;
+  for (int l0 = 0; l0 < nl; l0 += Q) {
+    float v[Q][2];
+    int c[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      c[q] = l0 + q < nl ? list[l0 + q] * 128 : N;
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const int col = c[q] + h * 64 + lane;
+        v[q][h] = col < N ? (float)srow[col] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; q++)
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const int col = c[q] + h * 64 + lane;
+        const bool pass = col < N && col != i && v[q][h] >= t0 && sel_key(v[q][h], (uint32_t)col) > tau;
+        const uint64_t m = __ballot(pass);
+        if (!m) continue;
+        if (pass) ring[(head + cnt + __popcll(m & below)) & 127] = sel_key(v[q][h], (uint32_t)col);
+        cnt += __popcll(m);
+        if (cnt >= 64) {
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          const uint64_t bk = ring[(head + lane) & 127];
+          head = (head + 64) & 127;
+          cnt -= 64;
+          wave_merge_batch<R>(best, bk);
+          tau = wave_rank_key<R>(best, K - 1);
+        }
+      }
+  }
+  if (cnt > 0) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint64_t bk = lane < cnt ? ring[(head + lane) & 127] : 0ull;
+    wave_merge_batch<R>(best, bk);
+  }
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int e = r * 64 + lane;
+    if (e < K) {
+      const uint32_t j = key_col(best[r]);
+      oidx[(int64_t)i * ldo + e] = (int32_t)j;
+      oval[(int64_t)i * ldo + e] = (j == (uint32_t)i) ? 1.0f : key_val(best[r]);
+    }
+  }
+}
+
 // ============================================================== a3b: re-score
 // Candidates of row i re-scored as cos(x_i, x_j): the FP32 products are exact
 // in FP64 and summed there (the sum's error, a few units of 2^-53 of
