@@ -70,13 +70,18 @@ def stage_work(spec, prec: str = "f32", extra=None, final: str = "f32", aggregat
     kc = min(k1 + (EXTRA[prec] if extra is None or extra < 0 else extra), n, 256)
     in_b = 2 if spec.dtype == "bf16" else 4
     s_b = 4 if prec == "f32" else 2  # the low-precision paths store S as binary16
+    # the library reads only the S blocks a member can lie in when the
+    # candidates are few against the row's 128-column blocks (as its plan decides)
+    tb = (n + 127) // 128
+    pruned = n <= 512 * 128 and 4 * (kc - 1) <= tb
     w = {
         # read X; write the padded FP32 copy, the low-precision copy, norms and scales
         "prep": ("byte", n * d * in_b + n * ldp * 4 + n * ldl * lb + 8 * n),
         # the unique entries of the symmetric S
         "similarity": ("flop", n * (n + 1) * d),
-        # read S once, write the candidate lists
-        "topk": ("byte", s_b * n * n + 8 * n * kc),
+        # read S once (pruned selection: the block maxima and at least one
+        # 128-column block per candidate), write the candidate lists
+        "topk": ("byte", (4 * n * tb + s_b * n * kc * 128 if pruned else s_b * n * n) + 8 * n * kc),
         # every feature row at least once, the candidates in, the k1 lists out
         "rescore": ("byte", n * ldp * 4 + 8 * n * kc + 8 * n * k1),
         "final": ("flop", 2 * q * g * n),

@@ -27,7 +27,9 @@ def test_stage_work_of_the_mid_workload():
     w = bench.stage_work(s, "f32")
     assert w["similarity"] == ("flop", n * (n + 1) * 2048)  # unique entries of the symmetric S
     assert w["final"] == ("flop", 2 * 3368 * 15913 * n)     # 2.067e12
-    assert w["topk"] == ("byte", 4 * n * n + 8 * n * 34)    # S read once, candidates written
+    # 34 candidates against 151 column blocks: the pruned selection reads the
+    # block maxima and at least one block per candidate
+    assert w["topk"] == ("byte", 4 * n * 151 + 4 * n * 34 * 128 + 8 * n * 34)
     # L = 1 with A* rows and the sum aggregator: the first layer is built from the
     # sparse rows and written once (no dense A*, no dense layer)
     assert w["propagate"] == ("byte", 4 * n * ldn + 13 * n * 26 + 4 * n)
@@ -51,15 +53,18 @@ def test_stage_work_of_the_large_workload():
     # layer 1 kept as CSR rows, layer 2 written once as dense rows from them
     assert w["propagate"] == ("byte", 2 * 13 * n * 20 + 4 * n + 4 * n * ldn)
     assert w["prep"] == ("byte", n * 512 * 2 + n * 512 * 4 + 8 * n)
+    # pruned selection at every precision (391 blocks per row)
+    assert w["topk"] == ("byte", 4 * n * 391 + 4 * n * 28 * 128 + 8 * n * 28)
+    assert bench.stage_work(s, "fp8")["topk"][1] == 4 * n * 391 + 2 * n * 52 * 128 + 8 * n * 52
 
 
 # Stage times (ms) measured on one MI355X (bench.py's HIP events and the
 # rocprofv3 kernel traces committed under profiles/).
 MEASURED = {
-    "mid_n19281_d2048": {"prep": 0.078, "similarity": 6.45, "topk": 0.299, "rescore": 0.402, "adjacency": 0.072,
+    "mid_n19281_d2048": {"prep": 0.078, "similarity": 6.45, "topk": 0.128, "rescore": 0.27, "adjacency": 0.072,
                          "propagate": 0.245, "final": 15.2},
-    "large_n50000_d512": {"prep": 0.0514, "similarity": 12.14, "topk": 1.707, "rescore": 0.306, "adjacency": 0.117,
-                          "propagate": 2.81, "final": 283.8},
+    "large_n50000_d512": {"prep": 0.0514, "similarity": 12.14, "topk": 0.29, "rescore": 0.27, "adjacency": 0.117,
+                          "propagate": 2.78, "final": 283.4},
 }
 
 
