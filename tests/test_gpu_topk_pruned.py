@@ -67,3 +67,24 @@ def test_pruned_selection_low_precision(gpu_lib, prec, n, k1):
         exact = xhat[ki[i]] @ xhat[i]
         exact[0] = 1.0
         np.testing.assert_allclose(kv[i], exact, atol=2e-6)
+
+
+@pytest.mark.parametrize("n,k1,extra", [
+    (33000, 60, 5),   # K - 1 = 64: the bound is the last lane maximum of the sort
+    (36000, 66, 4),   # K = 70 (two keys per lane): no bound, every block read
+])
+def test_pruned_selection_many_candidates(gpu_lib, n, k1, extra):
+    assert _pruned(n, k1, extra)
+    x = synth.random_features(n, 16, seed=n, n_ids=n // 40)
+    ki, kv = _knn(x, k1, extra_cand=extra)
+    assert np.all(ki[:, 0] == np.arange(n))
+    rows = np.random.Generator(np.random.PCG64(5)).choice(n, 300, replace=False)
+    g = orc.knn_lists(x, k1, 3, rows=rows)
+    xhat = orc.unit_rows(x)
+    from tests.parity import check_alternative
+    for r, i in enumerate(rows):
+        if g.gap1[r] >= TIE_TOL:
+            assert set(ki[i].tolist()) == set(g.idx[r].tolist()), f"row {i}"
+            np.testing.assert_allclose(kv[i], g.val[r], atol=2e-6)
+        else:
+            check_alternative(xhat, int(i), ki[i], TIE_TOL, "k1 set")
