@@ -40,6 +40,16 @@ enum { EPI_DIST = 1, EPI_SIM_SYM = 2, EPI_SIM_SYM16 = 3, EPI_PART = 4, EPI_KNN =
 __host__ __device__ constexpr int sim_lds_bytes(int epi) {
   return epi == EPI_SIM_SYM16 ? GEMM_LDS_1BUF : GEMM_LDS_BYTES;
 }
+// Layout of that LDS in the epilogue: the staged tile (128 rows of 128 + one
+// 16-byte run of padding, in the output type), the column-maximum join (256
+// floats), then the tile's scales (256 floats: rows m0 .., columns n0 ..).
+__host__ __device__ constexpr int sim_stage_bytes(int epi) {
+  return epi == EPI_SIM_SYM16 ? BM * (BN + 8) * 2 : BM * (BN + 4) * 4;
+}
+__host__ __device__ constexpr int sim_join_off(int epi) { return (sim_stage_bytes(epi) + 15) & ~15; }
+__host__ __device__ constexpr int sim_scale_off(int epi) { return sim_join_off(epi) + 256 * 4; }
+static_assert(sim_scale_off(EPI_SIM_SYM) + 256 * 4 <= sim_lds_bytes(EPI_SIM_SYM), "FP32 epilogue LDS");
+static_assert(sim_scale_off(EPI_SIM_SYM16) + 256 * 4 <= sim_lds_bytes(EPI_SIM_SYM16), "binary16 epilogue LDS");
 
 template <int MODE>
 __device__ __forceinline__ void mfma_stage(f32x16 (&acc)[2][2], const u32x4 (&a)[2][4], const u32x4 (&b)[2][4]) {
@@ -109,8 +119,28 @@ struct GemmArgs {
   int64_t ldbm = 0;
 };
 
+// This thread's share of tile (tm, tn)'s scales: the row scale of row
+// m0 + t (threads t < 128), else the column scale of column n0 + t - 128;
+// 0 outside the matrix. Fetched before the tile's K loop, so its latency
+// hides behind the products, and put in LDS for the epilogue.
+__device__ __forceinline__ float sim_scale_fetch(const GemmArgs& g, int tm, int tn) {
+  const int t = threadIdx.x;
+  if (t < BM) {
+    const int r = tm * BM + t;
+    return r < g.M ? g.sa[r] : 0.f;
+  }
+  const int c = tn * BN + t - BM;
+  return c < g.Nn ? g.sb[c] : 0.f;
+}
+template <int EPI>
+__device__ __forceinline__ void sim_scale_put(uint8_t* lds, float v) {
+  ((float*)(lds + sim_scale_off(EPI)))[threadIdx.x] = v;
+  __syncthreads();
+}
+
 // Similarity epilogue of tile (tm, tn) from its accumulators (EPI_SIM_SYM or
-// EPI_SIM_SYM16); uses `lds` (sim_lds_bytes(EPI)) and block barriers.
+// EPI_SIM_SYM16); uses `lds` (sim_lds_bytes(EPI)), which holds the tile's
+// scales (sim_scale_put) on entry, and block barriers.
 template <int EPI>
 __device__ __forceinline__ void sim_epilogue(const GemmArgs& g, int tm, int tn, const f32x16 (&acc)[2][2],
                                              uint8_t* lds) {
@@ -128,23 +158,28 @@ __device__ __forceinline__ void sim_epilogue(const GemmArgs& g, int tm, int tn, 
   using OT = typename std::conditional<H16, _Float16, float>::type;
   constexpr int V = 16 / (int)sizeof(OT);  // elements per 16-byte store
   constexpr int TS = BN + V;               // staged row stride (16-byte aligned rows)
-  static_assert(BM * TS * (int)sizeof(OT) <= sim_lds_bytes(EPI), "staged tile must fit the similarity LDS");
+  static_assert(BM * TS * (int)sizeof(OT) == sim_stage_bytes(EPI), "staged tile layout");
   typedef OT ov __attribute__((ext_vector_type(V)));
   OT* T = (OT*)lds;
+  // Scales are 0 outside the matrix, so those entries stage as +0 with no
+  // branch (they are neither stored nor counted in a maximum).
+  const float* sc = (const float*)(lds + sim_scale_off(EPI));
 #pragma unroll
-  for (int sm = 0; sm < 2; sm++)
+  for (int sm = 0; sm < 2; sm++) {
+    f32x4 rs[4];  // row scales of this lane's rows 8 j + 4 (lane / 32) + e of the sub-block
+#pragma unroll
+    for (int j = 0; j < 4; j++) rs[j] = *(const f32x4*)(sc + wm * 64 + sm * 32 + j * 8 + (lane >> 5) * 4);
 #pragma unroll
     for (int sn = 0; sn < 2; sn++) {
       const int lc = wn * 64 + sn * 32 + (lane & 31);
-      const int col = n0 + lc;
-      const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
+      const float scol = sc[BM + lc];
 #pragma unroll
       for (int r = 0; r < 16; r++) {
         const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        const int row = m0 + lr;
-        T[lr * TS + lc] = (row < g.M && col < g.Nn) ? sim_value<OT>(acc[sm][sn][r], g.sa[row], scol) : (OT)0.f;
+        T[lr * TS + lc] = sim_value<OT>(acc[sm][sn][r], rs[r >> 2][r & 3], scol);
       }
     }
+  }
   __syncthreads();
   constexpr int CPR = BN / V;           // 16-byte chunks per tile row
   constexpr int RPP = 256 / CPR;        // tile rows per pass
@@ -214,8 +249,7 @@ __device__ __forceinline__ void sim_epilogue(const GemmArgs& g, int tm, int tn, 
         if (m0 + ch * V + e < g.M) cmx = fmaxf(cmx, (float)v[e]);
     }
     if (g.bm) {  // row n0 + lc's maximum over column block tm: two halves, joined in LDS after the tile
-      float* cm = (float*)(lds + ((BM * TS * (int)sizeof(OT) + 15) & ~15));
-      static_assert(((BM * TS * (int)sizeof(OT) + 15) & ~15) + 256 * 4 <= sim_lds_bytes(EPI), "room for the join");
+      float* cm = (float*)(lds + sim_join_off(EPI));
       cm[tid] = cmx;
       __syncthreads();
       if (tid < BN && row < g.Nn) g.bm[(int64_t)tm * g.ldbm + row] = fmaxf(cm[tid], cm[tid + BN]);
@@ -351,12 +385,13 @@ __device__ __forceinline__ void knn_epilogue(const GemmArgs& g, int tm, int tn, 
     for (int sn = 0; sn < 2; sn++) {
       const int lc = wn * 64 + sn * 32 + (lane & 31);
       const int col = n0 + lc;
-      const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
+      const float scol = (col < g.Nn) ? g.sb[min(col, g.Nn - 1)] : 0.f;
 #pragma unroll
       for (int r = 0; r < 16; r++) {
         const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
         const int row = m0 + lr;
-        T[lr * TS + lc] = (row < g.M && col < g.Nn) ? sim_value<OT>(acc[sm][sn][r], g.sa[row], scol) : (OT)0.f;
+        const float srow = g.sa[min(row, g.M - 1)];  // loaded outside the bounds check
+        T[lr * TS + lc] = (row < g.M && col < g.Nn) ? sim_value<OT>(acc[sm][sn][r], srow, scol) : (OT)0.f;
       }
     }
   __syncthreads();
@@ -507,6 +542,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = tm * BM, n0 = tn * BN;
+  constexpr bool SIM = EPI == EPI_SIM_SYM || EPI == EPI_SIM_SYM16;
+  float scale = 0.f;
+  if constexpr (SIM || EPI == EPI_DIST) scale = sim_scale_fetch(g, tm, tn);
   f32x16 acc[2][2];
   gemm_tile_acc<MODE, NBUF, KS>(g, tm, tn, lds, acc, st0, st1);
   // 32x32 accumulator layout: register r of lane l holds
@@ -520,23 +558,35 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
         for (int r = 0; r < 16; r++) g.out[((sm * 2 + sn) * 16 + r) * 256 + tid] = acc[sm][sn][r];
     __syncthreads();
   } else if constexpr (EPI == EPI_DIST) {
+    // the tile's scales through LDS (free after the K loop), read as float4
+    // runs of this lane's rows, so no load waits inside the bounds checks
+    float* sc = (float*)lds;
+    sc[tid] = scale;
+    __syncthreads();
 #pragma unroll
-    for (int sm = 0; sm < 2; sm++)
+    for (int sm = 0; sm < 2; sm++) {
+      f32x4 rs[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) rs[j] = *(const f32x4*)(sc + wm * 64 + sm * 32 + j * 8 + (lane >> 5) * 4);
 #pragma unroll
       for (int sn = 0; sn < 2; sn++) {
         const int col = n0 + wn * 64 + sn * 32 + (lane & 31);
-        const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
+        const float scol = sc[BM + wn * 64 + sn * 32 + (lane & 31)];
 #pragma unroll
         for (int r = 0; r < 16; r++) {
           const int row = m0 + wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-          if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = 1.0f - g.sa[row] * scol * acc[sm][sn][r];
+          if (row < g.M && col < g.Nn)
+            g.out[(int64_t)row * g.ldo + col] = 1.0f - rs[r >> 2][r & 3] * scol * acc[sm][sn][r];
         }
       }
+    }
     __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
   } else if constexpr (EPI == EPI_KNN) {
     knn_epilogue<MODE>(g, tm, tn, acc, lds);
     __syncthreads();  // the staged tile is overwritten by the next tile's stages
   } else {
+    static_assert(SIM, "similarity epilogues");
+    sim_scale_put<EPI>(lds, scale);
     sim_epilogue<EPI>(g, tm, tn, acc, lds);
     __syncthreads();  // LDS is reused by the next tile of a persistent workgroup
   }
@@ -554,14 +604,15 @@ __device__ __forceinline__ void gemm_fix_tile(const GemmArgs& g, int tm, int tn,
 #pragma unroll
     for (int sn = 0; sn < 2; sn++) {
       const int col = n0 + wn * 64 + sn * 32 + (lane & 31);
-      const float scol = (col < g.Nn) ? g.sb[col] : 0.f;
+      const float scol = (col < g.Nn) ? g.sb[min(col, g.Nn - 1)] : 0.f;
 #pragma unroll 4
       for (int r = 0; r < 16; r++) {
         const int at = ((sm * 2 + sn) * 16 + r) * 256 + tid;
         float v = part[at];
         for (int k = 1; k < parts; k++) v += part[(int64_t)k * BM * BN + at];
         const int row = m0 + wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = 1.0f - g.sa[row] * scol * v;
+        const float srow = g.sa[min(row, g.M - 1)];  // loaded outside the bounds check
+        if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = 1.0f - srow * scol * v;
       }
     }
 }
@@ -572,6 +623,7 @@ template <int EPI>
 __device__ __forceinline__ void gemm_sim_fix_tile(const GemmArgs& g, int tm, int tn, const float* __restrict__ part,
                                                   int parts, uint8_t* lds) {
   const int tid = threadIdx.x;
+  const float scale = sim_scale_fetch(g, tm, tn);
   f32x16 acc[2][2];
 #pragma unroll
   for (int sm = 0; sm < 2; sm++)
@@ -584,6 +636,7 @@ __device__ __forceinline__ void gemm_sim_fix_tile(const GemmArgs& g, int tm, int
         for (int k = 1; k < parts; k++) v += part[(int64_t)k * BM * BN + at];
         acc[sm][sn][r] = v;
       }
+  sim_scale_put<EPI>(lds, scale);
   sim_epilogue<EPI>(g, tm, tn, acc, lds);
 }
 
@@ -689,7 +742,8 @@ __device__ __forceinline__ void gemm_tile_x3(const GemmX3Args& g, int tm, int tn
 #pragma unroll
       for (int r = 0; r < 16; r++) {
         const int row = m0 + wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        if (row < g.M) g.out[(int64_t)row * g.ldo + col] = 1.0f - g.sa[row] * scol * acc[sm][sn][r];
+        const float srow = g.sa[min(row, g.M - 1)];  // loaded outside the bounds check
+        if (row < g.M) g.out[(int64_t)row * g.ldo + col] = 1.0f - srow * scol * acc[sm][sn][r];
       }
     }
   __syncthreads();

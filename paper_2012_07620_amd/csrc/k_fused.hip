@@ -85,13 +85,13 @@ __global__ __launch_bounds__(256) void knn_sample_kernel(GemmArgs g, FusedGeo f,
     for (int sn = 0; sn < 2; sn++) {
       const int lc = wn * 64 + sn * 32 + (lane & 31);
       const int col = tn * BN + lc;
-      const float scol = col < g.Nn ? g.sb[col] : 0.f;
+      const float scol = col < g.Nn ? g.sb[min(col, g.Nn - 1)] : 0.f;
 #pragma unroll
       for (int r = 0; r < 16; r++) {
         const int row = tm * BM + wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const float srow = g.sa[min(row, g.M - 1)];  // loaded outside the bounds check
         if (row < g.M)
-          samp[(int64_t)row * f.m + t * BN + lc] = col < g.Nn ? sim_value<OT>(acc[sm][sn][r], g.sa[row], scol)
-                                                              : (OT)0.f;
+          samp[(int64_t)row * f.m + t * BN + lc] = col < g.Nn ? sim_value<OT>(acc[sm][sn][r], srow, scol) : (OT)0.f;
       }
     }
 }
@@ -262,12 +262,13 @@ void knn_emit_kernel(GemmArgs g, FusedGeo f, const OT* __restrict__ samp, EmitAr
       for (int sn = 0; sn < 2; sn++) {
         const int lc = wn * 64 + sn * 32 + (lane & 31);
         const int col = tn * BN + lc;
-        const float scol = col < g.Nn ? g.sb[col] : 0.f;
+        const float scol = col < g.Nn ? g.sb[min(col, g.Nn - 1)] : 0.f;
 #pragma unroll
         for (int r = 0; r < 16; r++) {
           const int lr = wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
           const int row = tm * BM + lr;
-          T[lr * TS + lc] = (row < g.M && col < g.Nn) ? sim_value<OT>(acc[sm][sn][r], g.sa[row], scol) : (OT)0.f;
+          const float srow = g.sa[min(row, g.M - 1)];  // loaded outside the bounds check
+          T[lr * TS + lc] = (row < g.M && col < g.Nn) ? sim_value<OT>(acc[sm][sn][r], srow, scol) : (OT)0.f;
         }
       }
   } else {
