@@ -23,7 +23,8 @@ time. The same line carries:
   by side, with its own roofline and oracle baseline;
 * ``serving``: the request stream (Poisson arrivals, N ~ U[1000, 30000]):
   closed-loop saturation, then open-loop p50 / p99 latency at 0.5 and 0.7 of
-  the FP32 saturation rate, for the FP32, BF16 and BF16 + sparse-final paths;
+  the FP32 saturation rate, for the FP32 and BF16 paths, and at 0.7 for BF16
+  with the FP32-accurate bf16x3 final product and BF16 + sparse final;
 * ``cpu_baseline``: the FP64 oracle timed on this host (model and threads
   stated).
 """
@@ -296,7 +297,7 @@ def serving_bench(binding, torch, synth, count, warmup, distinct, oracle_sample)
                         "latency": "arrival -> completion (rerank_wait), queueing included"},
            "saturation": {}, "open_loop": {}}
     for name, prec, final in (("f32", "f32", "f32"), ("bf16", "bf16", "f32"),
-                              ("bf16_final_sparse", "bf16", "sparse")):
+                              ("bf16_final_bf16x3", "bf16", "bf16x3"), ("bf16_final_sparse", "bf16", "sparse")):
         log(f"serving: closed-loop saturation, {name}")
         res["saturation"][name] = serve_leg(binding, torch, reqs, count, warmup, prec, final)
     mu = res["saturation"]["f32"]["req_per_s"]
@@ -304,8 +305,8 @@ def serving_bench(binding, torch, synth, count, warmup, distinct, oracle_sample)
     for frac in (0.5, 0.7):
         leg = {"qps": frac * mu}
         for name, prec, final in (("f32", "f32", "f32"), ("bf16", "bf16", "f32"),
-                                  ("bf16_final_sparse", "bf16", "sparse")):
-            if frac == 0.5 and name == "bf16_final_sparse":
+                                  ("bf16_final_bf16x3", "bf16", "bf16x3"), ("bf16_final_sparse", "bf16", "sparse")):
+            if frac == 0.5 and name in ("bf16_final_bf16x3", "bf16_final_sparse"):
                 continue
             log(f"serving: open loop at {frac} x mu_f32 = {frac * mu:.1f} req/s, {name}")
             leg[name] = serve_leg(binding, torch, reqs, count, warmup, prec, final, qps=frac * mu)

@@ -160,7 +160,7 @@ def test_injected_allocation_failure_fails_one_request(gpu_lib):
 
 
 @pytest.mark.parametrize("kw", [dict(aggregator="mean"), dict(aggregator="max"), dict(node="adj_raw"),
-                                dict(final_prec="sparse"), dict(final_prec="bf16")])
+                                dict(final_prec="sparse"), dict(final_prec="bf16"), dict(final_prec="bf16x3")])
 def test_variants_same_alone_and_in_the_mix(gpu_lib, kw):
     from paper_2012_07620_amd import binding
     probs = _requests(51, 6, 300, 2500) + _requests(52, 1, 9000, 9500, dims=(128,))
