@@ -25,8 +25,11 @@
  *   - Functions return a rerank_status and never abort. Parameters are
  *     validated before any work is enqueued; on error nothing is enqueued
  *     and rerank_last_error() gives a readable reason.
- *   - Inputs must be finite and no feature row may be all zero; the result is
- *     unspecified otherwise.
+ *   - Inputs must be finite and no feature row may be all zero; the values of
+ *     the result are unspecified otherwise. Even then, every neighbour list
+ *     holds K distinct columns of the problem (row i first), so no stage reads
+ *     outside its buffers: a selection whose pruning bound admits fewer than K
+ *     values (a NaN passes no comparison) re-selects over the whole row.
  *   - All library-owned device memory (similarity matrix, neighbour lists,
  *     feature buffers) comes from a pool bounded by the context's budget.
  */

@@ -309,7 +309,10 @@ __global__ __launch_bounds__(256) void knn_select_kernel(const uint64_t* __restr
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
   const int c = cnt[i];
-  if (c > C) {
+  // an overflowed buffer, or fewer than K kept values (possible only when the
+  // bound and the values disagree, as with non-finite inputs): the row panel
+  // is recomputed in full
+  if (c > C || c < K) {
     if (lane == 0) flag[i / BM] = 1;
     return;
   }

@@ -224,7 +224,10 @@ __device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, i
 // four at a time; keys with a value of at least t0 that beat the K-th best so
 // far go through an LDS ring into the sorted list (as topk_row). Every member
 // lies in a listed block, so the lists are exactly topk_row's. With more than
-// 65 candidates (K - 1 > 64) every block is read.
+// 65 candidates (K - 1 > 64) every block is read. A row that ends with fewer
+// than K keys (only possible when S and the block maxima disagree, as with
+// non-finite inputs, whose NaN values pass no bound) is selected again by
+// topk_row over the whole row, so every list holds K columns of the row.
 template <int R, typename T>
 __device__ __forceinline__ void topk_pruned_row(const T* __restrict__ S, int64_t ldS, int N, int i, int K,
                                                 const float* __restrict__ bm, int64_t ldbm,
@@ -308,6 +311,14 @@ __device__ __forceinline__ void topk_pruned_row(const T* __restrict__ S, int64_t
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const uint64_t bk = lane < cnt ? ring[(head + lane) & 127] : 0ull;
     wave_merge_batch<R>(best, bk);
+  }
+  int have = 0;  // keys held (key 0 = empty)
+#pragma unroll
+  for (int r = 0; r < R; r++) have += __popcll(__ballot(r * 64 + lane < K && best[r] != 0ull));
+  if (have < K) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the ring is reused
+    topk_row<R, false, T>(S, ldS, N, i, K, oidx, oval, ldo, ring);
+    return;
   }
 #pragma unroll
   for (int r = 0; r < R; r++) {
