@@ -49,16 +49,42 @@ __global__ __launch_bounds__(256) void topk_pruned_kernel(const T* __restrict__ 
   topk_pruned_row<R, T>(S, ldS, N, i, K, bm, ldbm, oidx, oval, ldo, ring_all[w], list_all[w]);
 }
 
+// Rows the pruned selection left marked (first index -1) are selected again
+// over the whole row. One wavefront checks 64 rows with one load, so a launch
+// over finite inputs, where no row is marked, reads 4 bytes per row.
+template <int R, typename T>
+__global__ __launch_bounds__(256) void topk_redo_kernel(const T* __restrict__ S, int64_t ldS, int N, int rows, int K,
+                                                        int32_t* __restrict__ oidx, float* __restrict__ oval,
+                                                        int ldo) {
+  __shared__ uint64_t ring_all[4][128];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i0 = (blockIdx.x * 4 + w) * 64;
+  if (i0 >= rows) return;  // waves are independent
+  const int i = i0 + lane;
+  uint64_t m = __ballot(i < rows && oidx[(int64_t)i * ldo] < 0);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // every lane has read its marker
+  while (m) {
+    const int r = __builtin_ctzll(m);
+    m &= m - 1;
+    topk_row<R, false, T>(S, ldS, N, i0 + r, K, oidx, oval, ldo, ring_all[w]);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the ring is reused by the next row
+  }
+}
+
 template <typename T>
 static void launch_topk_pruned_t(const T* S, int64_t ldS, int N, int rows, int K, const float* bm, int64_t ldbm,
                                  int32_t* idx, float* val, int ldo, hipStream_t s) {
-  dim3 grid((rows + 3) / 4), block(256);
-  if (K <= 64)
+  dim3 grid((rows + 3) / 4), block(256), grid_redo((rows + 255) / 256);
+  if (K <= 64) {
     hipLaunchKernelGGL((topk_pruned_kernel<1, T>), grid, block, 0, s, S, ldS, N, rows, K, bm, ldbm, idx, val, ldo);
-  else if (K <= 128)
+    hipLaunchKernelGGL((topk_redo_kernel<1, T>), grid_redo, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
+  } else if (K <= 128) {
     hipLaunchKernelGGL((topk_pruned_kernel<2, T>), grid, block, 0, s, S, ldS, N, rows, K, bm, ldbm, idx, val, ldo);
-  else
+    hipLaunchKernelGGL((topk_redo_kernel<2, T>), grid_redo, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
+  } else {
     hipLaunchKernelGGL((topk_pruned_kernel<4, T>), grid, block, 0, s, S, ldS, N, rows, K, bm, ldbm, idx, val, ldo);
+    hipLaunchKernelGGL((topk_redo_kernel<4, T>), grid_redo, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
+  }
 }
 
 hipError_t launch_topk_pruned(const void* S, bool half, int64_t ldS, int N, int rows, int K, const float* bm,

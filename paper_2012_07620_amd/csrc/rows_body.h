@@ -226,8 +226,11 @@ __device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, i
 // lies in a listed block, so the lists are exactly topk_row's. With more than
 // 65 candidates (K - 1 > 64) every block is read. A row that ends with fewer
 // than K keys (only possible when S and the block maxima disagree, as with
-// non-finite inputs, whose NaN values pass no bound) is selected again by
-// topk_row over the whole row, so every list holds K columns of the row.
+// non-finite inputs, whose NaN values pass no bound) writes -1 as its first
+// index and nothing else; the launcher then selects such rows again over the
+// whole row (topk_redo_kernel), so every list holds K columns of the row. The
+// whole-row selection is not inlined here: it needs about twice the registers
+// of this function and would halve its occupancy.
 template <int R, typename T>
 __device__ __forceinline__ void topk_pruned_row(const T* __restrict__ S, int64_t ldS, int N, int i, int K,
                                                 const float* __restrict__ bm, int64_t ldbm,
@@ -316,8 +319,7 @@ __device__ __forceinline__ void topk_pruned_row(const T* __restrict__ S, int64_t
 #pragma unroll
   for (int r = 0; r < R; r++) have += __popcll(__ballot(r * 64 + lane < K && best[r] != 0ull));
   if (have < K) {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the ring is reused
-    topk_row<R, false, T>(S, ldS, N, i, K, oidx, oval, ldo, ring);
+    if (lane == 0) oidx[(int64_t)i * ldo] = -1;  // selected again over the whole row
     return;
   }
 #pragma unroll
