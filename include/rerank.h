@@ -28,8 +28,9 @@
  *   - Inputs must be finite and no feature row may be all zero; the values of
  *     the result are unspecified otherwise. Even then, every neighbour list
  *     holds K distinct columns of the problem (row i first), so no stage reads
- *     outside its buffers: a selection whose pruning bound admits fewer than K
- *     values (a NaN passes no comparison) re-selects over the whole row.
+ *     outside its buffers: a NaN similarity ranks after every number, and a
+ *     selection whose pruning bound admits fewer than K values (a NaN passes
+ *     no comparison) re-selects over the whole row.
  *   - All library-owned device memory (similarity matrix, neighbour lists,
  *     feature buffers) comes from a pool bounded by the context's budget.
  */

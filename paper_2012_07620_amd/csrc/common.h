@@ -35,11 +35,15 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kWave = 64;
 
 // Order-preserving map float -> uint32 (larger float -> larger integer);
-// -0.0 is mapped like +0.0. Inputs are finite.
+// -0.0 is mapped like +0.0. A NaN (any sign or payload) maps to 0, below
+// -inf, so an undefined similarity ranks after every number and a few
+// non-finite rows do not displace the neighbours of the others; unord_f32(0)
+// is a NaN again.
 __device__ __forceinline__ uint32_t ord_f32(float v) {
   uint32_t b = __float_as_uint(v);
   if (b == 0x80000000u) b = 0u;
-  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  const uint32_t o = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return v == v ? o : 0u;
 }
 __device__ __forceinline__ float unord_f32(uint32_t u) {
   return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);

@@ -125,7 +125,8 @@ __global__ __launch_bounds__(256) void knn_tau_kernel(const OT* __restrict__ sam
     for (int u = 0; u < 4; u++) {
       const int t = (int)b + u * 64 + lane;
       const int j = f.sample(t / BN) * BN + t % BN;
-      v[u] = (t < f.m && j < n && j != i) ? (float)row[t] : NEG;
+      const float s = t < f.m ? (float)row[t] : NEG;
+      v[u] = (t < f.m && j < n && j != i && s == s) ? s : NEG;  // a NaN ranks last, as in the keys
     }
 #pragma unroll
     for (int u = 0; u < 4; u++) put(v[u]);

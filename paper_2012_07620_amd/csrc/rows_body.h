@@ -169,9 +169,12 @@ __device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, i
       for (int e = 0; e < 4; e++) {
         const int col = c0 + u * 256 + lane * 4 + e;
         // a key above tau has a value of at least tau's (or is the row's own
-        // column): full keys are built only when some lane has such a value
+        // column): full keys are built only when some lane has such a value.
+        // Written as "not below" so that a NaN, which the key orders by its
+        // bits, still reaches the key comparison and a row of NaN values
+        // fills its K slots.
         const float sv = ASC ? -v[u][e] : v[u][e];
-        const bool cand = col < N && (sv >= tf || (!ASC && col == i));
+        const bool cand = col < N && (!(sv < tf) || (!ASC && col == i));
         if (!__ballot(cand)) continue;
         uint64_t key = 0;
         if (col < N)
