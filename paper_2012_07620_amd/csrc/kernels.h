@@ -53,7 +53,8 @@ inline int64_t pad_k_elems(int64_t d, int bytes_per_elem) {
 inline int64_t pad_n(int64_t n) { return (n + 63) / 64 * 64; }
 
 // a1: feature preparation. Reads X (f32 or bf16 bits), writes
-//   xp  N x ldp float32 copy, zero-padded (always)
+//   xp  N x ldp float32 copy, zero-padded; null when the caller's FP32 rows
+//       are used in place (feature_rows)
 //   rn  1 / |x_i| (compensated sum of squares, correctly rounded sqrt/div)
 //   xl  low-precision copy (bf16 or fp8 e4m3, ldl elements) when prec != F32
 //   sl  per-row scale of the low-precision product (rn_i, or rn_i * s_i)

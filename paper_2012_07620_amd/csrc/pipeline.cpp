@@ -80,7 +80,7 @@ static T* at(void* ws, size_t off) {
 
 hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipStream_t s, const char** where,
                        StageClock* clk) {
-  float* xp = at<float>(ws, P.o_xp);
+  const float* xp = feature_rows(P, ws, x, in_bf16);
   float* rn = at<float>(ws, P.o_rn);
   float* sl = at<float>(ws, P.o_sl);
   void* xl = P.lbytes ? at<void>(ws, P.o_xl) : nullptr;
@@ -90,7 +90,8 @@ hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipS
   int32_t* ki = at<int32_t>(ws, P.o_ki);
   float* kv = at<float>(ws, P.o_kv);
   RR_STAGE(RERANK_STAGE_PREP, 0);
-  RR_TRY(launch_prep(x, in_bf16, P.n, P.d, xp, P.ldp, rn, P.prec, xl, P.ldl, sl, s));
+  RR_TRY(launch_prep(x, in_bf16, P.n, P.d, features_in_place(P, x, in_bf16) ? nullptr : at<float>(ws, P.o_xp), P.ldp,
+                     rn, P.prec, xl, P.ldl, sl, s));
   RR_STAGE(RERANK_STAGE_PREP, 1);
   RR_STAGE(RERANK_STAGE_SIMILARITY, 0);
   if (P.fused) {  // S never written: the similarity stage also selects the candidates
@@ -153,7 +154,7 @@ hipError_t enqueue_rerank(const Plan& P, void* ws, const void* x, int in_bf16, f
                           const char** where, StageClock* clk) {
   hipError_t e = enqueue_knn(P, ws, x, in_bf16, s, where, clk);
   if (e != hipSuccess) return e;
-  float* xp = at<float>(ws, P.o_xp);
+  const float* xp = feature_rows(P, ws, x, in_bf16);
   float* rn = at<float>(ws, P.o_rn);
   float* A = at<float>(ws, P.o_a);
   float* B = (P.layers > 0 || P.fprec == FinalPrec::SPARSE) ? at<float>(ws, P.o_b) : nullptr;

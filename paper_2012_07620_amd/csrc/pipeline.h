@@ -32,6 +32,17 @@ struct StageClock {
   hipError_t totals(double* mean_ms);  // mean per call since the last totals(), then reset
 };
 
+// The FP32 feature rows that the products, the re-score and raw-feature
+// layers read: the caller's rows in place when they already have the padded
+// layout (FP32 input, d a multiple of 64, 256-byte aligned), so prep only
+// reads them; else the zero-padded copy prep writes into the working set.
+inline bool features_in_place(const Plan& P, const void* x, int in_bf16) {
+  return !in_bf16 && P.ldp == P.d && ((uintptr_t)x & 255u) == 0;
+}
+inline const float* feature_rows(const Plan& P, void* ws, const void* x, int in_bf16) {
+  return features_in_place(P, x, in_bf16) ? (const float*)x : (const float*)((char*)ws + P.o_xp);
+}
+
 // Phase 1: features -> neighbour lists (in the working set at P.o_ki/P.o_kv).
 hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipStream_t s, const char** where,
                        StageClock* clk = nullptr);

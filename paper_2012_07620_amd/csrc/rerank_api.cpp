@@ -344,11 +344,13 @@ rerank_status rerank_similarity(rerank_ctx* ctx, const rerank_params* p, const v
   Plan P;
   make_plan(p, true, &P);
   return with_ws(ctx, P, hip_stream, [&](hipStream_t s, const char** where) -> hipError_t {
-    float* xp = (float*)((char*)ctx->ws + P.o_xp);
+    const int in_bf16 = in_dtype == RERANK_IN_BF16;
+    const float* xp = feature_rows(P, ctx->ws, d_x, in_bf16);
     float* rn = (float*)((char*)ctx->ws + P.o_rn);
     float* sl = (float*)((char*)ctx->ws + P.o_sl);
     void* xl = P.lbytes ? (char*)ctx->ws + P.o_xl : nullptr;
-    hipError_t e = launch_prep(d_x, in_dtype == RERANK_IN_BF16, P.n, P.d, xp, P.ldp, rn, P.prec, xl, P.ldl, sl, s);
+    float* copy = features_in_place(P, d_x, in_bf16) ? nullptr : (float*)((char*)ctx->ws + P.o_xp);
+    hipError_t e = launch_prep(d_x, in_bf16, P.n, P.d, copy, P.ldp, rn, P.prec, xl, P.ldl, sl, s);
     if (e != hipSuccess) {
       *where = "launch_prep";
       return e;

@@ -39,47 +39,107 @@ __device__ __forceinline__ uint32_t e4m3_rne_sat(float f) {
   return sign | code;
 }
 
-// One wavefront per row: exact FP32 copy (zero-padded to ldp), 1/|x_i| from a
-// compensated sum of squares with correctly rounded sqrt and division, and the
-// low-precision copy with its row scale.
+// One wavefront per row: exact FP32 copy (zero-padded to ldp; not written
+// when xp is null, where the caller's FP32 rows are used in place), 1/|x_i|
+// from a compensated sum of squares with correctly rounded sqrt and division,
+// and the low-precision copy with its row scale. A row of a multiple of 4
+// elements on an aligned input moves 4 elements per lane and access (16-byte
+// FP32, 8-byte bf16 loads); any other row one element. The choice depends
+// only on d and the input address, so every launch of a problem makes the
+// same one.
 template <SimPrec P, bool IN_BF16>
 __device__ __forceinline__ void prep_row(const void* __restrict__ x, int i, int d, float* __restrict__ xp,
                                          int64_t ldp, float* __restrict__ rn, void* __restrict__ xl, int64_t ldl,
                                          float* __restrict__ sl) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
   const int lane = threadIdx.x & 63;
   const int64_t src = (int64_t)i * d;
-  float* xr = xp + (int64_t)i * ldp;
+  const float* xf = (const float*)x + src;
+  const uint16_t* xh = (const uint16_t*)x + src;
+  float* xr = xp ? xp + (int64_t)i * ldp : nullptr;
+  const bool vec = (d & 3) == 0 && ((uintptr_t)x & (IN_BF16 ? 7u : 15u)) == 0;
+  auto in1 = [&](int k) -> float { return IN_BF16 ? __uint_as_float((uint32_t)xh[k] << 16) : xf[k]; };
+  auto in4 = [&](int k) -> f32x4 {  // elements k .. k + 3, k < d, d a multiple of 4
+    if (IN_BF16) {
+      const u32x2 b = *(const u32x2*)(xh + k);
+      return f32x4{__uint_as_float(b.x << 16), __uint_as_float(b.x & 0xFFFF0000u), __uint_as_float(b.y << 16),
+                   __uint_as_float(b.y & 0xFFFF0000u)};
+    }
+    return *(const f32x4*)(xf + k);
+  };
   DF acc{0.f, 0.f};
   float amax = 0.f;
-  for (int k = lane; k < ldp; k += 64) {
-    float v = 0.f;
-    if (k < d) {
-      if (IN_BF16)
-        v = __uint_as_float((uint32_t)((const uint16_t*)x)[src + k] << 16);
-      else
-        v = ((const float*)x)[src + k];
+  uint16_t* xb = P == SimPrec::BF16 ? (uint16_t*)xl + (int64_t)i * ldl : nullptr;
+  uint8_t* xq = P == SimPrec::FP8 ? (uint8_t*)xl + (int64_t)i * ldl : nullptr;
+  // FP8 quantises after the row maximum is known, so it reads the row twice;
+  // its first KEEP steps stay in registers (d <= 2048 without a second read)
+  constexpr int KEEP = P == SimPrec::FP8 ? 8 : 1;
+  f32x4 keep[KEEP];
+  if (vec) {
+    // one step of the first pass: copy, sum of squares, maximum, and the
+    // bfloat16 copy (its rows are padded like the FP32 ones)
+    auto step = [&](int k) -> f32x4 {
+      const f32x4 v = k < d ? in4(k) : f32x4{0.f, 0.f, 0.f, 0.f};
+      if (k < ldp) {
+        if (xr) *(f32x4*)(xr + k) = v;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          dot2_acc(acc, v[e], v[e]);
+          amax = fmaxf(amax, fabsf(v[e]));
+        }
+      }
+      if (P == SimPrec::BF16 && k < ldl) {
+        u32x2 o = {0u, 0u};
+        if (k < d) {
+          if (IN_BF16) {
+            o = *(const u32x2*)(xh + k);
+          } else {
+            o.x = (uint32_t)bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16);
+            o.y = (uint32_t)bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16);
+          }
+        }
+        *(u32x2*)(xb + k) = o;
+      }
+      return v;
+    };
+    const int kend = ldp > ldl ? (int)ldp : (int)ldl;
+#pragma unroll
+    for (int j = 0; j < KEEP; j++) keep[j] = step(4 * lane + 256 * j);
+    for (int k = 4 * lane + 256 * KEEP; k < kend; k += 256) step(k);
+  } else {
+    for (int k = lane; k < ldp; k += 64) {
+      const float v = k < d ? in1(k) : 0.f;
+      if (xr) xr[k] = v;
+      dot2_acc(acc, v, v);
+      amax = fmaxf(amax, fabsf(v));
     }
-    xr[k] = v;
-    dot2_acc(acc, v, v);
-    amax = fmaxf(amax, fabsf(v));
+    if (P == SimPrec::BF16)
+      for (int k = lane; k < ldl; k += 64) xb[k] = k < d ? (IN_BF16 ? xh[k] : bf16_rne(xf[k])) : (uint16_t)0;
   }
   acc = wave_sum_df(acc);
   const float n2 = acc.hi + acc.lo;
   const float r = __fdiv_rn(1.0f, __fsqrt_rn(n2));
   if (P == SimPrec::BF16) {
-    uint16_t* xb = (uint16_t*)xl + (int64_t)i * ldl;
-    for (int k = lane; k < ldl; k += 64) {
-      uint16_t b = 0;
-      if (k < d) b = IN_BF16 ? ((const uint16_t*)x)[src + k] : bf16_rne(xr[k]);
-      xb[k] = b;
-    }
     if (lane == 0) sl[i] = r;
   } else if (P == SimPrec::FP8) {
     amax = wave_max_f32(amax);
     const float scale = amax > 0.f ? amax / 448.0f : 1.0f;
     const float inv = amax > 0.f ? 448.0f / amax : 1.0f;
-    uint8_t* xq = (uint8_t*)xl + (int64_t)i * ldl;
-    for (int k = lane; k < ldl; k += 64) xq[k] = (uint8_t)(k < d ? e4m3_rne_sat(xr[k] * inv) : 0u);
+    if (vec) {
+      auto put = [&](int k, const f32x4& v) {
+        if (k < ldl) {
+          uint32_t o = 0u;
+#pragma unroll
+          for (int e = 0; e < 4; e++) o |= e4m3_rne_sat(v[e] * inv) << (8 * e);  // v = 0 past d: code 0
+          *(uint32_t*)(xq + k) = o;
+        }
+      };
+#pragma unroll
+      for (int j = 0; j < KEEP; j++) put(4 * lane + 256 * j, keep[j]);
+      for (int k = 4 * lane + 256 * KEEP; k < ldl; k += 256) put(k, k < d ? in4(k) : f32x4{0.f, 0.f, 0.f, 0.f});
+    } else {
+      for (int k = lane; k < ldl; k += 64) xq[k] = (uint8_t)(k < d ? e4m3_rne_sat(in1(k) * inv) : 0u);
+    }
     if (lane == 0) sl[i] = r * scale;
   }
   if (lane == 0) rn[i] = r;

@@ -44,6 +44,9 @@ def test_stage_work_of_the_mid_workload():
     assert bench.stage_work(s, "fp8", extra=16)["topk"][1] == 2 * n * n + 8 * n * 42
     assert bench.stage_work(s, "fp8")["topk"][1] == 2 * n * n + 8 * n * 58
     assert abs(w["final"][1] - 2.067e12) / 2.067e12 < 1e-3
+    # FP32 rows of 2048 floats are read in place: no FP32 copy is written
+    assert w["prep"] == ("byte", n * 2048 * 4 + 8 * n)
+    assert bench.stage_work(s, "bf16")["prep"] == ("byte", n * 2048 * 4 + n * 2048 * 2 + 8 * n)
 
 
 def test_stage_work_of_the_large_workload():
@@ -61,7 +64,7 @@ def test_stage_work_of_the_large_workload():
 # Stage times (ms) measured on one MI355X (bench.py's HIP events and the
 # rocprofv3 kernel traces committed under profiles/).
 MEASURED = {
-    "mid_n19281_d2048": {"prep": 0.078, "similarity": 6.45, "topk": 0.128, "rescore": 0.27, "adjacency": 0.072,
+    "mid_n19281_d2048": {"prep": 0.045, "similarity": 6.45, "topk": 0.128, "rescore": 0.27, "adjacency": 0.072,
                          "propagate": 0.245, "final": 15.2},
     "large_n50000_d512": {"prep": 0.0514, "similarity": 12.14, "topk": 0.29, "rescore": 0.27, "adjacency": 0.117,
                           "propagate": 2.78, "final": 283.4},

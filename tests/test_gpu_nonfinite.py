@@ -1,10 +1,10 @@
-"""Non-finite features (NaN, Inf) give undefined distances for their own rows,
-but every candidate list still holds K columns of the problem: the selection
-keys rank a NaN similarity after every number, and the block-pruned selection
-and the fused k-NN fall back to a whole-row selection when their bound admits
-fewer than K values (NaN passes no bound), so nothing downstream indexes a row
-outside the problem and the other rows keep finite distances. Every call goes
-through the C-ABI library."""
+"""Non-finite features (NaN, Inf) and all-zero rows give undefined distances
+for their own rows, but every candidate list still holds K columns of the
+problem: the selection keys rank a NaN similarity after every number, and the
+block-pruned selection and the fused k-NN fall back to a whole-row selection
+when their bound admits fewer than K values (NaN passes no bound), so nothing
+downstream indexes a row outside the problem and the other rows keep finite
+distances. Every call goes through the C-ABI library."""
 import numpy as np
 import pytest
 
@@ -21,6 +21,7 @@ def _features(n, d, seed):
     x[5, 3] = float("nan")
     x[77, :] = float("inf")
     x[n - 1, 0] = float("-inf")
+    x[10, :] = 0.0  # norm 0: its similarities are 0 * inf = NaN
     return x, spec.n_query
 
 
@@ -51,7 +52,7 @@ def test_non_finite_features_keep_the_lists_in_range(gpu_lib, prec, fused, n, k1
         assert d.shape == (q, n - q)
         # a NaN similarity ranks after every number, so the rows with finite
         # features keep finite neighbours, and only the rows and columns of the
-        # three non-finite vectors have undefined distances
+        # four vectors without a direction have undefined distances
         assert np.isfinite(d.cpu().numpy()).mean() > 0.9
     ctx.close()
 
