@@ -18,10 +18,12 @@
  *
  * Conventions for every entry point:
  *   - Pointers named d_* are device pointers on the context's HIP device,
- *     owned by the caller, row-major and contiguous. They must stay valid
- *     until the work that uses them has completed (stream order for the
- *     stream-ordered calls, until rerank_wait/rerank_poll report completion
- *     for submitted requests).
+ *     owned by the caller, row-major and contiguous. They must stay valid,
+ *     and inputs unchanged, until the work that uses them has completed
+ *     (stream order for the stream-ordered calls, until rerank_wait/
+ *     rerank_poll report completion for submitted requests): FP32 features
+ *     whose rows are already 256-byte multiples on a 256-byte aligned address
+ *     are read in place by every stage rather than copied.
  *   - Functions return a rerank_status and never abort. Parameters are
  *     validated before any work is enqueued; on error nothing is enqueued
  *     and rerank_last_error() gives a readable reason.
