@@ -592,6 +592,25 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, uin
   }
 }
 
+// Sum of the `parts` partial tiles of one K-split tile, in range order
+// (part 0 + part 1 + ...), for this thread's 64 accumulator positions. Each
+// range is one pass of 64 independent loads, so the passes wait on memory
+// once each rather than once per element.
+__device__ __forceinline__ void fix_sum(const float* __restrict__ part, int parts, float (&v)[4][16]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < 4; s++)
+#pragma unroll
+    for (int r = 0; r < 16; r++) v[s][r] = part[(s * 16 + r) * 256 + tid];
+  for (int k = 1; k < parts; k++) {
+    const float* pk = part + (int64_t)k * BM * BN;
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) v[s][r] += pk[(s * 16 + r) * 256 + tid];
+  }
+}
+
 // Tail tile (tm, tn) of EPI_DIST computed as `parts` K ranges: sum the EPI_PART
 // partial tiles in range order, then the EPI_DIST epilogue.
 __device__ __forceinline__ void gemm_fix_tile(const GemmArgs& g, int tm, int tn, const float* __restrict__ part,
@@ -599,20 +618,19 @@ __device__ __forceinline__ void gemm_fix_tile(const GemmArgs& g, int tm, int tn,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = tm * BM, n0 = tn * BN;
+  float v[4][16];
+  fix_sum(part, parts, v);
 #pragma unroll
   for (int sm = 0; sm < 2; sm++)
 #pragma unroll
     for (int sn = 0; sn < 2; sn++) {
       const int col = n0 + wn * 64 + sn * 32 + (lane & 31);
       const float scol = (col < g.Nn) ? g.sb[min(col, g.Nn - 1)] : 0.f;
-#pragma unroll 4
+#pragma unroll
       for (int r = 0; r < 16; r++) {
-        const int at = ((sm * 2 + sn) * 16 + r) * 256 + tid;
-        float v = part[at];
-        for (int k = 1; k < parts; k++) v += part[(int64_t)k * BM * BN + at];
         const int row = m0 + wm * 64 + sm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
         const float srow = g.sa[min(row, g.M - 1)];  // loaded outside the bounds check
-        if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = 1.0f - srow * scol * v;
+        if (row < g.M && col < g.Nn) g.out[(int64_t)row * g.ldo + col] = 1.0f - srow * scol * v[sm * 2 + sn][r];
       }
     }
 }
@@ -622,20 +640,16 @@ __device__ __forceinline__ void gemm_fix_tile(const GemmArgs& g, int tm, int tn,
 template <int EPI>
 __device__ __forceinline__ void gemm_sim_fix_tile(const GemmArgs& g, int tm, int tn, const float* __restrict__ part,
                                                   int parts, uint8_t* lds) {
-  const int tid = threadIdx.x;
   const float scale = sim_scale_fetch(g, tm, tn);
+  float v[4][16];
+  fix_sum(part, parts, v);
   f32x16 acc[2][2];
 #pragma unroll
   for (int sm = 0; sm < 2; sm++)
 #pragma unroll
     for (int sn = 0; sn < 2; sn++)
-#pragma unroll 4
-      for (int r = 0; r < 16; r++) {
-        const int at = ((sm * 2 + sn) * 16 + r) * 256 + tid;
-        float v = part[at];
-        for (int k = 1; k < parts; k++) v += part[(int64_t)k * BM * BN + at];
-        acc[sm][sn][r] = v;
-      }
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[sm][sn][r] = v[sm * 2 + sn][r];
   sim_scale_put<EPI>(lds, scale);
   sim_epilogue<EPI>(g, tm, tn, acc, lds);
 }
