@@ -734,7 +734,8 @@ __device__ __forceinline__ void mutual_pair(const int32_t* __restrict__ knn, int
   const int j = knn[t];
   const int32_t* lj = knn + (int64_t)j * k1;
   bool mut = false;
-  for (int s = 0; s < k1; s++) mut |= (lj[s] == m);
+#pragma unroll 8
+  for (int s = 0; s < k1; s++) mut |= (lj[s] == m);  // eight loads in flight per step
   mflag[t] = mut ? 1 : 0;
   if (!mut) atomicAdd(innm + j, 1);
 }
