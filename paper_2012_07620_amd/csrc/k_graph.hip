@@ -17,7 +17,8 @@ __global__ void order_key_kernel(const int32_t* __restrict__ lists, int rows, in
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rows) return;
   int m = i;
-  for (int c = 0; c < w; c++) m = min(m, lists[(int64_t)i * w + c]);
+#pragma unroll 8
+  for (int c = 0; c < w; c++) m = min(m, lists[(int64_t)i * w + c]);  // eight loads in flight per step
   key[i] = m;
   atomicAdd(cnt + m, 1);
 }
