@@ -298,3 +298,7 @@ def test_features_read_in_place_and_copied_agree(gpu_lib):
         db, ib, vb = binding.run(b, q, 20, 6, 1, sim_prec=prec, return_knn=True)
         torch.cuda.synchronize()
         assert torch.equal(ia, ib) and torch.equal(va, vb) and torch.equal(da, db)
+        # the similarity entry point reads the rows the same two ways
+        sa, sb = binding.similarity(a, sim_prec=prec), binding.similarity(b, sim_prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(sa, sb)
