@@ -74,7 +74,7 @@ def stage_work(spec, prec: str = "f32", extra=None, final: str = "f32", aggregat
     # the library reads only the S blocks a member can lie in when the
     # candidates are few against the row's 128-column blocks (as its plan decides)
     tb = (n + 127) // 128
-    pruned = n <= 512 * 128 and 4 * (kc - 1) <= tb
+    pruned = n <= 512 * 128 and kc <= 128 and 4 * (kc - 1) <= tb
     # FP32 rows already in the padded layout (d a multiple of 64; the benchmark's
     # tensors are 256-byte aligned) are read in place, so no FP32 copy is written
     copy = 0 if (in_b == 4 and ldp == d) else n * ldp * 4

@@ -43,10 +43,22 @@ __global__ __launch_bounds__(256) void topk_pruned_kernel(const T* __restrict__ 
                                                           int ldo) {
   __shared__ uint64_t ring_all[4][128];
   __shared__ int list_all[4][512];
+  __shared__ float bm_all[4][512];  // the four rows' block maxima
   const int w = threadIdx.x >> 6;
-  const int i = blockIdx.x * 4 + w;
-  if (i >= rows) return;  // waves are independent
-  topk_pruned_row<R, T>(S, ldS, N, i, K, bm, ldbm, oidx, oval, ldo, ring_all[w], list_all[w]);
+  // consecutive row groups on one XCD, which then shares the maxima's lines
+  const int i0 = xcd_linear(blockIdx.x, gridDim.x) * 4;
+  // one 16-byte load per column block covers the workgroup's four rows
+  // (ldbm and i0 are multiples of 4; rows past the last are padding, unused)
+  const int TB = (N + 127) / 128;
+  for (int t = threadIdx.x; t < TB; t += 256) {
+    const f32x4 v = *(const f32x4*)(bm + (int64_t)t * ldbm + i0);
+#pragma unroll
+    for (int r = 0; r < 4; r++) bm_all[r][t] = v[r];
+  }
+  __syncthreads();
+  const int i = i0 + w;
+  if (i >= rows) return;  // no block-level barriers after this point
+  topk_pruned_row<R, T>(S, ldS, N, i, K, bm_all[w], oidx, oval, ldo, ring_all[w], list_all[w]);
 }
 
 // Rows the pruned selection left marked (first index -1) are selected again
@@ -78,18 +90,16 @@ static void launch_topk_pruned_t(const T* S, int64_t ldS, int N, int rows, int K
   if (K <= 64) {
     hipLaunchKernelGGL((topk_pruned_kernel<1, T>), grid, block, 0, s, S, ldS, N, rows, K, bm, ldbm, idx, val, ldo);
     hipLaunchKernelGGL((topk_redo_kernel<1, T>), grid_redo, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
-  } else if (K <= 128) {
+  } else {  // K <= 128 (checked by the launcher)
     hipLaunchKernelGGL((topk_pruned_kernel<2, T>), grid, block, 0, s, S, ldS, N, rows, K, bm, ldbm, idx, val, ldo);
     hipLaunchKernelGGL((topk_redo_kernel<2, T>), grid_redo, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
-  } else {
-    hipLaunchKernelGGL((topk_pruned_kernel<4, T>), grid, block, 0, s, S, ldS, N, rows, K, bm, ldbm, idx, val, ldo);
-    hipLaunchKernelGGL((topk_redo_kernel<4, T>), grid_redo, block, 0, s, S, ldS, N, rows, K, idx, val, ldo);
   }
 }
 
 hipError_t launch_topk_pruned(const void* S, bool half, int64_t ldS, int N, int rows, int K, const float* bm,
                               int64_t ldbm, int32_t* idx, float* val, int ldo, hipStream_t s) {
-  if (K < 1 || K > 256 || K > N || N > kPrunedMaxN || (ldS & 3) || !bm || ldbm < rows)
+  if (K < 1 || K > kPrunedMaxK || K > N || N > kPrunedMaxN || (ldS & 3) || !bm || (ldbm & 3) || ldbm < (rows + 3) / 4 * 4 ||
+      ((uintptr_t)bm & 15))
     return hipErrorInvalidValue;
   if (half)
     launch_topk_pruned_t((const _Float16*)S, ldS, N, rows, K, bm, ldbm, idx, val, ldo, s);

@@ -168,8 +168,11 @@ hipError_t launch_topk(const void* S, bool half, int64_t ldS, int N, int rows, i
 // The same lists from S and its block maxima bm (as launch_gemm_sim writes
 // them): only the column blocks whose maximum reaches a lower bound on the
 // row's K-th best value are read. N <= kPrunedMaxN (at most 512 blocks per
-// row).
+// row) and K <= kPrunedMaxK (pruning needs 4 (K - 1) <= blocks <= 512, so
+// larger K never prunes); bm 16-byte aligned with ldbm a multiple of 4 and at
+// least rows rounded up to 4 (four rows' maxima are read as one vector).
 constexpr int kPrunedMaxN = 512 * 128;
+constexpr int kPrunedMaxK = 128;
 hipError_t launch_topk_pruned(const void* S, bool half, int64_t ldS, int N, int rows, int K, const float* bm,
                               int64_t ldbm, int32_t* idx, float* val, int ldo, hipStream_t s);
 

@@ -110,14 +110,14 @@ hipError_t enqueue_knn(const Plan& P, void* ws, const void* x, int in_bf16, hipS
     float* bm = P.o_bm ? at<float>(ws, P.o_bm) : nullptr;
     if (P.prec == SimPrec::F32)
       RR_TRY(launch_gemm_sim(SimPrec::F32, xp, P.n, P.ldp * 4, P.ldp * 4, rn, S, P.ldN, false, sws, sws_bytes, s, bm,
-                             P.n));
+                             P.ldN));
     else
       RR_TRY(launch_gemm_sim(P.prec, xl, P.n, P.ldl * P.lbytes, P.ldl * P.lbytes, sl, S, P.ldN, true, sws, sws_bytes,
-                             s, bm, P.n));
+                             s, bm, P.ldN));
     RR_STAGE(RERANK_STAGE_SIMILARITY, 1);
     RR_STAGE(RERANK_STAGE_TOPK, 0);
     if (bm)
-      RR_TRY(launch_topk_pruned(S, P.prec != SimPrec::F32, P.ldN, P.n, P.n, P.kc, bm, P.n, ci, cv, P.kc, s));
+      RR_TRY(launch_topk_pruned(S, P.prec != SimPrec::F32, P.ldN, P.n, P.n, P.kc, bm, P.ldN, ci, cv, P.kc, s));
     else
       RR_TRY(launch_topk(S, P.prec != SimPrec::F32, P.ldN, P.n, P.n, P.kc, ci, cv, P.kc, s));
     RR_STAGE(RERANK_STAGE_TOPK, 1);

@@ -88,9 +88,9 @@ void make_plan(const rerank_params* p, bool knn_only, Plan* o, bool dense_layers
   // N = 19281: 34 candidates 0.28 -> 0.12 ms, while 42 and 58 ran faster
   // streaming whole rows), hence blocks >= 4 (candidates - 1).
   const int64_t tb = (P.n + 127) / 128;
-  if (!fused && P.n <= kPrunedMaxN && 4 * (int64_t)(P.kc - 1) <= tb) {
+  if (!fused && P.n <= kPrunedMaxN && P.kc <= kPrunedMaxK && 4 * (int64_t)(P.kc - 1) <= tb) {
     P.tb = tb;
-    P.o_bm = take((size_t)P.tb * n * 4);  // block-major, row stride n
+    P.o_bm = take((size_t)P.tb * P.ldN * 4);  // block-major, row stride ldN (16-byte loads of 4 rows)
   }
   P.o_ci = take(n * P.kc * 4);
   P.o_cv = take(n * P.kc * 4);

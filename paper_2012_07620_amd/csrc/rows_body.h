@@ -276,8 +276,9 @@ __device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, i
   }
 }
 
-// a3 with block maxima. bm[b * ldbm + i] holds the largest stored similarity
-// of row i in column block b (128 columns). The row itself ranks first, so
+// a3 with block maxima. bmrow[b] holds the largest stored similarity of row
+// i in column block b (128 columns; the launch stages the four rows of a
+// workgroup in LDS from bm[b * ldbm + i]). The row itself ranks first, so
 // K - 1 other members are needed; blocks are disjoint, so any K - 1 blocks'
 // maxima are K - 1 distinct elements of the row, and the (K - 1)-th largest of
 // any set of non-diagonal block maxima is at or below the value of the row's
@@ -296,9 +297,8 @@ __device__ __forceinline__ void topk_row(const T* __restrict__ S, int64_t ldS, i
 // of this function and would halve its occupancy.
 template <int R, typename T>
 __device__ __forceinline__ void topk_pruned_row(const T* __restrict__ S, int64_t ldS, int N, int i, int K,
-                                                const float* __restrict__ bm, int64_t ldbm,
-                                                int32_t* __restrict__ oidx, float* __restrict__ oval, int ldo,
-                                                uint64_t* ring, int* list) {
+                                                const float* bmrow, int32_t* __restrict__ oidx,
+                                                float* __restrict__ oval, int ldo, uint64_t* ring, int* list) {
   constexpr int NB = 8;  // up to 512 blocks: lane l holds blocks l, l + 64, ...
   constexpr int Q = 4;   // blocks read per step
   constexpr float NEG = -__builtin_inff();
@@ -310,7 +310,7 @@ __device__ __forceinline__ void topk_pruned_row(const T* __restrict__ S, int64_t
 #pragma unroll
   for (int b = 0; b < NB; b++) {
     const int t = b * 64 + lane;
-    bx[b] = t < TB ? bm[(int64_t)t * ldbm + i] : NEG;
+    bx[b] = t < TB ? bmrow[t] : NEG;
   }
   float t0 = NEG;
   if (K == 1) {
