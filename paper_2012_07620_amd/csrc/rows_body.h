@@ -570,7 +570,8 @@ __device__ __forceinline__ void scatter_pair(const int32_t* __restrict__ knn, in
   }
   const int32_t* lj = knn + (int64_t)j * k1;
   bool mut = false;
-  for (int s = 0; s < k1; s++) mut |= (lj[s] == i);
+#pragma unroll 8
+  for (int s = 0; s < k1; s++) mut |= (lj[s] == i);  // eight loads in flight per step
   const float v = mut ? 1.0f : 0.5f;
   H[(int64_t)i * ldH + j] = v;
   H[(int64_t)j * ldH + i] = v;
