@@ -221,3 +221,25 @@ def test_static_array_size_matches_header():
     text = open(HEADER).read()
     m = re.search(r"#define RERANK_STATIC_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
     assert m and int(m.group(1)) << int(m.group(2)) == binding.STATIC_BYTES
+
+
+def test_block_maxima_buffer_follows_the_pruning_rule():
+    """The similarity product records per-row block maxima (row stride padded
+    to 64 columns) only when the selection is pruned: 4 (K - 1) <= blocks and
+    K <= 128. Between K = 38 and K = 39 at N = 19281 (151 blocks) the knn
+    working set drops the maxima and gains one candidate column in each of the
+    two candidate arrays; above K = 128 nothing is pruned even at 512 blocks."""
+    n, d, k1 = 19281, 64, 26
+    ldn, tb = 19328, 151
+
+    def ws(n_, k1_, extra):
+        return binding.knn_workspace_bytes(binding.make_params(n_, 1, d, k1_, 1, 0, extra_cand=extra))
+
+    def up(v):
+        return (v + 255) // 256 * 256
+
+    pruned, streaming = ws(n, k1, 12), ws(n, k1, 13)  # K = 38 and 39
+    assert pruned - streaming == up(tb * ldn * 4) - 2 * (up(n * 39 * 4) - up(n * 38 * 4))
+    # K = 128 prunes at N = 65536 (4 * 127 <= 512 blocks), K = 129 does not
+    big = 65536
+    assert ws(big, 128, 0) - ws(big, 129, 0) == up(512 * big * 4) - 4 * (up(big * 129 * 4) - up(big * 128 * 4))
