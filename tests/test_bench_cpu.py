@@ -106,3 +106,15 @@ def test_committed_traffic_matches_the_current_kernel_sources():
     # a stale summary would make bench.py report traffic as null
     t = bench.measured_traffic("mid_n19281_d2048", "f32", "final")
     assert t is not None and t["bytes"] > 0
+
+
+def test_prep_bytes_charge_the_fp32_copy_only_when_it_is_made():
+    # FP32 rows of a multiple of 64 floats are read in place; any other row
+    # length (or bf16 input) is copied into the zero-padded FP32 layout
+    n = 1000
+    in_place = synth.ProblemSpec("p", 100, n - 100, 128, 10, 0.5)
+    copied = synth.ProblemSpec("p", 100, n - 100, 130, 10, 0.5)
+    bf16_in = synth.ProblemSpec("p", 100, n - 100, 128, 10, 0.5, dtype="bf16")
+    assert bench.stage_work(in_place)["prep"] == ("byte", n * 128 * 4 + 8 * n)
+    assert bench.stage_work(copied)["prep"] == ("byte", n * 130 * 4 + n * 192 * 4 + 8 * n)
+    assert bench.stage_work(bf16_in)["prep"] == ("byte", n * 128 * 2 + n * 128 * 4 + 8 * n)
